@@ -1,0 +1,817 @@
+/*
+ * FP64 CPU oracle of the wall-modeled LBM-LES time step of Kummerlaender,
+ * Bukreev, Shimojima, Ito, Krause, "Large-Scale Simulations of Turbulent
+ * Flows using Lattice Boltzmann Methods on Heterogeneous High Performance
+ * Computers" (arXiv 2506.21804).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg do.  It shares no code, header or table with the HIP path.
+ *
+ * It is deliberately plain: two population lattices (f, f*), one cell at a
+ * time, double precision, collide everything, then pull-stream everything.
+ * No blocking, no fusion, no in-place tricks.  The scalar type is a template
+ * parameter so the same code also runs on forward-mode dual numbers, which
+ * gives exact directional derivatives (the "tangent" oracle of the adjoint).
+ *
+ * What one step computes (n -> n+1), in this order:
+ *   1. wall prepass: for every wall-modeled cell b, friction velocity u_tau
+ *      from the Spalding law (Sec. 2.2.1, Eqs. (15)-(17)) solved by Newton
+ *      in FP64 at a reference cell r, the modeled tangential velocity at b
+ *      and the modeled strain magnitude G;
+ *   2. collision of every fluid cell: the homogenized LB update
+ *      (Sec. 2.2, Eq. (6)) in its BGK form, with the Smagorinsky effective
+ *      relaxation time (Eqs. (3),(4),(14)), the homogenized velocity
+ *      (Eq. (12)), and Guo forcing; wall cells use the wall-model
+ *      reconstruction (sigma = 0, solid velocity = modeled velocity,
+ *      Sec. 2.2.1 last paragraph, non-equilibrium from Eq. (10));
+ *      then the fringe blend / lid of the open-boundary urban setup;
+ *   3. streaming with halfway bounce-back at solid links.
+ *
+ * Readings of the paper where it is silent or garbled (each is also listed
+ * in the design document):
+ *   - lattice units, dx = dt = 1, c_s^2 = 1/3;
+ *   - second-order equilibrium (BGK) for the hot path;
+ *   - f^(1) = f - f^eq(rho, u); f* = f^eq(rho, u_hat) + (1 - 1/tau)(f - f^eq(rho,u));
+ *   - porosity phi in [0,1], 1 = fluid: u_hat = phi*u + (1-phi)*u_B, u_B = 0
+ *     in the bulk (the weights of Eq. (12) read with d := 1 - phi);
+ *   - tau_eff is the positive root of tau^2 - tau0*tau - C_S^2 |Pi| /
+ *     (sqrt(2) rho c_s^4) = 0, i.e. nu_eff = nu0 + C_S^2 |S|, |S| = sqrt(2 S:S),
+ *     with S taken from Pi^neq = -2 rho c_s^2 tau_eff S;
+ *   - Eq. (10) read as f^(1,FD)_i = -(w_i rho tau / c_s^2) H^(2)_i : S;
+ *   - Guo forcing, u = (j + F/2)/rho, source (1 - 1/(2 tau)) w_i
+ *     [3(xi_i - u) + 9 (xi_i.u) xi_i].F;
+ *   - smooth-wall Spalding constants kappa, E are parameters (0.41, 9.0);
+ *   - wall cells: fluid cells with at least one solid link; normal from the
+ *     sum of the solid links; reference cell one lattice step along the
+ *     direction best aligned with the normal; stress-consistent strain
+ *     G = 2 u_tau^2 / (nu + sqrt(nu^2 + 4 C_S^2 u_tau^2)).
+ */
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+extern "C" {
+/* The oracle's own parameter block (plain C layout for ctypes). */
+typedef struct {
+  int q, nx, ny, nz;
+  int periodic[3];
+  double tau0, cs_smag;
+  double force[3];
+  int wall_model;
+  double kappa, E;
+  int fringe_len;
+  double u_ref, z0;
+  int lid;
+} orc_params;
+}
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENONFINITE = -3, ORC_ENEWTON = -4 };
+
+namespace {
+
+/* ------------------------------------------------------------------------ */
+/* Forward-mode dual number: value and one directional derivative.           */
+/* ------------------------------------------------------------------------ */
+struct Dual {
+  double v, d;
+  Dual(double v_ = 0.0, double d_ = 0.0) : v(v_), d(d_) {}
+  Dual& operator+=(const Dual& b) { v += b.v; d += b.d; return *this; }
+  Dual& operator-=(const Dual& b) { v -= b.v; d -= b.d; return *this; }
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) {
+  return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v));
+}
+/* d sqrt(x) = dx / (2 sqrt(x)); at x = 0 the derivative is taken as 0 (the
+ * subgradient convention for the Frobenius norm of a vanishing stress). */
+inline Dual sqrt(Dual a) {
+  double s = std::sqrt(a.v);
+  return Dual(s, s > 0.0 ? a.d / (2.0 * s) : 0.0);
+}
+inline double val(double x) { return x; }
+inline double val(const Dual& x) { return x.v; }
+inline double der(double) { return 0.0; }
+inline double der(const Dual& x) { return x.d; }
+using std::sqrt;
+
+/* ------------------------------------------------------------------------ */
+/* Velocity sets.  D3Q19 is the stencil of the paper (Sec. 2.2, Fig. of the  */
+/* lattice); D3Q27 adds the eight corner directions.  Ordering: rest, the    */
+/* nine "positive" directions, (D3Q27: four corners with +x), then all       */
+/* negatives in the same order.                                              */
+/* ------------------------------------------------------------------------ */
+struct VelSet {
+  int q = 0;
+  int c[27][3];
+  double w[27];
+  int opp[27];
+};
+
+VelSet make_velocity_set(int q) {
+  VelSet v;
+  v.q = q;
+  static const int pos9[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0},
+                                 {1, 0, 1}, {1, 0, -1}, {0, 1, 1}, {0, 1, -1}};
+  static const int corner4[4][3] = {{1, 1, 1}, {1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
+  int npos = (q == 19) ? 9 : 13;
+  for (int a = 0; a < 3; ++a) v.c[0][a] = 0;
+  for (int k = 0; k < npos; ++k) {
+    const int* e = (k < 9) ? pos9[k] : corner4[k - 9];
+    for (int a = 0; a < 3; ++a) {
+      v.c[1 + k][a] = e[a];
+      v.c[1 + npos + k][a] = -e[a];
+    }
+  }
+  for (int i = 0; i < q; ++i) {
+    int n2 = v.c[i][0] * v.c[i][0] + v.c[i][1] * v.c[i][1] + v.c[i][2] * v.c[i][2];
+    if (q == 19) {
+      v.w[i] = (n2 == 0) ? 1.0 / 3.0 : (n2 == 1) ? 1.0 / 18.0 : 1.0 / 36.0;
+    } else {
+      v.w[i] = (n2 == 0) ? 8.0 / 27.0 : (n2 == 1) ? 2.0 / 27.0 : (n2 == 2) ? 1.0 / 54.0 : 1.0 / 216.0;
+    }
+    for (int j = 0; j < q; ++j)
+      if (v.c[j][0] == -v.c[i][0] && v.c[j][1] == -v.c[i][1] && v.c[j][2] == -v.c[i][2]) v.opp[i] = j;
+  }
+  return v;
+}
+
+/* Second-order equilibrium: w_i rho [1 + 3 xi.v + 9/2 (xi.v)^2 - 3/2 v.v]
+ * (the Hermite equilibrium of Sec. 2.2 truncated after H^(2), c_s^2 = 1/3). */
+template <class T>
+void equilibrium(const VelSet& vs, const T& rho, const T v[3], T* feq) {
+  T vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  for (int i = 0; i < vs.q; ++i) {
+    T cv = double(vs.c[i][0]) * v[0] + double(vs.c[i][1]) * v[1] + double(vs.c[i][2]) * v[2];
+    feq[i] = vs.w[i] * rho * (1.0 + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
+  }
+}
+
+/* Guo source term for population i: w_i [3(xi_i - v) + 9 (xi_i.v) xi_i].F. */
+template <class T>
+T guo_term(const VelSet& vs, int i, const T v[3], const double F[3]) {
+  T cv = double(vs.c[i][0]) * v[0] + double(vs.c[i][1]) * v[1] + double(vs.c[i][2]) * v[2];
+  double cF = vs.c[i][0] * F[0] + vs.c[i][1] * F[1] + vs.c[i][2] * F[2];
+  T vF = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
+  return vs.w[i] * (3.0 * (T(cF) - vF) + 9.0 * cv * cF);
+}
+
+/* Effective relaxation time of the Smagorinsky BGK model (Eqs. (3),(4),(14)):
+ * the positive root of tau^2 - tau0 tau - 9 C_S^2 |Pi| / (sqrt(2) rho) = 0. */
+template <class T>
+T tau_effective(double tau0, double cs, const T& pinorm, const T& rho) {
+  return 0.5 * (tau0 + sqrt(tau0 * tau0 + 18.0 * std::sqrt(2.0) * cs * cs * pinorm / rho));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spalding wall function (Sec. 2.2.1, Eq. (17)), smooth wall.               */
+/* ------------------------------------------------------------------------ */
+double spalding_g(double up, double kappa, double E) {
+  double k = kappa * up;
+  return up + (std::exp(k) - 1.0 - k - 0.5 * k * k - k * k * k / 6.0) / E;
+}
+double spalding_dg(double up, double kappa, double E) {
+  double k = kappa * up;
+  return 1.0 + kappa * (std::exp(k) - 1.0 - k - 0.5 * k * k) / E;
+}
+
+/* Friction velocity from the law at distance y with tangential speed U:
+ * root of F(ut) = g(U/ut) - y ut / nu.  F is convex and decreasing and the
+ * laminar guess sqrt(nu U / y) has F >= 0, so Newton climbs monotonically. */
+int solve_utau(double U, double y, double nu, double kappa, double E, double* utau, int* iters) {
+  double ut = std::sqrt(nu * U / y);
+  if (!(kappa * U / ut <= 700.0)) return ORC_ENEWTON;
+  for (int it = 1; it <= 100; ++it) {
+    double x = U / ut;
+    double Fv = spalding_g(x, kappa, E) - y * ut / nu;
+    double dF = -spalding_dg(x, kappa, E) * U / (ut * ut) - y / nu;
+    double step = -Fv / dF;
+    ut += step;
+    if (std::fabs(step) <= 1e-15 * ut) {
+      *utau = ut;
+      if (iters) *iters = it;
+      return ORC_OK;
+    }
+  }
+  return ORC_ENEWTON;
+}
+
+/* An upper bound of the root of g(u+) = y+: the root is below y+ (g(u) >= u),
+ * so exp(kappa u+) = E(y+ - u+) + 1 + k + k^2/2 + k^3/6 with k = kappa u+
+ * is at most E y+ + 1 + K + K^2/2 + K^3/6 with K = kappa y+. */
+double uplus_upper_bound(double yplus, double kappa, double E) {
+  double K = kappa * yplus;
+  double b = std::log(E * yplus + 1.0 + K + 0.5 * K * K + K * K * K / 6.0) / kappa;
+  return std::fmin(yplus, b);
+}
+
+/* Inverse of the law: u+ with g(u+) = y+, Newton from a start right of the
+ * root (g is convex and increasing there, so the iterates decrease). */
+int solve_uplus(double yplus, double start, double kappa, double E, double* uplus) {
+  double u = start;
+  if (!(kappa * u <= 700.0)) return ORC_ENEWTON;
+  for (int it = 1; it <= 100; ++it) {
+    double step = -(spalding_g(u, kappa, E) - yplus) / spalding_dg(u, kappa, E);
+    u += step;
+    if (std::fabs(step) <= 1e-15 * std::fabs(u)) {
+      *uplus = u;
+      return ORC_OK;
+    }
+  }
+  return ORC_ENEWTON;
+}
+
+enum Kind : uint8_t { K_SOLID = 0, K_BULK = 1, K_WALL = 2, K_LID = 3 };
+
+/* ------------------------------------------------------------------------ */
+/* The simulation state.                                                     */
+/* ------------------------------------------------------------------------ */
+struct SimBase {
+  virtual ~SimBase() {}
+  std::string err;
+  virtual int step(int n) = 0;
+  virtual int moments(double* rho, double* u) = 0;
+  virtual int diagnostics(double* out) = 0;
+  virtual int get_populations(double* f, double* df) = 0;
+  virtual int set_populations(const double* f, const double* df) = 0;
+  virtual int set_phi_tangent(const double* dphi) = 0;
+  virtual int objective(const int planes[2], double* J, double* dJ) = 0;
+  virtual int wall_info(long* cells, long* refs, double* normal, double* utau, double* G, double* tau) = 0;
+  virtual long num_wall() const = 0;
+  virtual int get_post_collision(double* f) = 0;
+};
+
+template <class T>
+struct Sim : SimBase {
+  orc_params p;
+  VelSet vs;
+  long N = 0;
+  std::vector<uint8_t> fluid, kind;
+  std::vector<T> phi;
+  std::vector<T> f, fs; /* [q][N]: state f^n and post-collision f* */
+  /* wall-model geometry (fixed at creation) */
+  std::vector<long> wcell, wref;
+  std::vector<double> wnorm, wyb, wyr;
+  std::vector<long> wall_index; /* cell -> wall record, -1 if none */
+  /* wall-model records of the current step (FP64) */
+  std::vector<double> wt, wutan, wG, wtau, wutau;
+
+  long idx(int x, int y, int z) const { return x + (long)p.nx * (y + (long)p.ny * z); }
+  void coords(long c, int& x, int& y, int& z) const {
+    x = int(c % p.nx);
+    y = int((c / p.nx) % p.ny);
+    z = int(c / ((long)p.nx * p.ny));
+  }
+  /* Cell at (x,y,z) + (dx,dy,dz) with periodic wrap; -1 if outside a non-periodic axis. */
+  long neighbor_xyz(int x, int y, int z, int dx, int dy, int dz) const {
+    int q[3] = {x + dx, y + dy, z + dz};
+    const int n[3] = {p.nx, p.ny, p.nz};
+    for (int a = 0; a < 3; ++a) {
+      if (q[a] < 0 || q[a] >= n[a]) {
+        if (!p.periodic[a]) return -1;
+        q[a] = (q[a] % n[a] + n[a]) % n[a];
+      }
+    }
+    return idx(q[0], q[1], q[2]);
+  }
+  long neighbor(long c, int dx, int dy, int dz) const {
+    int x, y, z;
+    coords(c, x, y, z);
+    return neighbor_xyz(x, y, z, dx, dy, dz);
+  }
+  bool is_fluid(long c) const { return c >= 0 && fluid[c]; }
+
+  /* Log-law inflow profile of the urban setup: u_ref ln(1+z_c/z0)/ln(1+z_top/z0). */
+  double u_in(double zc) const {
+    double ztop = p.nz - 0.5;
+    return p.u_ref * std::log(1.0 + zc / p.z0) / std::log(1.0 + ztop / p.z0);
+  }
+
+  int init(const orc_params* prm, const uint8_t* mask, const double* wall_dist, const double* porosity,
+           const double* rho0, const double* u0) {
+    p = *prm;
+    if (!(p.q == 19 || p.q == 27) || p.nx <= 0 || p.ny <= 0 || p.nz <= 0) {
+      err = "invalid lattice or size";
+      return ORC_EINVAL;
+    }
+    if (!(p.tau0 > 0.5) || !(p.cs_smag >= 0.0)) {
+      err = "tau0 must exceed 1/2 and C_S must be >= 0";
+      return ORC_EINVAL;
+    }
+    vs = make_velocity_set(p.q);
+    N = (long)p.nx * p.ny * p.nz;
+    fluid.assign(N, 1);
+    if (mask)
+      for (long c = 0; c < N; ++c) fluid[c] = mask[c] ? 1 : 0;
+    phi.assign(N, T(1.0));
+    if (porosity)
+      for (long c = 0; c < N; ++c) phi[c] = T(porosity[c]);
+    /* classify cells */
+    kind.assign(N, K_SOLID);
+    for (long c = 0; c < N; ++c) {
+      if (!fluid[c]) continue;
+      int x, y, z;
+      coords(c, x, y, z);
+      kind[c] = (p.lid && z == p.nz - 1) ? K_LID : K_BULK;
+    }
+    wall_index.assign(N, -1);
+    if (p.wall_model) {
+      if (!wall_dist) {
+        err = "wall model needs a wall-distance field";
+        return ORC_EINVAL;
+      }
+      for (long b = 0; b < N; ++b) {
+        if (kind[b] != K_BULK) continue;
+        int s[3] = {0, 0, 0};
+        bool any = false;
+        for (int i = 1; i < vs.q; ++i) {
+          long nb = neighbor(b, vs.c[i][0], vs.c[i][1], vs.c[i][2]);
+          if (!is_fluid(nb)) {
+            any = true;
+            for (int a = 0; a < 3; ++a) s[a] -= vs.c[i][a];
+          }
+        }
+        if (!any || (s[0] == 0 && s[1] == 0 && s[2] == 0)) continue; /* bulk (plain bounce-back) */
+        /* reference direction: argmax (xi.s)/|xi|, exact integer comparison,
+         * ties to the lowest index */
+        int best = -1;
+        long bdot = 0, bn2 = 1;
+        for (int i = 1; i < vs.q; ++i) {
+          long d = vs.c[i][0] * s[0] + vs.c[i][1] * s[1] + vs.c[i][2] * s[2];
+          long n2 = vs.c[i][0] * vs.c[i][0] + vs.c[i][1] * vs.c[i][1] + vs.c[i][2] * vs.c[i][2];
+          bool better;
+          if (best < 0) better = true;
+          else if ((d > 0) != (bdot > 0) || (d == 0) != (bdot == 0)) better = (d > bdot);
+          else if (d > 0) better = d * d * bn2 > bdot * bdot * n2;
+          else better = d * d * bn2 < bdot * bdot * n2; /* both <= 0 */
+          if (better) { best = i; bdot = d; bn2 = n2; }
+        }
+        long r = neighbor(b, vs.c[best][0], vs.c[best][1], vs.c[best][2]);
+        if (!is_fluid(r)) r = b;
+        double yb = wall_dist[b], yr = wall_dist[r];
+        if (!(yb > 0.0 && std::isfinite(yb) && yr > 0.0 && std::isfinite(yr))) {
+          err = "wall distance must be positive and finite at wall cells and their references";
+          return ORC_EINVAL;
+        }
+        double sn = std::sqrt(double(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
+        wall_index[b] = (long)wcell.size();
+        wcell.push_back(b);
+        wref.push_back(r);
+        for (int a = 0; a < 3; ++a) wnorm.push_back(s[a] / sn);
+        wyb.push_back(yb);
+        wyr.push_back(yr);
+        kind[b] = K_WALL;
+      }
+    }
+    long nw = (long)wcell.size();
+    wt.assign(3 * nw, 0.0);
+    wutan.assign(nw, 0.0);
+    wG.assign(nw, 0.0);
+    wtau.assign(nw, p.tau0);
+    wutau.assign(nw, 0.0);
+    /* initial populations: equilibrium of the initial density and velocity */
+    f.assign((size_t)vs.q * N, T(0.0));
+    fs.assign((size_t)vs.q * N, T(0.0));
+    for (long c = 0; c < N; ++c) {
+      if (!fluid[c]) continue;
+      T r = rho0 ? T(rho0[c]) : T(1.0);
+      T v[3];
+      for (int a = 0; a < 3; ++a) v[a] = u0 ? T(u0[(size_t)a * N + c]) : T(0.0);
+      T feq[27];
+      equilibrium(vs, r, v, feq);
+      for (int i = 0; i < vs.q; ++i) f[(size_t)i * N + c] = feq[i];
+    }
+    return ORC_OK;
+  }
+
+  void local_moments(long c, T& rho, T j[3]) const {
+    rho = T(0.0);
+    j[0] = j[1] = j[2] = T(0.0);
+    for (int i = 0; i < vs.q; ++i) {
+      T fi = f[(size_t)i * N + c];
+      rho += fi;
+      for (int a = 0; a < 3; ++a) j[a] += double(vs.c[i][a]) * fi;
+    }
+  }
+
+  /* Wall prepass: u_tau, modeled tangential speed and strain from f^n. */
+  int wall_prepass() {
+    const double nu = (p.tau0 - 0.5) / 3.0;
+    int status = ORC_OK;
+    long nw = (long)wcell.size();
+    for (long k = 0; k < nw; ++k) {
+      long r = wref[k];
+      T rho;
+      T j[3];
+      local_moments(r, rho, j);
+      double u[3];
+      for (int a = 0; a < 3; ++a) u[a] = (val(j[a]) + 0.5 * p.force[a]) / val(rho);
+      const double* n = &wnorm[3 * k];
+      double un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+      double ut[3] = {u[0] - un * n[0], u[1] - un * n[1], u[2] - un * n[2]};
+      double U = std::sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+      if (!(U > 1e-300)) {
+        wt[3 * k] = wt[3 * k + 1] = wt[3 * k + 2] = 0.0;
+        wutan[k] = 0.0;
+        wG[k] = 0.0;
+        wutau[k] = 0.0;
+        wtau[k] = 3.0 * nu + 0.5;
+        continue;
+      }
+      double utau = 0.0;
+      int rc = solve_utau(U, wyr[k], nu, p.kappa, p.E, &utau, nullptr);
+      if (rc != ORC_OK) { status = rc; continue; }
+      double uplus_b;
+      if (r == wcell[k]) {
+        uplus_b = U / utau;
+      } else {
+        double yplus_b = wyb[k] * utau / nu;
+        double start = uplus_upper_bound(yplus_b, p.kappa, p.E);
+        if (wyr[k] >= wyb[k]) start = std::fmin(start, U / utau);
+        rc = solve_uplus(yplus_b, start, p.kappa, p.E, &uplus_b);
+        if (rc != ORC_OK) { status = rc; continue; }
+      }
+      for (int a = 0; a < 3; ++a) wt[3 * k + a] = ut[a] / U;
+      wutan[k] = utau * uplus_b;
+      double cs2 = p.cs_smag * p.cs_smag;
+      double G = 2.0 * utau * utau / (nu + std::sqrt(nu * nu + 4.0 * cs2 * utau * utau));
+      wG[k] = G;
+      wutau[k] = utau;
+      wtau[k] = 3.0 * (nu + cs2 * G) + 0.5;
+    }
+    if (status != ORC_OK) err = "wall-function Newton solve failed (no convergence or exp range)";
+    return status;
+  }
+
+  /* Bulk cell (sigma = 1): homogenized BGK-Smagorinsky with Guo forcing. */
+  bool collide_bulk(long c, T* fo) const {
+    T fi[27];
+    T rho(0.0), j[3] = {T(0.0), T(0.0), T(0.0)};
+    for (int i = 0; i < vs.q; ++i) {
+      fi[i] = f[(size_t)i * N + c];
+      rho += fi[i];
+      for (int a = 0; a < 3; ++a) j[a] += double(vs.c[i][a]) * fi[i];
+    }
+    T u[3];
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * p.force[a]) / rho;
+    T feq[27];
+    equilibrium(vs, rho, u, feq);
+    T Pi[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) Pi[a][b] = T(0.0);
+    for (int i = 0; i < vs.q; ++i) {
+      T fneq = fi[i] - feq[i];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Pi[a][b] += double(vs.c[i][a] * vs.c[i][b]) * fneq;
+    }
+    T pi2(0.0);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) pi2 += Pi[a][b] * Pi[a][b];
+    T tau = tau_effective(p.tau0, p.cs_smag, sqrt(pi2), rho);
+    T uh[3];
+    for (int a = 0; a < 3; ++a) uh[a] = phi[c] * u[a];
+    T feqh[27];
+    equilibrium(vs, rho, uh, feqh);
+    for (int i = 0; i < vs.q; ++i)
+      fo[i] = feqh[i] + (1.0 - 1.0 / tau) * (fi[i] - feq[i]) +
+              (1.0 - 0.5 / tau) * guo_term(vs, i, u, p.force);
+    return std::isfinite(val(rho)) && val(rho) > 0.0;
+  }
+
+  /* Wall cell (sigma = 0): equilibrium at the modeled velocity plus the
+   * non-equilibrium built from the wall-law strain S = (G/2)(t n^T + n t^T). */
+  bool collide_wall(long c, long k, T* fo) const {
+    T rho(0.0), j[3] = {T(0.0), T(0.0), T(0.0)};
+    for (int i = 0; i < vs.q; ++i) {
+      T fi = f[(size_t)i * N + c];
+      rho += fi;
+      for (int a = 0; a < 3; ++a) j[a] += double(vs.c[i][a]) * fi;
+    }
+    const double* n = &wnorm[3 * k];
+    const double* t = &wt[3 * k];
+    T u[3];
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * p.force[a]) / rho;
+    T un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+    T uw[3];
+    for (int a = 0; a < 3; ++a) uw[a] = wutan[k] * t[a] + un * n[a];
+    double tau = wtau[k], G = wG[k];
+    T feq[27];
+    equilibrium(vs, rho, uw, feq);
+    for (int i = 0; i < vs.q; ++i) {
+      double ct = vs.c[i][0] * t[0] + vs.c[i][1] * t[1] + vs.c[i][2] * t[2];
+      double cn = vs.c[i][0] * n[0] + vs.c[i][1] * n[1] + vs.c[i][2] * n[2];
+      T ffd = -3.0 * vs.w[i] * rho * tau * G * ct * cn;
+      fo[i] = feq[i] + (1.0 - 1.0 / tau) * ffd + (1.0 - 0.5 / tau) * guo_term(vs, i, uw, p.force);
+    }
+    return std::isfinite(val(rho)) && val(rho) > 0.0;
+  }
+
+  int step_once() {
+    if (p.wall_model && !wcell.empty()) {
+      int rc = wall_prepass();
+      if (rc != ORC_OK) return rc;
+    }
+    int bad = 0;
+    const int fstart = p.nx - p.fringe_len;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int z = 0; z < p.nz; ++z)
+      for (int y = 0; y < p.ny; ++y)
+        for (int x = 0; x < p.nx; ++x) {
+          long c = idx(x, y, z);
+          if (!fluid[c]) continue;
+          T fo[27];
+          if (kind[c] == K_LID) {
+            T v[3] = {T(u_in(p.nz - 0.5)), T(0.0), T(0.0)};
+            equilibrium(vs, T(1.0), v, fo);
+          } else if (kind[c] == K_WALL) {
+            if (!collide_wall(c, wall_index[c], fo)) bad = 1;
+          } else {
+            if (!collide_bulk(c, fo)) bad = 1;
+          }
+          if (p.fringe_len > 0 && x >= fstart) {
+            double s = double(x - fstart + 1) / p.fringe_len;
+            double lam = s * s * (3.0 - 2.0 * s);
+            T v[3] = {T(u_in(z + 0.5)), T(0.0), T(0.0)};
+            T fin[27];
+            equilibrium(vs, T(1.0), v, fin);
+            for (int i = 0; i < vs.q; ++i) fo[i] = (1.0 - lam) * fo[i] + lam * fin[i];
+          }
+          for (int i = 0; i < vs.q; ++i) fs[(size_t)i * N + c] = fo[i];
+        }
+    /* pull streaming with halfway bounce-back */
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < p.nz; ++z)
+      for (int y = 0; y < p.ny; ++y)
+        for (int x = 0; x < p.nx; ++x) {
+          long c = idx(x, y, z);
+          if (!fluid[c]) continue;
+          for (int i = 0; i < vs.q; ++i) {
+            long src = neighbor_xyz(x, y, z, -vs.c[i][0], -vs.c[i][1], -vs.c[i][2]);
+            f[(size_t)i * N + c] = is_fluid(src) ? fs[(size_t)i * N + src] : fs[(size_t)vs.opp[i] * N + c];
+          }
+        }
+    if (bad) {
+      err = "non-finite or non-positive density";
+      return ORC_ENONFINITE;
+    }
+    return ORC_OK;
+  }
+
+  int step(int n) override {
+    for (int s = 0; s < n; ++s) {
+      int rc = step_once();
+      if (rc != ORC_OK) return rc;
+    }
+    return ORC_OK;
+  }
+
+  int moments(double* rho, double* u) override {
+    for (long c = 0; c < N; ++c) {
+      if (!fluid[c]) {
+        if (rho) rho[c] = 0.0;
+        if (u) u[c] = u[N + c] = u[2 * N + c] = 0.0;
+        continue;
+      }
+      T r, j[3];
+      local_moments(c, r, j);
+      if (rho) rho[c] = val(r);
+      if (u)
+        for (int a = 0; a < 3; ++a) u[(size_t)a * N + c] = val((j[a] + 0.5 * p.force[a]) / r);
+    }
+    return ORC_OK;
+  }
+
+  int diagnostics(double* out) override {
+    double M = 0, P[3] = {0, 0, 0};
+    for (long c = 0; c < N; ++c) {
+      if (!fluid[c]) continue;
+      T r, j[3];
+      local_moments(c, r, j);
+      M += val(r);
+      for (int a = 0; a < 3; ++a) P[a] += val(j[a]);
+    }
+    out[0] = M;
+    out[1] = P[0];
+    out[2] = P[1];
+    out[3] = P[2];
+    return ORC_OK;
+  }
+
+  int get_populations(double* fo, double* dfo) override {
+    for (size_t k = 0; k < f.size(); ++k) {
+      if (fo) fo[k] = val(f[k]);
+      if (dfo) dfo[k] = der(f[k]);
+    }
+    return ORC_OK;
+  }
+
+  int set_populations(const double* fi, const double* dfi) override;
+  int set_phi_tangent(const double* dphi) override;
+
+  /* Terminal objective of the porosity-gradient study: pressure drop between
+   * two x-planes plus mean kinetic energy (both over fluid cells). */
+  int objective(const int planes[2], double* J, double* dJ) override {
+    T s0(0.0), s1(0.0), ke(0.0);
+    long n0 = 0, n1 = 0, nf = 0;
+    for (long c = 0; c < N; ++c) {
+      if (!fluid[c]) continue;
+      int x, y, z;
+      coords(c, x, y, z);
+      T r, j[3];
+      local_moments(c, r, j);
+      T m[3];
+      for (int a = 0; a < 3; ++a) m[a] = j[a] + 0.5 * p.force[a];
+      ke += 0.5 * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / r;
+      ++nf;
+      if (x == planes[0]) { s0 += r; ++n0; }
+      if (x == planes[1]) { s1 += r; ++n1; }
+    }
+    if (n0 == 0 || n1 == 0 || nf == 0) {
+      err = "objective planes hold no fluid cell";
+      return ORC_EINVAL;
+    }
+    T Jv = (1.0 / 3.0) * (s0 / double(n0) - s1 / double(n1)) + ke / double(nf);
+    if (J) *J = val(Jv);
+    if (dJ) *dJ = der(Jv);
+    return ORC_OK;
+  }
+
+  long num_wall() const override { return (long)wcell.size(); }
+  /* post-collision populations f* of the last step, [q][N] */
+  int get_post_collision(double* fo) override {
+    for (size_t k = 0; k < fs.size(); ++k) fo[k] = val(fs[k]);
+    return ORC_OK;
+  }
+  int wall_info(long* cells, long* refs, double* normal, double* utau, double* G, double* tau) override {
+    long nw = (long)wcell.size();
+    for (long k = 0; k < nw; ++k) {
+      if (cells) cells[k] = wcell[k];
+      if (refs) refs[k] = wref[k];
+      if (normal)
+        for (int a = 0; a < 3; ++a) normal[3 * k + a] = wnorm[3 * k + a];
+      if (utau) utau[k] = wutau[k];
+      if (G) G[k] = wG[k];
+      if (tau) tau[k] = wtau[k];
+    }
+    return ORC_OK;
+  }
+};
+
+template <>
+int Sim<double>::set_populations(const double* fi, const double*) {
+  for (size_t k = 0; k < f.size(); ++k) f[k] = fi[k];
+  return ORC_OK;
+}
+template <>
+int Sim<Dual>::set_populations(const double* fi, const double* dfi) {
+  for (size_t k = 0; k < f.size(); ++k) f[k] = Dual(fi[k], dfi ? dfi[k] : 0.0);
+  return ORC_OK;
+}
+template <>
+int Sim<double>::set_phi_tangent(const double*) {
+  err = "tangent seeds need a dual-number oracle";
+  return ORC_EINVAL;
+}
+template <>
+int Sim<Dual>::set_phi_tangent(const double* dphi) {
+  for (long c = 0; c < N; ++c) phi[c].d = dphi ? dphi[c] : 0.0;
+  return ORC_OK;
+}
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+extern "C" {
+
+/* Creates a simulation.  tangent = 0: plain FP64; tangent = 1: dual numbers
+ * (wall model not supported in tangent mode). */
+void* orc_create(const orc_params* p, const uint8_t* mask, const double* wall_dist, const double* porosity,
+                 const double* rho0, const double* u0, int tangent) {
+  g_create_error.clear();
+  if (!p) {
+    g_create_error = "null parameters";
+    return nullptr;
+  }
+  if (tangent && p->wall_model) {
+    g_create_error = "tangent mode does not differentiate the wall model";
+    return nullptr;
+  }
+  SimBase* s;
+  int rc;
+  if (tangent) {
+    auto* t = new Sim<Dual>();
+    rc = t->init(p, mask, wall_dist, porosity, rho0, u0);
+    s = t;
+  } else {
+    auto* t = new Sim<double>();
+    rc = t->init(p, mask, wall_dist, porosity, rho0, u0);
+    s = t;
+  }
+  if (rc != ORC_OK) {
+    g_create_error = s->err;
+    delete s;
+    return nullptr;
+  }
+  return s;
+}
+const char* orc_create_error(void) { return g_create_error.c_str(); }
+const char* orc_last_error(void* h) { return h ? static_cast<SimBase*>(h)->err.c_str() : "null handle"; }
+void orc_free(void* h) { delete static_cast<SimBase*>(h); }
+int orc_step(void* h, int n) { return static_cast<SimBase*>(h)->step(n); }
+int orc_moments(void* h, double* rho, double* u) { return static_cast<SimBase*>(h)->moments(rho, u); }
+int orc_diagnostics(void* h, double* out) { return static_cast<SimBase*>(h)->diagnostics(out); }
+int orc_get_populations(void* h, double* f, double* df) {
+  return static_cast<SimBase*>(h)->get_populations(f, df);
+}
+int orc_set_populations(void* h, const double* f, const double* df) {
+  return static_cast<SimBase*>(h)->set_populations(f, df);
+}
+int orc_set_phi_tangent(void* h, const double* dphi) { return static_cast<SimBase*>(h)->set_phi_tangent(dphi); }
+int orc_objective(void* h, const int* planes, double* J, double* dJ) {
+  return static_cast<SimBase*>(h)->objective(planes, J, dJ);
+}
+int orc_get_post_collision(void* h, double* f) { return static_cast<SimBase*>(h)->get_post_collision(f); }
+long orc_num_wall(void* h) { return static_cast<SimBase*>(h)->num_wall(); }
+int orc_wall_info(void* h, long* cells, long* refs, double* normal, double* utau, double* G, double* tau) {
+  return static_cast<SimBase*>(h)->wall_info(cells, refs, normal, utau, G, tau);
+}
+
+/* Pure helpers exposed for the pin tests. */
+int orc_velocity_set(int q, int* c, double* w, int* opp) {
+  if (q != 19 && q != 27) return ORC_EINVAL;
+  VelSet v = make_velocity_set(q);
+  for (int i = 0; i < q; ++i) {
+    for (int a = 0; a < 3; ++a) c[3 * i + a] = v.c[i][a];
+    w[i] = v.w[i];
+    opp[i] = v.opp[i];
+  }
+  return ORC_OK;
+}
+void orc_equilibrium(int q, double rho, const double* u, double* feq) {
+  VelSet v = make_velocity_set(q);
+  double uu[3] = {u[0], u[1], u[2]};
+  equilibrium(v, rho, uu, feq);
+}
+double orc_tau_eff(double tau0, double cs, double pinorm, double rho) {
+  return tau_effective(tau0, cs, pinorm, rho);
+}
+/* One bulk-cell collision of populations fin (FP64), porosity phi. */
+void orc_collide_bulk(int q, double tau0, double cs, const double* force, double phi, const double* fin,
+                      double* fout) {
+  Sim<double> s;
+  s.p = orc_params{};
+  s.p.q = q;
+  s.p.tau0 = tau0;
+  s.p.cs_smag = cs;
+  for (int a = 0; a < 3; ++a) s.p.force[a] = force[a];
+  s.vs = make_velocity_set(q);
+  s.N = 1;
+  s.f.assign(fin, fin + q);
+  s.phi.assign(1, phi);
+  s.collide_bulk(0, fout);
+}
+/* One wall-cell reconstruction collision for given wall records. */
+void orc_collide_wall(int q, double tau0, double cs, const double* force, const double* fin, const double* normal,
+                      const double* tangent, double utan, double G, double tau, double* fout) {
+  Sim<double> s;
+  s.p = orc_params{};
+  s.p.q = q;
+  s.p.tau0 = tau0;
+  s.p.cs_smag = cs;
+  for (int a = 0; a < 3; ++a) s.p.force[a] = force[a];
+  s.vs = make_velocity_set(q);
+  s.N = 1;
+  s.f.assign(fin, fin + q);
+  s.wnorm.assign(normal, normal + 3);
+  s.wt.assign(tangent, tangent + 3);
+  s.wutan.assign(1, utan);
+  s.wG.assign(1, G);
+  s.wtau.assign(1, tau);
+  s.collide_wall(0, 0, fout);
+}
+double orc_spalding_yplus(double uplus, double kappa, double E) { return spalding_g(uplus, kappa, E); }
+int orc_spalding_uplus(double yplus, double kappa, double E, double* uplus) {
+  return solve_uplus(yplus, uplus_upper_bound(yplus, kappa, E), kappa, E, uplus);
+}
+int orc_solve_utau(double U, double y, double nu, double kappa, double E, double* utau, int* iters) {
+  return solve_utau(U, y, nu, kappa, E, utau, iters);
+}
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+}  /* extern "C" */
