@@ -1,0 +1,182 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) wall-modeled LBM-LES library.
+ *
+ * The library advances the homogenized lattice Boltzmann update of
+ * Kummerlaender et al., arXiv 2506.21804, Sec. 2.2, Eq. (6), in its BGK form
+ * with the Smagorinsky effective relaxation time (Sec. 2.1, Eqs. (3)-(5);
+ * Sec. 2.2, Eq. (14)), the homogenized velocity of Eq. (12) and Guo body
+ * forcing, on a D3Q19 (the paper's stencil, Sec. 2.2) or D3Q27 lattice,
+ * with halfway bounce-back on a voxel geometry and the Spalding wall model
+ * of Sec. 2.2.1 (Eqs. (15)-(17); sigma = 0 and the modeled velocity as the
+ * solid velocity in wall cells).  Populations live in one in-place buffer
+ * (AA pattern) in structure-of-arrays order as deviations from the rest
+ * weights, g_i = f_i - w_i, stored in FP64, FP32 or IEEE binary16.
+ *
+ * Conventions shared by every entry point:
+ *  - cell index c = x + nx*(y + ny*z); N = nx*ny*nz, 1 <= N < 2^31;
+ *  - scalar fields are [N], vector fields [3][N] (component-major),
+ *    population fields [q][N];
+ *  - "compute type" is double for LBM_F64 storage and float otherwise;
+ *  - device pointers are HIP device memory owned by the caller; the library
+ *    never allocates or frees device memory, and keeps no pointer to host
+ *    inputs after a call returns;
+ *  - all device work is enqueued on params.stream (NULL = the null stream);
+ *    calls marked "async" return before the work finishes;
+ *  - every function returns LBM_OK or a negative code and stores a message
+ *    readable with lbm_last_error(); a failed argument check has no side
+ *    effects.  Faults detected inside kernels (a non-finite density, a
+ *    wall-function Newton failure) are reported by the next synchronising
+ *    call (lbm_sync, lbm_diagnostics, lbm_objective, lbm_gradient).
+ *  - a context is not thread-safe; use one per host thread.
+ */
+#ifndef LBM_MI355X_H
+#define LBM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* invalid argument */
+  LBM_EHIP = -2,       /* a HIP runtime call or kernel launch failed */
+  LBM_ENONFINITE = -3, /* a cell density became non-finite or non-positive */
+  LBM_ENEWTON = -4,    /* the wall-function Newton solve failed */
+  LBM_ESIZE = -5       /* workspace or buffer too small, or domain too large */
+};
+
+enum { LBM_D3Q19 = 19, LBM_D3Q27 = 27 };
+enum { LBM_F64 = 0, LBM_F32DEV = 1, LBM_F16DEV = 2 };
+
+typedef struct {
+  int lattice;        /* LBM_D3Q19 or LBM_D3Q27 */
+  int nx, ny, nz;     /* domain size in cells */
+  int periodic[3];    /* per axis; outside a non-periodic axis is solid */
+  int storage;        /* LBM_F64 | LBM_F32DEV | LBM_F16DEV */
+  double tau0;        /* molecular relaxation time, nu = (tau0 - 1/2)/3, > 1/2 */
+  double cs_smag;     /* Smagorinsky constant C_S (filter width = 1 cell), >= 0 */
+  double force[3];    /* body force per unit volume, lattice units (Guo) */
+  int wall_model;     /* 0: bounce-back only; 1: Spalding wall model on wall cells */
+  double kappa, E;    /* Spalding constants (0.41, 9.0 for a smooth wall) */
+  int fringe_len;     /* urban open boundary: fringe over the last planes in x (0 = off) */
+  double u_ref, z0;   /* log-law inflow u_ref ln(1 + z_c/z0)/ln(1 + z_top/z0) */
+  int lid;            /* 1: the top plane z = nz-1 holds the inflow equilibrium */
+  void *stream;       /* hipStream_t for all device work (NULL = null stream) */
+} lbm_params;
+
+/* Device bytes the caller must provide to lbm_init for these parameters and
+ * this host mask (uint8 [N], 1 = fluid; NULL = all fluid).  Returns 0 on
+ * invalid parameters.  porous != 0 reserves room for a porosity field. */
+size_t lbm_workspace_bytes(const lbm_params *p, const uint8_t *mask, int porous);
+
+/* Creates a context, builds the cell flags and wall-cell records on the host
+ * (wall cells: fluid cells with a solid link; normal from the sum of solid
+ * links; reference cell one step along the best-aligned lattice direction),
+ * uploads them, and writes f^0 = f^eq(rho0, u0) (Sec. 2.2 second-order
+ * equilibrium).  Synchronises the stream before returning.
+ *   mask      host uint8 [N], 1 = fluid, 0 = solid; NULL = all fluid
+ *   wall_dist host double [N], distance from each cell centre to the wall,
+ *             read at wall cells and their reference cells only; NULL with
+ *             wall_model = 1 makes the library compute the voxel distance
+ *             (nearest solid unit cube within two cells, outside = solid)
+ *   porosity  host double [N] in [0,1] (1 = fluid; Eq. (12) read with
+ *             d = 1 - porosity); NULL = 1 everywhere
+ *   rho0, u0  DEVICE double [N] and [3][N] initial fields; NULL = 1 and 0
+ *   workspace device memory of at least lbm_workspace_bytes(p, mask,
+ *             porosity != NULL) bytes, caller-owned, 256-byte aligned,
+ *             not touched by the caller while the context lives. */
+int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const double *wall_dist,
+             const double *porosity, const double *rho0, const double *u0, void *workspace,
+             size_t workspace_bytes);
+
+/* Advances n >= 0 time steps (async).  Each step: wall prepass (u_tau by
+ * Newton in FP64 from the Spalding law at the reference cell), then the
+ * fused collide-and-stream of all fluid cells and the wall reconstruction. */
+int lbm_step(lbm_ctx *ctx, int n);
+
+/* Density and velocity u = (j + F/2)/rho of the current state into device
+ * buffers of the compute type, rho [N] and u [3][N]; solid cells give 0
+ * (async). */
+int lbm_moments(lbm_ctx *ctx, void *rho, void *u);
+
+/* Total mass and momentum over fluid cells of the current state, summed in
+ * FP64 in a fixed order (deterministic): out = {M, Px, Py, Pz}.  Synchronises
+ * and reports kernel-side faults. */
+int lbm_diagnostics(lbm_ctx *ctx, double out[4]);
+
+/* Waits for the stream and reports kernel-side faults. */
+int lbm_sync(lbm_ctx *ctx);
+
+/* Number of time steps taken since lbm_init (or the loaded state). */
+long long lbm_steps_done(const lbm_ctx *ctx);
+
+/* Current populations f_i = w_i + g_i in natural order [q][N] of the compute
+ * type (device, async); solid cells give 0. */
+int lbm_get_populations(lbm_ctx *ctx, void *f);
+/* Replaces the state by the populations f [q][N] of the compute type
+ * (device, async); values at solid cells are ignored. */
+int lbm_set_populations(lbm_ctx *ctx, const void *f);
+
+/* Snapshot of the state (populations in their in-memory layout plus the step
+ * counter) into / from caller device memory of lbm_state_bytes() bytes
+ * (async D2D copies; load reads the step counter synchronously). */
+size_t lbm_state_bytes(const lbm_ctx *ctx);
+int lbm_save_state(lbm_ctx *ctx, void *dst);
+int lbm_load_state(lbm_ctx *ctx, const void *src);
+
+/* Terminal objective of the porosity-gradient problem:
+ * J = c_s^2 (<rho>_{x=planes[0]} - <rho>_{x=planes[1]}) + <rho |u|^2 / 2>,
+ * means over the fluid cells of each plane / of the domain, u the Guo
+ * velocity.  Synchronises; *J in FP64. */
+int lbm_objective(lbm_ctx *ctx, const int planes[2], double *J);
+
+/* Discrete adjoint.  An adjoint field lambda has the layout of the state
+ * (q arrays of N entries of the compute type, in-memory AA order of the
+ * current step parity); it is caller device memory of lbm_adjoint_bytes().
+ *  lbm_adjoint_seed: lambda = dJ/df of the current state (async).
+ *  lbm_adjoint_step: given lambda = dJ/df^{n+1} and the state f^n currently
+ *    held by the context (step counter n), overwrites lambda with dJ/df^n
+ *    and adds dJ/dphi contributions of step n to grad_phi [N] (compute
+ *    type); decrements nothing (the caller restores f^{n-1} itself). Async.
+ *  lbm_adjoint_to_natural / _from_natural: convert lambda between the
+ *    in-memory layout of the current parity and natural [q][N] order. */
+size_t lbm_adjoint_bytes(const lbm_ctx *ctx);
+int lbm_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lambda);
+int lbm_adjoint_step(lbm_ctx *ctx, void *lambda, void *grad_phi);
+int lbm_adjoint_to_natural(lbm_ctx *ctx, const void *lambda, void *natural);
+int lbm_adjoint_from_natural(lbm_ctx *ctx, const void *natural, void *lambda);
+
+/* Gradient dJ/dphi after T steps from the current state (which becomes step
+ * 0 of the sweep), by a binomial checkpointing reverse sweep (Griewank-
+ * Walther): snapshots is caller device memory for nsnap >= 1 states of
+ * lbm_state_bytes() each, lambda of lbm_adjoint_bytes(), grad_phi [N] of
+ * the compute type (overwritten).  *J receives the objective at step T, and
+ * *nforward the number of forward steps taken (T plus recomputation).  On
+ * return the context holds the state of step 0 again.  Synchronises. */
+int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
+                 void *grad_phi, double *J, long long *nforward);
+
+/* The forward-step count of the optimal binomial schedule for T steps and
+ * nsnap snapshot slots (host only; the starting state occupies one slot). */
+long long lbm_revolve_cost(int T, int nsnap);
+
+/* Number of wall-modeled cells, and their records (host arrays of that
+ * length; any pointer may be NULL): cell, reference cell, normal [n][3],
+ * and from the last wall prepass u_tau, G, tau_eff.  Synchronises. */
+int lbm_wall_count(const lbm_ctx *ctx);
+int lbm_wall_records(lbm_ctx *ctx, int *cell, int *ref, double *normal, double *utau, double *G,
+                     double *tau);
+
+const char *lbm_last_error(const lbm_ctx *ctx);
+/* Releases the context (host memory only; the workspace stays the caller's). */
+void lbm_free(lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_MI355X_H */

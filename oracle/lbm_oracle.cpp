@@ -173,15 +173,31 @@ T tau_effective(double tau0, double cs, const T& pinorm, const T& rho) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Spalding wall function (Sec. 2.2.1, Eq. (17)), smooth wall.               */
+/* Spalding wall function (Sec. 2.2.1, Eq. (17)), smooth wall:               */
+/*   y+ = g(u+) = u+ + [exp(a) - 1 - a - a^2/2 - a^3/6] / E,  a = kappa u+.   */
+/* For small a the bracket is evaluated by its power series sum_{n>=4}       */
+/* a^n/n!, which avoids the cancellation of the four leading terms.          */
 /* ------------------------------------------------------------------------ */
+double exp_tail(double a, int from) {
+  /* sum_{n >= from} a^n / n!  for 0 <= a < 1/2 (from = 3 or 4) */
+  double term = 1.0;
+  for (int n = 1; n <= from; ++n) term *= a / n;
+  double sum = 0.0;
+  for (int n = from; n < from + 24; ++n) {
+    sum += term;
+    term *= a / (n + 1);
+  }
+  return sum;
+}
 double spalding_g(double up, double kappa, double E) {
   double k = kappa * up;
-  return up + (std::exp(k) - 1.0 - k - 0.5 * k * k - k * k * k / 6.0) / E;
+  double rem = (k >= 0.0 && k < 0.5) ? exp_tail(k, 4) : std::exp(k) - 1.0 - k - 0.5 * k * k - k * k * k / 6.0;
+  return up + rem / E;
 }
 double spalding_dg(double up, double kappa, double E) {
   double k = kappa * up;
-  return 1.0 + kappa * (std::exp(k) - 1.0 - k - 0.5 * k * k) / E;
+  double rem = (k >= 0.0 && k < 0.5) ? exp_tail(k, 3) : std::exp(k) - 1.0 - k - 0.5 * k * k;
+  return 1.0 + kappa * rem / E;
 }
 
 /* Friction velocity from the law at distance y with tangential speed U:

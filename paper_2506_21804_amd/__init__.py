@@ -1,0 +1,362 @@
+"""Python binding of the MI355X wall-modeled LBM-LES library (``liblbm_hip.so``).
+
+The functions here carry the C-ABI names of ``include/lbm.h`` and only
+marshal arguments: torch tensors supply device memory and the HIP stream,
+numpy arrays the host inputs.  Every step of the computation runs in the HIP
+kernels of the library.  The library must have been built
+(``python -m paper_2506_21804_amd.build``); loading fails loudly otherwise.
+There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = [
+    "load", "LbmError", "Params", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_moments",
+    "lbm_diagnostics", "lbm_sync", "lbm_steps_done", "lbm_get_populations", "lbm_set_populations",
+    "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes",
+    "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural",
+    "lbm_gradient", "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_last_error", "lbm_free",
+    "Lattice", "D3Q19", "D3Q27", "F64", "F32DEV", "F16DEV",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbm_hip.so")
+
+OK, EINVAL, EHIP, ENONFINITE, ENEWTON, ESIZE = 0, -1, -2, -3, -4, -5
+D3Q19, D3Q27 = 19, 27
+F64, F32DEV, F16DEV = 0, 1, 2
+STORAGE_NAMES = {"f64": F64, "f32": F32DEV, "f16": F16DEV}
+
+
+class Params(C.Structure):
+    """Mirror of ``lbm_params``."""
+    _fields_ = [
+        ("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("periodic", C.c_int * 3),
+        ("storage", C.c_int),
+        ("tau0", C.c_double), ("cs_smag", C.c_double),
+        ("force", C.c_double * 3),
+        ("wall_model", C.c_int),
+        ("kappa", C.c_double), ("E", C.c_double),
+        ("fringe_len", C.c_int),
+        ("u_ref", C.c_double), ("z0", C.c_double),
+        ("lid", C.c_int),
+        ("stream", C.c_void_p),
+    ]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Loads the built HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_21804_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, sz, i, d, ll = C.c_void_p, C.c_size_t, C.c_int, C.c_double, C.c_longlong
+    sig = {
+        "lbm_workspace_bytes": (sz, [C.POINTER(Params), vp, i]),
+        "lbm_init": (i, [C.POINTER(vp), C.POINTER(Params), vp, vp, vp, vp, vp, vp, sz]),
+        "lbm_step": (i, [vp, i]),
+        "lbm_moments": (i, [vp, vp, vp]),
+        "lbm_diagnostics": (i, [vp, vp]),
+        "lbm_sync": (i, [vp]),
+        "lbm_steps_done": (ll, [vp]),
+        "lbm_get_populations": (i, [vp, vp]),
+        "lbm_set_populations": (i, [vp, vp]),
+        "lbm_state_bytes": (sz, [vp]),
+        "lbm_save_state": (i, [vp, vp]),
+        "lbm_load_state": (i, [vp, vp]),
+        "lbm_objective": (i, [vp, vp, C.POINTER(d)]),
+        "lbm_adjoint_bytes": (sz, [vp]),
+        "lbm_adjoint_seed": (i, [vp, vp, vp]),
+        "lbm_adjoint_step": (i, [vp, vp, vp]),
+        "lbm_adjoint_to_natural": (i, [vp, vp, vp]),
+        "lbm_adjoint_from_natural": (i, [vp, vp, vp]),
+        "lbm_gradient": (i, [vp, i, vp, vp, i, vp, vp, C.POINTER(d), C.POINTER(ll)]),
+        "lbm_revolve_cost": (ll, [i, i]),
+        "lbm_wall_count": (i, [vp]),
+        "lbm_wall_records": (i, [vp, vp, vp, vp, vp, vp, vp]),
+        "lbm_last_error": (C.c_char_p, [vp]),
+        "lbm_free": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_moments", "lbm_diagnostics", "lbm_sync",
+            "lbm_steps_done", "lbm_get_populations", "lbm_set_populations", "lbm_state_bytes",
+            "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes", "lbm_adjoint_seed",
+            "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural", "lbm_gradient",
+            "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_last_error", "lbm_free"]
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _hptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(ctx, rc):
+    if rc != OK:
+        raise LbmError(rc, load().lbm_last_error(ctx).decode())
+
+
+def make_params(q, shape, periodic=(1, 1, 1), storage=F64, tau0=0.6, cs_smag=0.0, force=(0.0, 0.0, 0.0),
+                wall_model=0, kappa=0.41, E=9.0, fringe_len=0, u_ref=0.0, z0=1.0, lid=0, stream=None) -> Params:
+    p = Params()
+    p.lattice = q
+    p.nx, p.ny, p.nz = shape
+    p.periodic = (C.c_int * 3)(*[int(v) for v in periodic])
+    p.storage = STORAGE_NAMES.get(storage, storage) if isinstance(storage, str) else storage
+    p.tau0, p.cs_smag = tau0, cs_smag
+    p.force = (C.c_double * 3)(*force)
+    p.wall_model, p.kappa, p.E = wall_model, kappa, E
+    p.fringe_len, p.u_ref, p.z0, p.lid = fringe_len, u_ref, z0, lid
+    p.stream = stream
+    return p
+
+
+# ---- C-ABI wrappers (same names) --------------------------------------------
+
+def lbm_workspace_bytes(p: Params, mask=None, porous=False) -> int:
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    n = load().lbm_workspace_bytes(C.byref(p), _hptr(m), 1 if porous else 0)
+    if n == 0:
+        raise LbmError(EINVAL, load().lbm_last_error(None).decode())
+    return n
+
+
+def lbm_init(p: Params, mask, wall_dist, porosity, rho0_dev, u0_dev, workspace):
+    keep = [None if a is None else np.ascontiguousarray(a, dtype=dt)
+            for a, dt in ((mask, np.uint8), (wall_dist, np.float64), (porosity, np.float64))]
+    ctx = C.c_void_p()
+    rc = load().lbm_init(C.byref(ctx), C.byref(p), _hptr(keep[0]), _hptr(keep[1]), _hptr(keep[2]),
+                         _dptr(rho0_dev), _dptr(u0_dev), _dptr(workspace), workspace.numel())
+    if rc != OK:
+        raise LbmError(rc, load().lbm_last_error(None).decode())
+    return ctx
+
+
+def lbm_step(ctx, n=1):
+    _check(ctx, load().lbm_step(ctx, int(n)))
+
+
+def lbm_moments(ctx, rho, u):
+    _check(ctx, load().lbm_moments(ctx, _dptr(rho), _dptr(u)))
+
+
+def lbm_diagnostics(ctx):
+    out = (C.c_double * 4)()
+    _check(ctx, load().lbm_diagnostics(ctx, out))
+    return np.array(out[:])
+
+
+def lbm_sync(ctx):
+    _check(ctx, load().lbm_sync(ctx))
+
+
+def lbm_steps_done(ctx) -> int:
+    return load().lbm_steps_done(ctx)
+
+
+def lbm_get_populations(ctx, f):
+    _check(ctx, load().lbm_get_populations(ctx, _dptr(f)))
+
+
+def lbm_set_populations(ctx, f):
+    _check(ctx, load().lbm_set_populations(ctx, _dptr(f)))
+
+
+def lbm_state_bytes(ctx) -> int:
+    return load().lbm_state_bytes(ctx)
+
+
+def lbm_save_state(ctx, dst):
+    _check(ctx, load().lbm_save_state(ctx, _dptr(dst)))
+
+
+def lbm_load_state(ctx, src):
+    _check(ctx, load().lbm_load_state(ctx, _dptr(src)))
+
+
+def lbm_objective(ctx, planes) -> float:
+    pl = (C.c_int * 2)(*planes)
+    J = C.c_double()
+    _check(ctx, load().lbm_objective(ctx, pl, C.byref(J)))
+    return J.value
+
+
+def lbm_adjoint_bytes(ctx) -> int:
+    return load().lbm_adjoint_bytes(ctx)
+
+
+def lbm_adjoint_seed(ctx, planes, lam):
+    pl = (C.c_int * 2)(*planes)
+    _check(ctx, load().lbm_adjoint_seed(ctx, pl, _dptr(lam)))
+
+
+def lbm_adjoint_step(ctx, lam, grad):
+    _check(ctx, load().lbm_adjoint_step(ctx, _dptr(lam), _dptr(grad)))
+
+
+def lbm_adjoint_to_natural(ctx, lam, nat):
+    _check(ctx, load().lbm_adjoint_to_natural(ctx, _dptr(lam), _dptr(nat)))
+
+
+def lbm_adjoint_from_natural(ctx, nat, lam):
+    _check(ctx, load().lbm_adjoint_from_natural(ctx, _dptr(nat), _dptr(lam)))
+
+
+def lbm_gradient(ctx, T, planes, snapshots, nsnap, lam, grad):
+    pl = (C.c_int * 2)(*planes)
+    J = C.c_double()
+    nf = C.c_longlong()
+    _check(ctx, load().lbm_gradient(ctx, int(T), pl, _dptr(snapshots), int(nsnap), _dptr(lam), _dptr(grad),
+                                    C.byref(J), C.byref(nf)))
+    return J.value, nf.value
+
+
+def lbm_revolve_cost(T, nsnap) -> int:
+    return load().lbm_revolve_cost(int(T), int(nsnap))
+
+
+def lbm_wall_count(ctx) -> int:
+    return load().lbm_wall_count(ctx)
+
+
+def lbm_wall_records(ctx):
+    nw = lbm_wall_count(ctx)
+    cell = np.empty(nw, np.int32)
+    ref = np.empty(nw, np.int32)
+    normal = np.empty((nw, 3))
+    utau, G, tau = np.empty(nw), np.empty(nw), np.empty(nw)
+    _check(ctx, load().lbm_wall_records(ctx, _hptr(cell), _hptr(ref), _hptr(normal), _hptr(utau), _hptr(G),
+                                        _hptr(tau)))
+    return dict(cells=cell, refs=ref, normal=normal, utau=utau, G=G, tau=tau)
+
+
+def lbm_last_error(ctx) -> str:
+    return load().lbm_last_error(ctx).decode()
+
+
+def lbm_free(ctx):
+    load().lbm_free(ctx)
+
+
+# ---- convenience object ------------------------------------------------------
+
+class Lattice:
+    """Owns a context and its torch-allocated workspace on the current device.
+
+    ``case`` is an ``inputs.Case`` (or anything with the same attributes);
+    ``storage`` one of "f64", "f32", "f16".  rho0/u0 of the case are uploaded
+    to the device as float64 for initialisation and then released."""
+
+    def __init__(self, case, storage="f64", stream=None, wall_dist="case"):
+        import torch
+        self.torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.q = case.q
+        self.shape = tuple(case.shape)
+        self.N = int(np.prod(self.shape))
+        self.storage = STORAGE_NAMES[storage] if isinstance(storage, str) else storage
+        self.rdtype = torch.float64 if self.storage == F64 else torch.float32
+        self.p = make_params(case.q, case.shape, periodic=case.periodic, storage=self.storage, tau0=case.tau0,
+                             cs_smag=case.cs_smag, force=case.force, wall_model=case.wall_model, kappa=case.kappa,
+                             E=case.E, fringe_len=case.fringe_len, u_ref=case.u_ref, z0=case.z0, lid=case.lid,
+                             stream=stream.cuda_stream)
+        porous = case.porosity is not None
+        nbytes = lbm_workspace_bytes(self.p, case.mask, porous)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws = self.workspace[off:off + nbytes]
+        dev = torch.device("cuda")
+        rho0 = None if case.rho0 is None else torch.as_tensor(np.ascontiguousarray(case.rho0), device=dev)
+        u0 = None if case.u0 is None else torch.as_tensor(np.ascontiguousarray(case.u0), device=dev)
+        wd = case.wall_dist if isinstance(wall_dist, str) else wall_dist
+        with torch.cuda.stream(stream):
+            self.ctx = lbm_init(self.p, case.mask, wd, case.porosity, rho0, u0, self.ws)
+        del rho0, u0
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            try:
+                lbm_sync(ctx)
+            except Exception:
+                pass
+            lbm_free(ctx)
+            self.ctx = None
+
+    def step(self, n=1):
+        lbm_step(self.ctx, n)
+
+    def sync(self):
+        lbm_sync(self.ctx)
+
+    @property
+    def steps(self) -> int:
+        return lbm_steps_done(self.ctx)
+
+    def moments(self):
+        torch = self.torch
+        rho = torch.empty(self.N, dtype=self.rdtype, device="cuda")
+        u = torch.empty((3, self.N), dtype=self.rdtype, device="cuda")
+        lbm_moments(self.ctx, rho, u)
+        lbm_sync(self.ctx)
+        return rho, u
+
+    def diagnostics(self):
+        return lbm_diagnostics(self.ctx)
+
+    def populations(self):
+        f = self.torch.empty((self.q, self.N), dtype=self.rdtype, device="cuda")
+        lbm_get_populations(self.ctx, f)
+        lbm_sync(self.ctx)
+        return f
+
+    def set_populations(self, f):
+        f = f.to(device="cuda", dtype=self.rdtype).contiguous()
+        lbm_set_populations(self.ctx, f)
+        lbm_sync(self.ctx)
+
+    def new_state_buffer(self, count=1):
+        return self.torch.empty(count * lbm_state_bytes(self.ctx), dtype=self.torch.uint8, device="cuda")
+
+    def save_state(self, buf):
+        lbm_save_state(self.ctx, buf)
+
+    def load_state(self, buf):
+        lbm_load_state(self.ctx, buf)
+
+    def objective(self, planes):
+        return lbm_objective(self.ctx, planes)
+
+    def new_adjoint(self):
+        return self.torch.zeros((self.q, self.N), dtype=self.rdtype, device="cuda")
+
+    def wall_records(self):
+        return lbm_wall_records(self.ctx)

@@ -1,0 +1,497 @@
+// C ABI of the MI355X LBM-LES library: argument checks, workspace layout,
+// geometry upload, the step loop and the checkpointed reverse sweep.  All
+// arithmetic of the method runs in the kernels of kernels.hip / adjoint.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace lbmk;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int PARTIAL_SLOTS = 1024;
+constexpr size_t HEADER_BYTES = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+std::string g_static_error;
+
+int set_err(lbm_ctx *ctx, int code, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  else g_static_error = msg;
+  return code;
+}
+
+size_t storage_bytes(int storage) { return storage == LBM_F64 ? 8 : storage == LBM_F32DEV ? 4 : 2; }
+size_t compute_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
+
+// Parameter validation shared by lbm_workspace_bytes and lbm_init.
+bool params_ok(const lbm_params *p, std::string &msg) {
+  if (!p) {
+    msg = "null parameters";
+    return false;
+  }
+  if (p->lattice != 19 && p->lattice != 27) {
+    msg = "lattice must be 19 or 27";
+    return false;
+  }
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) {
+    msg = "domain sizes must be positive";
+    return false;
+  }
+  const long long N = (long long)p->nx * p->ny * p->nz;
+  if (N >= (1LL << 31)) {
+    msg = "domain has 2^31 cells or more";
+    return false;
+  }
+  if (p->storage != LBM_F64 && p->storage != LBM_F32DEV && p->storage != LBM_F16DEV) {
+    msg = "storage must be LBM_F64, LBM_F32DEV or LBM_F16DEV";
+    return false;
+  }
+  if (!(p->tau0 > 0.5) || !std::isfinite(p->tau0)) {
+    msg = "tau0 must be finite and exceed 1/2";
+    return false;
+  }
+  if (!(p->cs_smag >= 0.0) || !std::isfinite(p->cs_smag)) {
+    msg = "cs_smag must be finite and >= 0";
+    return false;
+  }
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->force[a])) {
+      msg = "force must be finite";
+      return false;
+    }
+  if (p->wall_model && (!(p->kappa > 0.0) || !(p->E > 0.0))) {
+    msg = "wall model needs kappa > 0 and E > 0";
+    return false;
+  }
+  if (p->fringe_len < 0 || p->fringe_len > p->nx) {
+    msg = "fringe_len must be in [0, nx]";
+    return false;
+  }
+  if ((p->fringe_len > 0 || p->lid) && (!(p->z0 > 0.0) || !std::isfinite(p->u_ref))) {
+    msg = "fringe / lid need z0 > 0 and a finite u_ref";
+    return false;
+  }
+  return true;
+}
+
+struct Layout {
+  size_t pop, flags, phi, tables, wcell, wref, wrec, partial, result, errflag, total;
+};
+
+Layout layout_of(const lbm_params &p, long long nwall, bool porous) {
+  const size_t N = (size_t)p.nx * p.ny * p.nz;
+  const size_t rb = compute_bytes(p.storage);
+  Layout L{};
+  size_t off = 0;
+  L.pop = off;
+  off += align_up((size_t)p.lattice * N * storage_bytes(p.storage));
+  L.flags = off;
+  off += align_up(N);
+  L.phi = off;
+  off += porous ? align_up(N * rb) : 0;
+  L.tables = off;
+  off += align_up(((size_t)p.nz + p.nx) * rb);
+  L.wcell = off;
+  off += align_up((size_t)nwall * sizeof(int));
+  L.wref = off;
+  off += align_up((size_t)nwall * sizeof(int));
+  L.wrec = off;
+  off += align_up((size_t)nwall * WR_COUNT * sizeof(double));
+  L.partial = off;
+  off += align_up((size_t)PARTIAL_SLOTS * 8 * sizeof(double));
+  L.result = off;
+  off += align_up(32 * sizeof(double));
+  L.errflag = off;
+  off += align_up(sizeof(int));
+  L.total = off;
+  return L;
+}
+
+int sync_and_check(lbm_ctx *ctx) {
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  int flag = 0;
+  e = hipMemcpy(&flag, ctx->errflag, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reading the fault flag");
+  if (flag & 1) return set_err(ctx, LBM_ENONFINITE, "a cell density became non-finite or non-positive");
+  if (flag & 2) return set_err(ctx, LBM_ENEWTON, "wall-function Newton solve failed (no convergence or exp range)");
+  return LBM_OK;
+}
+
+std::vector<unsigned char> to_compute(const std::vector<double> &v, int storage) {
+  std::vector<unsigned char> out(v.size() * compute_bytes(storage));
+  if (storage == LBM_F64) std::memcpy(out.data(), v.data(), v.size() * sizeof(double));
+  else
+    for (size_t i = 0; i < v.size(); ++i) {
+      const float f = (float)v[i];
+      std::memcpy(out.data() + 4 * i, &f, 4);
+    }
+  return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params *p, const uint8_t *mask, int porous) {
+  std::string msg;
+  if (!params_ok(p, msg)) {
+    g_static_error = msg;
+    return 0;
+  }
+  return layout_of(*p, count_wall_cells(*p, mask), porous != 0).total;
+}
+
+int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const double *wall_dist,
+             const double *porosity, const double *rho0, const double *u0, void *workspace,
+             size_t workspace_bytes) {
+  std::string msg;
+  if (!out) return set_err(nullptr, LBM_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!params_ok(p, msg)) return set_err(nullptr, LBM_EINVAL, msg);
+  if (!workspace || ((uintptr_t)workspace % ALIGN) != 0)
+    return set_err(nullptr, LBM_EINVAL, "workspace must be non-null and 256-byte aligned");
+  const long long N = (long long)p->nx * p->ny * p->nz;
+  if (porosity)
+    for (long long c = 0; c < N; ++c)
+      if (!(porosity[c] >= 0.0 && porosity[c] <= 1.0))
+        return set_err(nullptr, LBM_EINVAL, "porosity must lie in [0, 1]");
+
+  Geometry g;
+  int rc = build_geometry(*p, mask, g, msg);
+  if (rc != LBM_OK) return set_err(nullptr, rc, msg);
+  const long long nwall = (long long)g.wcell.size();
+  const Layout L = layout_of(*p, nwall, porosity != nullptr);
+  if (workspace_bytes < L.total)
+    return set_err(nullptr, LBM_ESIZE, "workspace smaller than lbm_workspace_bytes()");
+
+  // wall records: normals and wall distances (static part)
+  std::vector<double> rec((size_t)nwall * WR_COUNT, 0.0);
+  for (long long k = 0; k < nwall; ++k) {
+    const long long b = g.wcell[k], r = g.wref[k];
+    const double yb = wall_dist ? wall_dist[b] : voxel_distance(*p, mask, b);
+    const double yr = wall_dist ? wall_dist[r] : voxel_distance(*p, mask, r);
+    if (!(yb > 0.0 && std::isfinite(yb) && yr > 0.0 && std::isfinite(yr)))
+      return set_err(nullptr, LBM_EINVAL,
+                     "wall distance must be positive and finite at wall cells and their references");
+    for (int a = 0; a < 3; ++a) rec[(size_t)(WR_NX + a) * nwall + k] = g.wnorm[3 * k + a];
+    rec[(size_t)WR_YB * nwall + k] = yb;
+    rec[(size_t)WR_YR * nwall + k] = yr;
+    rec[(size_t)WR_TAU * nwall + k] = p->tau0;
+  }
+
+  lbm_ctx *ctx = new (std::nothrow) lbm_ctx();
+  if (!ctx) return set_err(nullptr, LBM_EINVAL, "out of host memory");
+  ctx->p = *p;
+  ctx->q = p->lattice;
+  ctx->N = N;
+  ctx->elem = storage_bytes(p->storage);
+  ctx->stream = (hipStream_t)p->stream;
+  ctx->porous = porosity != nullptr;
+  ctx->has_solid = g.has_solid;
+  ctx->has_lid = g.has_lid;
+  char *base = (char *)workspace;
+  ctx->pop = base + L.pop;
+  ctx->flags = (uint8_t *)(base + L.flags);
+  ctx->phi = ctx->porous ? base + L.phi : nullptr;
+  ctx->tables = base + L.tables;
+  ctx->nwall = (int)nwall;
+  ctx->wcell = (int *)(base + L.wcell);
+  ctx->wref = (int *)(base + L.wref);
+  ctx->wrec = (double *)(base + L.wrec);
+  ctx->partial = (double *)(base + L.partial);
+  ctx->npartial = PARTIAL_SLOTS;
+  ctx->result = (double *)(base + L.result);
+  ctx->errflag = (int *)(base + L.errflag);
+
+  // kernel constants
+  KArgs &k = ctx->ka;
+  k.nx = p->nx;
+  k.ny = p->ny;
+  k.nz = p->nz;
+  k.N = (int)N;
+  for (int a = 0; a < 3; ++a) k.per[a] = p->periodic[a] ? 1 : 0;
+  k.tau0 = p->tau0;
+  k.cs2 = p->cs_smag * p->cs_smag;
+  k.smag = 18.0 * std::sqrt(2.0) * k.cs2;
+  k.nu = (p->tau0 - 0.5) / 3.0;
+  for (int a = 0; a < 3; ++a) k.F[a] = p->force[a];
+  k.kappa = p->kappa;
+  k.E = p->E;
+  k.fringe_start = p->fringe_len > 0 ? p->nx - p->fringe_len : p->nx;
+  k.u_lid = p->u_ref;  // ln(1 + z_top/z0) / ln(1 + z_top/z0) = 1 at the lid plane
+  // inflow profile u_in(z) and fringe weights lambda(x)
+  std::vector<double> tab((size_t)p->nz + p->nx, 0.0);
+  if (p->fringe_len > 0 || p->lid) {
+    const double ztop = p->nz - 0.5;
+    for (int z = 0; z < p->nz; ++z)
+      tab[z] = p->u_ref * std::log(1.0 + (z + 0.5) / p->z0) / std::log(1.0 + ztop / p->z0);
+  }
+  for (int x = k.fringe_start; x < p->nx; ++x) {
+    const double s = double(x - k.fringe_start + 1) / p->fringe_len;
+    tab[(size_t)p->nz + x] = s * s * (3.0 - 2.0 * s);
+  }
+  std::vector<unsigned char> tabc = to_compute(tab, p->storage);
+  k.uin = ctx->tables;
+  k.lam = (char *)ctx->tables + (size_t)p->nz * compute_bytes(p->storage);
+
+  hipError_t e;
+  auto fail = [&](hipError_t err, const char *what) {
+    int code = hip_fail(ctx, err, what);
+    g_static_error = ctx->err;
+    delete ctx;
+    return code;
+  };
+  std::vector<unsigned char> phic;
+  if (porosity) {
+    std::vector<double> ph(porosity, porosity + N);
+    phic = to_compute(ph, p->storage);
+  }
+  // uploads (synchronous copies from pageable host memory; the stream is
+  // synchronised below before any kernel reads them)
+  if ((e = hipMemcpy(ctx->flags, g.flags.data(), (size_t)N, hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e, "upload flags");
+  if ((e = hipMemcpy(ctx->tables, tabc.data(), tabc.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e, "upload tables");
+  if (porosity && (e = hipMemcpy(ctx->phi, phic.data(), phic.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e, "upload porosity");
+  if (nwall > 0) {
+    if ((e = hipMemcpy(ctx->wcell, g.wcell.data(), nwall * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e, "upload wall cells");
+    if ((e = hipMemcpy(ctx->wref, g.wref.data(), nwall * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e, "upload wall references");
+    if ((e = hipMemcpy(ctx->wrec, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e, "upload wall records");
+  }
+  if (dev_fill(ctx, ctx->errflag, ALIGN) != LBM_OK || dev_init_equilibrium(ctx, rho0, u0) != LBM_OK) {
+    int code = LBM_EHIP;
+    g_static_error = ctx->err;
+    delete ctx;
+    return code;
+  }
+  if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return fail(e, "hipStreamSynchronize");
+  ctx->steps = 0;
+  *out = ctx;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *ctx, int n) {
+  if (!ctx) return LBM_EINVAL;
+  if (n < 0) return set_err(ctx, LBM_EINVAL, "negative step count");
+  for (int s = 0; s < n; ++s) {
+    int rc = dev_step(ctx);
+    if (rc != LBM_OK) return rc;
+    ++ctx->steps;
+  }
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx *ctx, void *rho, void *u) {
+  if (!ctx) return LBM_EINVAL;
+  if (!rho && !u) return set_err(ctx, LBM_EINVAL, "both outputs are null");
+  return dev_moments(ctx, rho, u);
+}
+
+int lbm_sync(lbm_ctx *ctx) {
+  if (!ctx) return LBM_EINVAL;
+  return sync_and_check(ctx);
+}
+
+int lbm_diagnostics(lbm_ctx *ctx, double out[4]) {
+  if (!ctx || !out) return ctx ? set_err(ctx, LBM_EINVAL, "null output") : LBM_EINVAL;
+  int rc = dev_reduce_diag(ctx);
+  if (rc != LBM_OK) return rc;
+  rc = sync_and_check(ctx);
+  if (rc != LBM_OK) return rc;
+  double r[8];
+  hipError_t e = hipMemcpy(r, ctx->result, sizeof(r), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "read diagnostics");
+  // mass = number of fluid cells + sum of density deviations
+  out[0] = r[4] + r[0];
+  out[1] = r[1];
+  out[2] = r[2];
+  out[3] = r[3];
+  return LBM_OK;
+}
+
+long long lbm_steps_done(const lbm_ctx *ctx) { return ctx ? ctx->steps : -1; }
+
+int lbm_get_populations(lbm_ctx *ctx, void *f) {
+  if (!ctx || !f) return ctx ? set_err(ctx, LBM_EINVAL, "null output") : LBM_EINVAL;
+  return dev_export(ctx, f);
+}
+
+int lbm_set_populations(lbm_ctx *ctx, const void *f) {
+  if (!ctx || !f) return ctx ? set_err(ctx, LBM_EINVAL, "null input") : LBM_EINVAL;
+  return dev_import(ctx, f);
+}
+
+size_t lbm_state_bytes(const lbm_ctx *ctx) {
+  if (!ctx) return 0;
+  return HEADER_BYTES + align_up((size_t)ctx->q * ctx->N * ctx->elem);
+}
+
+int lbm_save_state(lbm_ctx *ctx, void *dst) {
+  if (!ctx || !dst) return ctx ? set_err(ctx, LBM_EINVAL, "null destination") : LBM_EINVAL;
+  int rc = dev_write_header(ctx, dst);
+  if (rc != LBM_OK) return rc;
+  hipError_t e = hipMemcpyAsync((char *)dst + HEADER_BYTES, ctx->pop, (size_t)ctx->q * ctx->N * ctx->elem,
+                                hipMemcpyDeviceToDevice, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "save state");
+  return LBM_OK;
+}
+
+int lbm_load_state(lbm_ctx *ctx, const void *src) {
+  if (!ctx || !src) return ctx ? set_err(ctx, LBM_EINVAL, "null source") : LBM_EINVAL;
+  long long h[5];
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  e = hipMemcpy(h, src, sizeof(h), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "read state header");
+  if (h[0] != 0x4c424d5354415445LL || h[2] != ctx->q || h[3] != ctx->N || h[4] != ctx->p.storage)
+    return set_err(ctx, LBM_EINVAL, "state buffer does not match this context");
+  e = hipMemcpyAsync(ctx->pop, (const char *)src + HEADER_BYTES, (size_t)ctx->q * ctx->N * ctx->elem,
+                     hipMemcpyDeviceToDevice, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "load state");
+  ctx->steps = h[1];
+  return LBM_OK;
+}
+
+int lbm_objective(lbm_ctx *ctx, const int planes[2], double *J) {
+  if (!ctx || !planes || !J) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
+  if (planes[0] < 0 || planes[0] >= ctx->p.nx || planes[1] < 0 || planes[1] >= ctx->p.nx)
+    return set_err(ctx, LBM_EINVAL, "objective planes outside the domain");
+  int rc = dev_objective(ctx, planes);
+  if (rc != LBM_OK) return rc;
+  rc = sync_and_check(ctx);
+  if (rc != LBM_OK) return rc;
+  double r[8];
+  hipError_t e = hipMemcpy(r, ctx->result + 8, sizeof(r), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "read objective");
+  const double n0 = r[3], n1 = r[4], nf = r[5];
+  if (!(n0 > 0) || !(n1 > 0) || !(nf > 0)) return set_err(ctx, LBM_EINVAL, "objective planes hold no fluid cell");
+  *J = (1.0 / 3.0) * (r[0] / n0 - r[1] / n1) + r[2] / nf;
+  return LBM_OK;
+}
+
+size_t lbm_adjoint_bytes(const lbm_ctx *ctx) {
+  if (!ctx) return 0;
+  return (size_t)ctx->q * ctx->N * compute_bytes(ctx->p.storage);
+}
+
+int lbm_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lambda) {
+  if (!ctx || !planes || !lambda) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
+  if (planes[0] < 0 || planes[0] >= ctx->p.nx || planes[1] < 0 || planes[1] >= ctx->p.nx)
+    return set_err(ctx, LBM_EINVAL, "objective planes outside the domain");
+  return dev_adjoint_seed(ctx, planes, lambda);
+}
+
+int lbm_adjoint_step(lbm_ctx *ctx, void *lambda, void *grad_phi) {
+  if (!ctx || !lambda || !grad_phi) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
+  if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
+  return dev_adjoint_step(ctx, lambda, grad_phi);
+}
+
+int lbm_adjoint_to_natural(lbm_ctx *ctx, const void *lambda, void *natural) {
+  if (!ctx || !lambda || !natural) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
+  return dev_layout_to_natural(ctx, lambda, natural);
+}
+
+int lbm_adjoint_from_natural(lbm_ctx *ctx, const void *natural, void *lambda) {
+  if (!ctx || !lambda || !natural) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
+  return dev_layout_from_natural(ctx, natural, lambda);
+}
+
+long long lbm_revolve_cost(int T, int nsnap) { return revolve_cost(T, nsnap); }
+
+int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
+                 void *grad_phi, double *J, long long *nforward) {
+  if (!ctx) return LBM_EINVAL;
+  if (T < 1 || nsnap < 1 || !snapshots || !lambda || !grad_phi || !planes)
+    return set_err(ctx, LBM_EINVAL, "gradient needs T >= 1, nsnap >= 1 and non-null buffers");
+  if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
+  const size_t sb = lbm_state_bytes(ctx);
+  auto slot = [&](int k) { return (char *)snapshots + (size_t)k * sb; };
+  long long fwd = 0;
+  int rc = lbm_save_state(ctx, slot(0));
+  if (rc != LBM_OK) return rc;
+  const long long step0 = ctx->steps;
+  // forward sweep to T for the objective and the seed
+  if ((rc = lbm_step(ctx, T)) != LBM_OK) return rc;
+  fwd += T;
+  double Jv = 0.0;
+  if ((rc = lbm_objective(ctx, planes, &Jv)) != LBM_OK) return rc;
+  if ((rc = lbm_adjoint_seed(ctx, planes, lambda)) != LBM_OK) return rc;
+  if ((rc = dev_fill(ctx, grad_phi, (size_t)ctx->N * compute_bytes(ctx->p.storage))) != LBM_OK) return rc;
+  // reverse sweep along the binomial schedule
+  const std::vector<Action> acts = revolve_schedule(T, nsnap);
+  long long have = -1;  // step index held by the context, relative to step0 (-1: not a scheduled state)
+  for (const Action &a : acts) {
+    switch (a.kind) {
+      case ACT_RESTORE:
+        if (have != a.step) {
+          if ((rc = lbm_load_state(ctx, slot(a.arg))) != LBM_OK) return rc;
+          have = a.step;
+        }
+        break;
+      case ACT_ADVANCE:
+        if ((rc = lbm_step(ctx, a.arg)) != LBM_OK) return rc;
+        fwd += a.arg;
+        have += a.arg;
+        break;
+      case ACT_STORE:
+        if ((rc = lbm_save_state(ctx, slot(a.arg))) != LBM_OK) return rc;
+        break;
+      case ACT_REVERSE:
+        if (ctx->steps != step0 + a.arg) return set_err(ctx, LBM_EINVAL, "internal: schedule out of step");
+        if ((rc = dev_adjoint_step(ctx, lambda, grad_phi)) != LBM_OK) return rc;
+        break;
+    }
+  }
+  if ((rc = lbm_load_state(ctx, slot(0))) != LBM_OK) return rc;
+  if ((rc = sync_and_check(ctx)) != LBM_OK) return rc;
+  if (J) *J = Jv;
+  if (nforward) *nforward = fwd;
+  return LBM_OK;
+}
+
+int lbm_wall_count(const lbm_ctx *ctx) { return ctx ? ctx->nwall : -1; }
+
+int lbm_wall_records(lbm_ctx *ctx, int *cell, int *ref, double *normal, double *utau, double *G, double *tau) {
+  if (!ctx) return LBM_EINVAL;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  const size_t nw = (size_t)ctx->nwall;
+  if (nw == 0) return LBM_OK;
+  std::vector<double> rec(nw * WR_COUNT);
+  if ((e = hipMemcpy(rec.data(), ctx->wrec, rec.size() * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(ctx, e, "read wall records");
+  if (cell && (e = hipMemcpy(cell, ctx->wcell, nw * sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(ctx, e, "read wall cells");
+  if (ref && (e = hipMemcpy(ref, ctx->wref, nw * sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(ctx, e, "read wall references");
+  for (size_t k = 0; k < nw; ++k) {
+    if (normal)
+      for (int a = 0; a < 3; ++a) normal[3 * k + a] = rec[(WR_NX + a) * nw + k];
+    if (utau) utau[k] = rec[WR_UTAU * nw + k];
+    if (G) G[k] = rec[WR_G * nw + k];
+    if (tau) tau[k] = rec[WR_TAU * nw + k];
+  }
+  return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err.c_str() : g_static_error.c_str(); }
+
+void lbm_free(lbm_ctx *ctx) { delete ctx; }
+
+}  // extern "C"

@@ -1,0 +1,377 @@
+// Discrete adjoint (reverse mode) of the forward step of kernels.hip, for
+// gradients of a terminal objective with respect to the per-cell porosity of
+// the homogenized velocity (Sec. 2.2, Eq. (12)).
+//
+// An adjoint field lam has the state's in-memory AA layout.  One reverse step
+// at parity n is the transpose of the forward step: for each cell, the
+// adjoints of its post-collision outputs are read from the slots the forward
+// step wrote (its write set), pushed back through the collision by the
+// hand-written vector-Jacobian product below, and stored into the slots the
+// forward step read (its read set).  Read set = write set per cell, so the
+// reverse step is in place and every cell is independent, exactly like the
+// forward step; streaming and bounce-back need no code of their own.
+// The Frobenius norm of the stress has no derivative at zero; its adjoint is
+// taken as 0 there.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "lattice.h"
+
+namespace lbmk {
+
+constexpr int ATX = 64, ATY = 4, ABLOCK = ATX * ATY;
+
+struct ATiles {
+  unsigned nblocks;
+  int gx, gy;
+};
+static ATiles atiles_of(const KArgs &k) {
+  ATiles t;
+  t.gx = (k.nx + ATX - 1) / ATX;
+  t.gy = (k.ny + ATY - 1) / ATY;
+  t.nblocks = (unsigned)t.gx * (unsigned)t.gy * (unsigned)k.nz;
+  return t;
+}
+__device__ __forceinline__ bool atile_xyz(const KArgs &k, ATiles t, int &x, int &y, int &z) {
+  const unsigned L = xcd_remap(blockIdx.x, t.nblocks);
+  const int tx = (int)(L % (unsigned)t.gx);
+  const unsigned r = L / (unsigned)t.gx;
+  const int ty = (int)(r % (unsigned)t.gy);
+  z = (int)(r / (unsigned)t.gy);
+  x = tx * ATX + (int)(threadIdx.x & (ATX - 1));
+  y = ty * ATY + (int)(threadIdx.x / ATX);
+  return x < k.nx && y < k.ny;
+}
+
+// Vector-Jacobian product of the bulk collision: given the populations g
+// (deviations) and the adjoints mu of the outputs, returns the adjoints of
+// the inputs in gb and the porosity adjoint.
+template <int Q, typename R, bool POROUS>
+__device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi, const KArgs &k, R gb[Q]) {
+  // ---- forward recomputation
+  R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+  R mxx = R(0), myy = R(0), mzz = R(0), mxy = R(0), mxz = R(0), myz = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+    drho += g[i];
+    acc(jx, cx, g[i]);
+    acc(jy, cy, g[i]);
+    acc(jz, cz, g[i]);
+    acc(mxx, cx * cx, g[i]);
+    acc(myy, cy * cy, g[i]);
+    acc(mzz, cz * cz, g[i]);
+    acc(mxy, cx * cy, g[i]);
+    acc(mxz, cx * cz, g[i]);
+    acc(myz, cy * cz, g[i]);
+  }
+  const R rho = R(1) + drho;
+  const R ir = R(1) / rho;
+  const R Fx = R(k.F[0]), Fy = R(k.F[1]), Fz = R(k.F[2]);
+  const R mx = jx + R(0.5) * Fx, my = jy + R(0.5) * Fy, mz = jz + R(0.5) * Fz;
+  const R ux = mx * ir, uy = my * ir, uz = mz * ir;
+  const R cs2 = R(1.0 / 3.0);
+  const R pxx = mxx - drho * cs2 - rho * ux * ux;
+  const R pyy = myy - drho * cs2 - rho * uy * uy;
+  const R pzz = mzz - drho * cs2 - rho * uz * uz;
+  const R pxy = mxy - rho * ux * uy;
+  const R pxz = mxz - rho * ux * uz;
+  const R pyz = myz - rho * uy * uz;
+  const R pn = sqrt(pxx * pxx + pyy * pyy + pzz * pzz + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz));
+  const R tau0 = R(k.tau0), smag = R(k.smag);
+  const R sA = sqrt(tau0 * tau0 + smag * pn * ir);
+  const R tau = R(0.5) * (tau0 + sA);
+  const R om = R(1) / tau;
+  const R c1 = R(1) - om, c2 = R(1) - R(0.5) * om;
+  const R uu = ux * ux + uy * uy + uz * uz;
+  const R vx = POROUS ? phi * ux : ux, vy = POROUS ? phi * uy : uy, vz = POROUS ? phi * uz : uz;
+  const R vv = vx * vx + vy * vy + vz * vz;
+  const R uF = ux * Fx + uy * Fy + uz * Fz;
+
+  // ---- reverse through the output combination
+  R c1b = R(0), c2b = R(0);
+  R au0 = R(0), au1 = R(0), aux = R(0), auy = R(0), auz = R(0);  // from gu (equilibrium at u)
+  R av0 = R(0), av1 = R(0), avx = R(0), avy = R(0), avz = R(0);  // from gv (equilibrium at v)
+  R b0 = R(0), bx = R(0), by = R(0), bz = R(0);                  // from the Guo term
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+    const R w = R(Lat<Q>::w(i));
+    const R cu = dot3(cx, cy, cz, ux, uy, uz);
+    const R cF = dot3(cx, cy, cz, Fx, Fy, Fz);
+    const R gu = w * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+    const R guo = w * (R(3) * (cF - uF) + R(9) * cu * cF);
+    const R m = mu[i];
+    c1b += m * (g[i] - gu);
+    c2b += m * guo;
+    gb[i] = c1 * m;
+    // adjoint of gu: -c1 m ; of gv: m ; of guo: c2 m (each times w folded below)
+    const R su = -c1 * m * w;
+    au0 += su;
+    au1 += su * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+    const R tu = su * (R(3) + R(9) * cu);
+    acc(aux, cx, tu);
+    acc(auy, cy, tu);
+    acc(auz, cz, tu);
+    const R sv = m * w;
+    if (POROUS) {
+      const R cv = dot3(cx, cy, cz, vx, vy, vz);
+      av0 += sv;
+      av1 += sv * (R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv);
+      const R tv = sv * (R(3) + R(9) * cv);
+      acc(avx, cx, tv);
+      acc(avy, cy, tv);
+      acc(avz, cz, tv);
+    } else {
+      // v = u: accumulate into the u terms directly
+      au0 += sv;
+      au1 += sv * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+      const R tv = sv * (R(3) + R(9) * cu);
+      acc(aux, cx, tv);
+      acc(auy, cy, tv);
+      acc(auz, cz, tv);
+    }
+    const R sg = c2 * m * w;
+    b0 += sg;
+    const R tg = sg * R(9) * cF;
+    acc(bx, cx, tg);
+    acc(by, cy, tg);
+    acc(bz, cz, tg);
+  }
+  // equilibria: d/d drho = w, d/d rho = w (3cv + 9/2 cv^2 - 3/2 v.v), d/dv = w rho (3c + 9 (c.v) c - 3 v)
+  R drhob = au0;
+  R rhob = au1;
+  R uxb = rho * aux - R(3) * rho * ux * au0;
+  R uyb = rho * auy - R(3) * rho * uy * au0;
+  R uzb = rho * auz - R(3) * rho * uz * au0;
+  R phib = R(0);
+  if (POROUS) {
+    drhob += av0;
+    rhob += av1;
+    const R vxb = rho * avx - R(3) * rho * vx * av0;
+    const R vyb = rho * avy - R(3) * rho * vy * av0;
+    const R vzb = rho * avz - R(3) * rho * vz * av0;
+    uxb += phi * vxb;
+    uyb += phi * vyb;
+    uzb += phi * vzb;
+    phib = vxb * ux + vyb * uy + vzb * uz;
+  }
+  // Guo term: d/du = w (-3 F + 9 (c.F) c)
+  uxb += bx - R(3) * Fx * b0;
+  uyb += by - R(3) * Fy * b0;
+  uzb += bz - R(3) * Fz * b0;
+  // relaxation rate: om = 1/tau, tau = (tau0 + sqrt(A))/2, A = tau0^2 + smag pn / rho
+  const R omb = -c1b - R(0.5) * c2b;
+  const R taub = -omb * om * om;
+  const R Ab = R(0.5) * taub / (R(2) * sA);
+  const R pnb = Ab * smag * ir;
+  R irb = Ab * smag * pn;
+  const R q = pn > R(0) ? pnb / pn : R(0);  // d pn / d P_ab = P_ab / pn (off-diagonals twice)
+  const R pxxb = q * pxx, pyyb = q * pyy, pzzb = q * pzz;
+  const R pxyb = R(2) * q * pxy, pxzb = R(2) * q * pxz, pyzb = R(2) * q * pyz;
+  drhob -= cs2 * (pxxb + pyyb + pzzb);
+  rhob -= ux * ux * pxxb + uy * uy * pyyb + uz * uz * pzzb + ux * uy * pxyb + ux * uz * pxzb + uy * uz * pyzb;
+  uxb -= rho * (R(2) * ux * pxxb + uy * pxyb + uz * pxzb);
+  uyb -= rho * (R(2) * uy * pyyb + ux * pxyb + uz * pyzb);
+  uzb -= rho * (R(2) * uz * pzzb + ux * pxzb + uy * pyzb);
+  // u = m / rho
+  const R mxb = uxb * ir, myb = uyb * ir, mzb = uzb * ir;
+  irb += uxb * mx + uyb * my + uzb * mz;
+  rhob -= irb * ir * ir;
+  drhob += rhob;
+  // moments -> populations
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+    R s = drhob;
+    acc(s, cx, mxb);
+    acc(s, cy, myb);
+    acc(s, cz, mzb);
+    acc(s, cx * cx, pxxb);
+    acc(s, cy * cy, pyyb);
+    acc(s, cz * cz, pzzb);
+    acc(s, cx * cy, pxyb);
+    acc(s, cx * cz, pxzb);
+    acc(s, cy * cz, pyzb);
+    gb[i] += s;
+  }
+  return phib;
+}
+
+template <int Q, typename S, bool ODD, bool POROUS, bool SOLID>
+__global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                    typename Store<S>::R *__restrict__ lam,
+                                                    const typename Store<S>::R *__restrict__ phi,
+                                                    typename Store<S>::R *__restrict__ grad, KArgs k, ATiles t) {
+  using R = typename Store<S>::R;
+  int x, y, z;
+  if (!atile_xyz(k, t, x, y, z)) return;
+  const Nb n = make_nb(x, y, z, k);
+  const uint8_t fl = flags[n.cell];
+  if (!(fl & FL_FLUID)) return;
+  unsigned sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  const size_t N = (size_t)k.N;
+  R mu[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) mu[i] = lam[write_slot<Q, ODD>(n, sm, i, N)];
+  R gb[Q];
+  if (fl & FL_LID) {
+    // the lid output does not depend on the state
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gb[i] = R(0);
+  } else {
+    if (x >= k.fringe_start) {
+      const R l = static_cast<const R *>(k.lam)[x];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) mu[i] *= (R(1) - l);
+    }
+    R g[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+    const R ph = POROUS ? phi[n.cell] : R(1);
+    const R phib = collide_bulk_vjp<Q, R, POROUS>(g, mu, ph, k, gb);
+    if (POROUS) grad[n.cell] += phib;
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) lam[read_slot<Q, ODD>(n, sm, i, N)] = gb[i];
+}
+
+// lam = dJ/df of the current state for the terminal objective
+// J = c_s^2 (<rho>_{x=p0} - <rho>_{x=p1}) + <rho |u|^2 / 2>; the fluid-cell
+// counts come from the objective reduction already in cnt[0..2].
+template <int Q, typename S, bool ODD, bool SOLID>
+__global__ __launch_bounds__(ABLOCK) void k_seed(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                 typename Store<S>::R *__restrict__ lam, KArgs k, ATiles t, int p0,
+                                                 int p1, const double *__restrict__ cnt) {
+  using R = typename Store<S>::R;
+  int x, y, z;
+  if (!atile_xyz(k, t, x, y, z)) return;
+  const Nb n = make_nb(x, y, z, k);
+  const uint8_t fl = flags[n.cell];
+  if (!(fl & FL_FLUID)) return;
+  unsigned sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  const size_t N = (size_t)k.N;
+  double g[Q];
+  double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    g[i] = (double)Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+    drho += g[i];
+    acc(jx, Lat<Q>::c(i, 0), g[i]);
+    acc(jy, Lat<Q>::c(i, 1), g[i]);
+    acc(jz, Lat<Q>::c(i, 2), g[i]);
+  }
+  const double rho = 1.0 + drho;
+  const double ux = (jx + 0.5 * k.F[0]) / rho, uy = (jy + 0.5 * k.F[1]) / rho, uz = (jz + 0.5 * k.F[2]) / rho;
+  const double uu = ux * ux + uy * uy + uz * uz;
+  double base = 0.0;
+  if (x == p0) base += 1.0 / (3.0 * cnt[0]);
+  if (x == p1) base -= 1.0 / (3.0 * cnt[1]);
+  const double inf = 1.0 / cnt[2];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double cu = dot3(Lat<Q>::c(i, 0), Lat<Q>::c(i, 1), Lat<Q>::c(i, 2), ux, uy, uz);
+    lam[read_slot<Q, ODD>(n, sm, i, N)] = (R)(base + (cu - 0.5 * uu) * inf);
+  }
+}
+
+// Natural order [q][N] <-> in-memory layout of the current parity.
+template <int Q, bool ODD, bool SOLID, bool TO_NATURAL, typename R>
+__global__ __launch_bounds__(ABLOCK) void k_relayout(const uint8_t *__restrict__ flags, const R *__restrict__ src,
+                                                     R *__restrict__ dst, KArgs k, ATiles t) {
+  int x, y, z;
+  if (!atile_xyz(k, t, x, y, z)) return;
+  const Nb n = make_nb(x, y, z, k);
+  const uint8_t fl = flags[n.cell];
+  const size_t N = (size_t)k.N;
+  if (!(fl & FL_FLUID)) {
+    if (TO_NATURAL)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) dst[(size_t)i * N + n.cell] = R(0);
+    return;
+  }
+  unsigned sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const size_t s = read_slot<Q, ODD>(n, sm, i, N);
+    if (TO_NATURAL) dst[(size_t)i * N + n.cell] = src[s];
+    else dst[s] = src[(size_t)i * N + n.cell];
+  }
+}
+
+// ---------------------------------------------------------------------------
+static int check(lbm_ctx *ctx, const char *what) {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LBM_OK : hip_fail(ctx, e, what);
+}
+
+template <typename F>
+static int adispatch(lbm_ctx *ctx, F &&f) {
+  const bool odd = (ctx->steps & 1) != 0;
+  auto by_geo = [&]<int Q, typename S>() {
+    if (odd) return ctx->has_solid ? f.template operator()<Q, S, true, true>() : f.template operator()<Q, S, true, false>();
+    return ctx->has_solid ? f.template operator()<Q, S, false, true>() : f.template operator()<Q, S, false, false>();
+  };
+  if (ctx->q == 19) {
+    if (ctx->p.storage == LBM_F64) return by_geo.template operator()<19, double>();
+    if (ctx->p.storage == LBM_F32DEV) return by_geo.template operator()<19, float>();
+    return by_geo.template operator()<19, _Float16>();
+  }
+  if (ctx->p.storage == LBM_F64) return by_geo.template operator()<27, double>();
+  if (ctx->p.storage == LBM_F32DEV) return by_geo.template operator()<27, float>();
+  return by_geo.template operator()<27, _Float16>();
+}
+
+int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv) {
+  const ATiles t = atiles_of(ctx->ka);
+  return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
+    using R = typename Store<S>::R;
+    R *lam = (R *)lamv;
+    R *grad = (R *)gradv;
+    const R *phi = (const R *)ctx->phi;
+    if (ctx->porous)
+      k_adjoint<Q, S, ODD, true, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, lam,
+                                                                              phi, grad, ctx->ka, t);
+    else
+      k_adjoint<Q, S, ODD, false, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags,
+                                                                               lam, phi, grad, ctx->ka, t);
+    return check(ctx, "k_adjoint");
+  });
+}
+
+int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lamv) {
+  int rc = dev_objective(ctx, planes);  // fills the fluid-cell counts
+  if (rc != LBM_OK) return rc;
+  const ATiles t = atiles_of(ctx->ka);
+  return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
+    using R = typename Store<S>::R;
+    k_seed<Q, S, ODD, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, (R *)lamv, ctx->ka,
+                                                                   t, planes[0], planes[1], ctx->result + 8 + 3);
+    return check(ctx, "k_seed");
+  });
+}
+
+int dev_layout_to_natural(lbm_ctx *ctx, const void *lamv, void *natv) {
+  const ATiles t = atiles_of(ctx->ka);
+  return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
+    using R = typename Store<S>::R;
+    k_relayout<Q, ODD, SOLID, true, R><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, (const R *)lamv, (R *)natv,
+                                                                           ctx->ka, t);
+    return check(ctx, "k_relayout");
+  });
+}
+
+int dev_layout_from_natural(lbm_ctx *ctx, const void *natv, void *lamv) {
+  const ATiles t = atiles_of(ctx->ka);
+  return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
+    using R = typename Store<S>::R;
+    k_relayout<Q, ODD, SOLID, false, R><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, (const R *)natv, (R *)lamv,
+                                                                            ctx->ka, t);
+    return check(ctx, "k_relayout");
+  });
+}
+
+}  // namespace lbmk

@@ -1,0 +1,127 @@
+// Internal declarations shared by the host side (abi.cpp, geometry.cpp,
+// revolve.cpp) and the device side (kernels.hip, adjoint.hip) of the
+// MI355X LBM-LES library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+
+namespace lbmk {
+
+// Per-cell flag byte.  0 = solid (no state).
+enum : uint8_t {
+  FL_FLUID = 1,  // carries populations
+  FL_NEAR = 2,   // at least one link to a solid cell or outside a non-periodic axis
+  FL_WALL = 4,   // wall-modeled cell (reconstruction collision, wall kernel)
+  FL_LID = 8     // top-lid cell (inflow equilibrium)
+};
+
+// Number of doubles per wall record (structure of arrays, nwall entries each).
+enum {
+  WR_NX = 0, WR_NY, WR_NZ,  // unit normal (static)
+  WR_YB, WR_YR,             // wall distance of the wall cell and of its reference cell (static)
+  WR_TX, WR_TY, WR_TZ,      // unit tangent of the reference velocity (per step)
+  WR_UTAN,                  // modeled tangential speed u_tau * u+ at the wall cell (per step)
+  WR_G,                     // modeled strain magnitude |S| (per step)
+  WR_TAU,                   // effective relaxation time of the wall cell (per step)
+  WR_UTAU,                  // friction velocity (per step)
+  WR_COUNT
+};
+
+// Constants every kernel needs, passed by value.
+struct KArgs {
+  int nx, ny, nz, N;
+  int per[3];
+  double tau0;
+  double smag;  // 18 sqrt(2) C_S^2: coefficient of |Pi|/rho under the root of tau_eff
+  double cs2;   // C_S^2
+  double nu;    // (tau0 - 1/2)/3
+  double F[3];
+  double kappa, E;
+  int fringe_start;  // first fringe plane in x (nx when there is no fringe)
+  double u_lid;      // lid velocity (x component)
+  const void *uin;   // [nz] fringe inflow profile, compute type
+  const void *lam;   // [nx] fringe blend weight, compute type (0 before the fringe)
+};
+
+}  // namespace lbmk
+
+struct lbm_ctx {
+  lbm_params p{};
+  int q = 0;
+  long long N = 0;
+  size_t elem = 0;  // bytes per stored population value
+  hipStream_t stream = nullptr;
+  lbmk::KArgs ka{};
+  bool porous = false;
+  bool has_solid = false;  // some cell has a solid link (bounce-back needed)
+  bool has_lid = false;
+  // device regions carved from the caller's workspace
+  void *pop = nullptr;        // [q][N] stored deviations
+  uint8_t *flags = nullptr;   // [N]
+  void *phi = nullptr;        // [N] compute type, porous only
+  void *tables = nullptr;     // [nz] inflow + [nx] fringe weights, compute type
+  int nwall = 0;
+  int *wcell = nullptr;       // [nwall]
+  int *wref = nullptr;        // [nwall]
+  double *wrec = nullptr;     // [WR_COUNT][nwall]
+  double *partial = nullptr;  // reduction partials
+  int npartial = 0;           // number of partial slots (blocks) available
+  double *result = nullptr;   // [8] finalised reductions
+  int *errflag = nullptr;     // [1] bit 0 non-finite, bit 1 Newton
+  long long steps = 0;
+  std::string err;
+};
+
+namespace lbmk {
+
+// ---- host geometry (geometry.cpp) ------------------------------------------
+struct Geometry {
+  std::vector<uint8_t> flags;  // [N]
+  std::vector<int> wcell, wref;
+  std::vector<double> wnorm;   // [3 * nwall]
+  bool has_solid = false;
+  bool has_lid = false;
+};
+// Builds flags and the wall list; returns LBM_OK or an error code with msg.
+int build_geometry(const lbm_params &p, const uint8_t *mask, Geometry &g, std::string &msg);
+// Counts wall-modeled cells only (for the workspace size).
+long long count_wall_cells(const lbm_params &p, const uint8_t *mask);
+// Voxel wall distance of cell c: nearest solid unit cube within two cells.
+double voxel_distance(const lbm_params &p, const uint8_t *mask, long long c);
+
+// ---- binomial checkpointing (revolve.cpp) ----------------------------------
+enum ActionKind { ACT_ADVANCE, ACT_STORE, ACT_RESTORE, ACT_REVERSE };
+struct Action {
+  ActionKind kind;
+  int arg;   // ADVANCE: number of steps; STORE/RESTORE: slot; REVERSE: step index
+  int step;  // step index of the state before the action
+};
+long long revolve_cost(int T, int nsnap);
+std::vector<Action> revolve_schedule(int T, int nsnap);
+
+// ---- device launchers (kernels.hip, adjoint.hip) ---------------------------
+// Each returns LBM_OK or LBM_EHIP (with ctx->err set).
+int dev_init_equilibrium(lbm_ctx *ctx, const double *rho0, const double *u0);
+int dev_step(lbm_ctx *ctx);  // one time step at parity ctx->steps & 1
+int dev_moments(lbm_ctx *ctx, void *rho, void *u);
+int dev_reduce_diag(lbm_ctx *ctx);  // writes result[0..3]
+int dev_objective(lbm_ctx *ctx, const int planes[2]);  // writes result[4]
+int dev_export(lbm_ctx *ctx, void *f);
+int dev_import(lbm_ctx *ctx, const void *f);
+int dev_layout_to_natural(lbm_ctx *ctx, const void *lam, void *nat);
+int dev_layout_from_natural(lbm_ctx *ctx, const void *nat, void *lam);
+int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lam);
+int dev_adjoint_step(lbm_ctx *ctx, void *lam, void *grad);
+int dev_fill(lbm_ctx *ctx, void *ptr, size_t bytes);  // zero fill with a kernel
+int dev_write_header(lbm_ctx *ctx, void *dst);
+
+int hip_fail(lbm_ctx *ctx, hipError_t e, const char *what);
+
+}  // namespace lbmk

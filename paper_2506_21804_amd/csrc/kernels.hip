@@ -1,0 +1,741 @@
+// Forward kernels of the wall-modeled LBM-LES step for gfx950 (wave64).
+//
+// One time step at parity p is three launches on the context's stream:
+//   K1 k_wall_prepass  one thread per wall cell: friction velocity from the
+//                      Spalding law (Sec. 2.2.1, Eq. (17)) by Newton in FP64
+//                      at the reference cell, modeled tangential velocity and
+//                      strain; reads only, so it must finish before K2/K3;
+//   K2 k_bulk          one thread per cell (64x4 tiles): AA gather, BGK
+//                      collision with the Smagorinsky tau_eff (Eqs. (3),(4),
+//                      (14)), homogenized velocity (Eq. (12)), Guo forcing,
+//                      fringe/lid, AA scatter; skips wall cells;
+//   K3 k_wall          one thread per wall cell: sigma = 0 reconstruction
+//                      (equilibrium at the modeled velocity plus the
+//                      non-equilibrium of Eq. (10) built from the wall-law
+//                      strain), then the same scatter.
+// K2 and K3 touch disjoint slot sets (AA read set = write set per cell).
+// The path is bound by HBM traffic: q loads and q stores per cell plus the
+// flag byte, no contraction, so no MFMA.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+#include "lattice.h"
+
+namespace lbmk {
+
+constexpr int TX = 64;  // tile width in x (one wavefront)
+constexpr int TY = 4;   // tile height in y (four wavefronts per block)
+constexpr int BLOCK = TX * TY;
+
+struct Tiles {
+  unsigned nblocks;
+  int gx, gy;
+};
+static Tiles tiles_of(const KArgs &k) {
+  Tiles t;
+  t.gx = (k.nx + TX - 1) / TX;
+  t.gy = (k.ny + TY - 1) / TY;
+  t.nblocks = (unsigned)t.gx * (unsigned)t.gy * (unsigned)k.nz;
+  return t;
+}
+
+// Cell coordinates of this thread in the tiled grid; false when outside.
+__device__ __forceinline__ bool tile_xyz(const KArgs &k, Tiles t, unsigned block, int &x, int &y, int &z) {
+  const unsigned L = xcd_remap(block, t.nblocks);
+  const int tx = (int)(L % (unsigned)t.gx);
+  const unsigned r = L / (unsigned)t.gx;
+  const int ty = (int)(r % (unsigned)t.gy);
+  z = (int)(r / (unsigned)t.gy);
+  x = tx * TX + (int)(threadIdx.x & (TX - 1));
+  y = ty * TY + (int)(threadIdx.x / TX);
+  return x < k.nx && y < k.ny;
+}
+
+template <typename R>
+__device__ __forceinline__ bool finite_pos(R v) {
+  return v > R(0) && v < R(INFINITY);
+}
+
+// Deviation of the second-order equilibrium from the rest weight:
+// f^eq_i(rho, v) - w_i = w_i [drho + rho (3 c.v + 9/2 (c.v)^2 - 3/2 v.v)].
+template <typename R>
+__device__ __forceinline__ R geq_dev(R w, R drho, R rho, R cv, R vv) {
+  return w * (drho + rho * (R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv));
+}
+
+// Fringe blend toward the inflow equilibrium and lid equilibrium (open
+// boundary of the urban setup).
+template <int Q, typename R>
+__device__ __forceinline__ void fringe_blend(R g[Q], int x, int z, const KArgs &k) {
+  if (x < k.fringe_start) return;
+  const R lam = static_cast<const R *>(k.lam)[x];
+  const R U = static_cast<const R *>(k.uin)[z];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R w = R(Lat<Q>::w(i));
+    R cu = R(0);
+    acc(cu, Lat<Q>::c(i, 0), U);
+    const R ge = w * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * U * U);
+    g[i] = (R(1) - lam) * g[i] + lam * ge;
+  }
+}
+
+template <int Q, typename R>
+__device__ __forceinline__ void lid_equilibrium(R g[Q], const KArgs &k) {
+  const R U = R(k.u_lid);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R w = R(Lat<Q>::w(i));
+    R cu = R(0);
+    acc(cu, Lat<Q>::c(i, 0), U);
+    g[i] = w * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * U * U);
+  }
+}
+
+// Bulk collision on deviations g (sigma = 1): BGK with tau_eff from the
+// non-equilibrium stress, homogenized velocity u_hat = phi u, Guo forcing.
+// Returns false for a non-finite or non-positive density.
+template <int Q, typename R, bool POROUS>
+__device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
+  R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+  R mxx = R(0), myy = R(0), mzz = R(0), mxy = R(0), mxz = R(0), myz = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+    drho += g[i];
+    acc(jx, cx, g[i]);
+    acc(jy, cy, g[i]);
+    acc(jz, cz, g[i]);
+    acc(mxx, cx * cx, g[i]);
+    acc(myy, cy * cy, g[i]);
+    acc(mzz, cz * cz, g[i]);
+    acc(mxy, cx * cy, g[i]);
+    acc(mxz, cx * cz, g[i]);
+    acc(myz, cy * cz, g[i]);
+  }
+  const R rho = R(1) + drho;
+  const bool ok = finite_pos(rho);
+  const R ir = R(1) / rho;
+  const R Fx = R(k.F[0]), Fy = R(k.F[1]), Fz = R(k.F[2]);
+  const R ux = (jx + R(0.5) * Fx) * ir, uy = (jy + R(0.5) * Fy) * ir, uz = (jz + R(0.5) * Fz) * ir;
+  // Pi^neq = sum c c (f - f^eq(rho,u)) = M2(g) - drho c_s^2 I - rho u u
+  const R cs2 = R(1.0 / 3.0);
+  const R pxx = mxx - drho * cs2 - rho * ux * ux;
+  const R pyy = myy - drho * cs2 - rho * uy * uy;
+  const R pzz = mzz - drho * cs2 - rho * uz * uz;
+  const R pxy = mxy - rho * ux * uy;
+  const R pxz = mxz - rho * ux * uz;
+  const R pyz = myz - rho * uy * uz;
+  const R pn = sqrt(pxx * pxx + pyy * pyy + pzz * pzz + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz));
+  const R tau0 = R(k.tau0);
+  const R tau = R(0.5) * (tau0 + sqrt(tau0 * tau0 + R(k.smag) * pn * ir));
+  const R om = R(1) / tau;
+  const R c1 = R(1) - om, c2 = R(1) - R(0.5) * om;
+  const R uu = ux * ux + uy * uy + uz * uz;
+  const R vx = POROUS ? phi * ux : ux, vy = POROUS ? phi * uy : uy, vz = POROUS ? phi * uz : uz;
+  const R vv = vx * vx + vy * vy + vz * vz;
+  const R uF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+    const R w = R(Lat<Q>::w(i));
+    const R cu = dot3(cx, cy, cz, ux, uy, uz);
+    const R gu = geq_dev(w, drho, rho, cu, uu);
+    R gv = gu;
+    if (POROUS) gv = geq_dev(w, drho, rho, dot3(cx, cy, cz, vx, vy, vz), vv);
+    const R cF = dot3(cx, cy, cz, Fx, Fy, Fz);
+    const R guo = w * (R(3) * (cF - uF) + R(9) * cu * cF);
+    g[i] = gv + c1 * (g[i] - gu) + c2 * guo;
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// K2: fused gather / collide / scatter over all non-wall fluid cells.
+// ---------------------------------------------------------------------------
+template <int Q, typename S, bool ODD, bool POROUS, bool SOLID>
+__global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                const typename Store<S>::R *__restrict__ phi, KArgs k,
+                                                Tiles t, int *__restrict__ errflag) {
+  using R = typename Store<S>::R;
+  int x, y, z;
+  if (!tile_xyz(k, t, blockIdx.x, x, y, z)) return;
+  const Nb n = make_nb(x, y, z, k);
+  const uint8_t fl = flags[n.cell];
+  if (!(fl & FL_FLUID) || (fl & FL_WALL)) return;
+  unsigned sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  const size_t N = (size_t)k.N;
+  R g[Q];
+  if (fl & FL_LID) {
+    lid_equilibrium<Q, R>(g, k);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+    const R ph = POROUS ? phi[n.cell] : R(1);
+    if (!collide_bulk<Q, R, POROUS>(g, ph, k)) atomicOr(errflag, 1);
+  }
+  fringe_blend<Q, R>(g, x, z, k);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) Store<S>::st(pop + write_slot<Q, ODD>(n, sm, i, N), g[i]);
+}
+
+// ---------------------------------------------------------------------------
+// K1: wall prepass (FP64).  Spalding function g(u+) = u+ + R(kappa u+)/E
+// with R(a) = exp(a) - 1 - a - a^2/2 - a^3/6, and its derivative; below
+// a = 1/2 the remainders are summed as power series (no cancellation).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double series_tail(double a, int from) {
+  double term = 1.0;
+  for (int n = 1; n <= from; ++n) term *= a / n;
+  double sum = 0.0;
+  for (int n = from; n < from + 24; ++n) {
+    sum += term;
+    term *= a / (n + 1);
+  }
+  return sum;
+}
+__device__ __forceinline__ double spalding(double up, double kappa, double E) {
+  const double a = kappa * up;
+  const double r = (a >= 0.0 && a < 0.5) ? series_tail(a, 4) : exp(a) - 1.0 - a - 0.5 * a * a - a * a * a / 6.0;
+  return up + r / E;
+}
+__device__ __forceinline__ double spalding_d(double up, double kappa, double E) {
+  const double a = kappa * up;
+  const double r = (a >= 0.0 && a < 0.5) ? series_tail(a, 3) : exp(a) - 1.0 - a - 0.5 * a * a;
+  return 1.0 + kappa * r / E;
+}
+
+template <int Q, typename S, bool ODD>
+__global__ __launch_bounds__(256) void k_wall_prepass(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                      const int *__restrict__ wcell, const int *__restrict__ wref,
+                                                      double *__restrict__ rec, int nwall, KArgs k,
+                                                      int *__restrict__ errflag) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nwall) return;
+  const int r = wref[w];
+  int x, y, z;
+  cell_xyz(r, k, x, y, z);
+  const Nb n = make_nb(x, y, z, k);
+  unsigned sm = 0;
+  if (ODD && (flags[r] & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  const size_t N = (size_t)k.N;
+  double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double gi = (double)Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+    drho += gi;
+    acc(jx, Lat<Q>::c(i, 0), gi);
+    acc(jy, Lat<Q>::c(i, 1), gi);
+    acc(jz, Lat<Q>::c(i, 2), gi);
+  }
+  const double rho = 1.0 + drho;
+  const double ux = (jx + 0.5 * k.F[0]) / rho, uy = (jy + 0.5 * k.F[1]) / rho, uz = (jz + 0.5 * k.F[2]) / rho;
+  const size_t M = (size_t)nwall;
+  const double nx = rec[WR_NX * M + w], ny = rec[WR_NY * M + w], nz = rec[WR_NZ * M + w];
+  const double un = ux * nx + uy * ny + uz * nz;
+  const double tx = ux - un * nx, ty = uy - un * ny, tz = uz - un * nz;
+  const double U = sqrt(tx * tx + ty * ty + tz * tz);
+  const double nu = k.nu, kap = k.kappa, E = k.E;
+  double utau = 0.0, utan = 0.0, G = 0.0, tau = 3.0 * nu + 0.5;
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+  bool fail = false;
+  if (U > 1e-300) {
+    const double yr = rec[WR_YR * M + w], yb = rec[WR_YB * M + w];
+    // F(u) = g(U/u) - yr u / nu, convex and decreasing; start at the laminar
+    // value sqrt(nu U / yr) where F >= 0, so Newton climbs monotonically.
+    double ut = sqrt(nu * U / yr);
+    bool conv = false;
+    if (kap * U / ut <= 700.0) {
+      for (int it = 0; it < 100; ++it) {
+        const double xx = U / ut;
+        const double Fv = spalding(xx, kap, E) - yr * ut / nu;
+        const double dF = -spalding_d(xx, kap, E) * U / (ut * ut) - yr / nu;
+        const double st = -Fv / dF;
+        ut += st;
+        if (fabs(st) <= 1e-15 * ut) {
+          conv = true;
+          break;
+        }
+      }
+    }
+    double up = U / ut;
+    if (conv && r != wcell[w]) {
+      // u+ at the wall cell: g(u+) = y+_b by Newton from an upper bound of
+      // the root (g convex increasing: the iterates decrease monotonically).
+      const double ypb = yb * ut / nu;
+      const double K = kap * ypb;
+      double s = fmin(ypb, log(E * ypb + 1.0 + K + 0.5 * K * K + K * K * K / 6.0) / kap);
+      if (yr >= yb) s = fmin(s, U / ut);
+      conv = false;
+      if (kap * s <= 700.0) {
+        for (int it = 0; it < 100; ++it) {
+          const double st = -(spalding(s, kap, E) - ypb) / spalding_d(s, kap, E);
+          s += st;
+          if (fabs(st) <= 1e-15 * fabs(s)) {
+            conv = true;
+            break;
+          }
+        }
+      }
+      up = s;
+    }
+    if (!conv) {
+      fail = true;
+    } else {
+      utau = ut;
+      utan = ut * up;
+      t0 = tx / U;
+      t1 = ty / U;
+      t2 = tz / U;
+      G = 2.0 * ut * ut / (nu + sqrt(nu * nu + 4.0 * k.cs2 * ut * ut));
+      tau = 3.0 * (nu + k.cs2 * G) + 0.5;
+    }
+  }
+  if (fail) atomicOr(errflag, 2);
+  rec[WR_TX * M + w] = t0;
+  rec[WR_TY * M + w] = t1;
+  rec[WR_TZ * M + w] = t2;
+  rec[WR_UTAN * M + w] = utan;
+  rec[WR_G * M + w] = G;
+  rec[WR_TAU * M + w] = tau;
+  rec[WR_UTAU * M + w] = utau;
+}
+
+// ---------------------------------------------------------------------------
+// K3: wall reconstruction (sigma = 0, solid velocity = modeled velocity).
+// ---------------------------------------------------------------------------
+template <int Q, typename S, bool ODD>
+__global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                              const int *__restrict__ wcell, const double *__restrict__ rec,
+                                              int nwall, KArgs k, int *__restrict__ errflag) {
+  using R = typename Store<S>::R;
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nwall) return;
+  const int b = wcell[w];
+  int x, y, z;
+  cell_xyz(b, k, x, y, z);
+  const Nb n = make_nb(x, y, z, k);
+  const unsigned sm = ODD ? solid_mask<Q>(n, flags) : 0u;
+  const size_t N = (size_t)k.N;
+  R g[Q];
+  R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+    drho += g[i];
+    acc(jx, Lat<Q>::c(i, 0), g[i]);
+    acc(jy, Lat<Q>::c(i, 1), g[i]);
+    acc(jz, Lat<Q>::c(i, 2), g[i]);
+  }
+  const R rho = R(1) + drho;
+  if (!finite_pos(rho)) atomicOr(errflag, 1);
+  const R Fx = R(k.F[0]), Fy = R(k.F[1]), Fz = R(k.F[2]);
+  const R ir = R(1) / rho;
+  const R ux = (jx + R(0.5) * Fx) * ir, uy = (jy + R(0.5) * Fy) * ir, uz = (jz + R(0.5) * Fz) * ir;
+  const size_t M = (size_t)nwall;
+  const R nx = R(rec[WR_NX * M + w]), ny = R(rec[WR_NY * M + w]), nz = R(rec[WR_NZ * M + w]);
+  const R tx = R(rec[WR_TX * M + w]), ty = R(rec[WR_TY * M + w]), tz = R(rec[WR_TZ * M + w]);
+  const R utan = R(rec[WR_UTAN * M + w]), G = R(rec[WR_G * M + w]), tau = R(rec[WR_TAU * M + w]);
+  const R un = ux * nx + uy * ny + uz * nz;
+  const R vx = utan * tx + un * nx, vy = utan * ty + un * ny, vz = utan * tz + un * nz;
+  const R vv = vx * vx + vy * vy + vz * vz;
+  const R vF = vx * Fx + vy * Fy + vz * Fz;
+  const R om = R(1) / tau;
+  const R c1 = R(1) - om, c2 = R(1) - R(0.5) * om;
+  const R fd = R(-3) * rho * tau * G;  // f^(1,FD)_i = fd * w_i (c.t)(c.n)
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+    const R w = R(Lat<Q>::w(i));
+    const R cv = dot3(cx, cy, cz, vx, vy, vz);
+    const R ct = dot3(cx, cy, cz, tx, ty, tz);
+    const R cn = dot3(cx, cy, cz, nx, ny, nz);
+    const R cF = dot3(cx, cy, cz, Fx, Fy, Fz);
+    const R ge = geq_dev(w, drho, rho, cv, vv);
+    const R ffd = fd * w * ct * cn;
+    const R guo = w * (R(3) * (cF - vF) + R(9) * cv * cF);
+    g[i] = ge + c1 * ffd + c2 * guo;
+  }
+  fringe_blend<Q, R>(g, x, z, k);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) Store<S>::st(pop + write_slot<Q, ODD>(n, sm, i, N), g[i]);
+}
+
+// ---------------------------------------------------------------------------
+// K0: initial equilibrium; moments; natural-order export / import.
+// ---------------------------------------------------------------------------
+template <int Q, typename S>
+__global__ __launch_bounds__(BLOCK) void k_init_eq(S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                   const double *__restrict__ rho0, const double *__restrict__ u0,
+                                                   KArgs k, Tiles t) {
+  int x, y, z;
+  if (!tile_xyz(k, t, blockIdx.x, x, y, z)) return;
+  const int c = x + k.nx * (y + k.ny * z);
+  const size_t N = (size_t)k.N;
+  if (!(flags[c] & FL_FLUID)) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Store<S>::st(pop + (size_t)i * N + c, typename Store<S>::R(0));
+    return;
+  }
+  const double rho = rho0 ? rho0[c] : 1.0;
+  const double drho = rho0 ? rho0[c] - 1.0 : 0.0;
+  const double ux = u0 ? u0[c] : 0.0, uy = u0 ? u0[N + c] : 0.0, uz = u0 ? u0[2 * N + c] : 0.0;
+  const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double cu = dot3(Lat<Q>::c(i, 0), Lat<Q>::c(i, 1), Lat<Q>::c(i, 2), ux, uy, uz);
+    Store<S>::st(pop + (size_t)i * N + c, (typename Store<S>::R)geq_dev(Lat<Q>::w(i), drho, rho, cu, uu));
+  }
+}
+
+template <int Q, typename S, bool ODD, bool SOLID>
+__device__ __forceinline__ bool gather_state(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                             const KArgs &k, int x, int y, int z, Nb &n,
+                                             typename Store<S>::R g[Q]) {
+  n = make_nb(x, y, z, k);
+  const uint8_t fl = flags[n.cell];
+  if (!(fl & FL_FLUID)) return false;
+  unsigned sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, (size_t)k.N));
+  return true;
+}
+
+template <int Q, typename S, bool ODD, bool SOLID>
+__global__ __launch_bounds__(BLOCK) void k_moments(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                   typename Store<S>::R *__restrict__ rho_out,
+                                                   typename Store<S>::R *__restrict__ u_out, KArgs k, Tiles t) {
+  using R = typename Store<S>::R;
+  int x, y, z;
+  if (!tile_xyz(k, t, blockIdx.x, x, y, z)) return;
+  Nb n;
+  R g[Q];
+  const size_t N = (size_t)k.N;
+  if (!gather_state<Q, S, ODD, SOLID>(pop, flags, k, x, y, z, n, g)) {
+    const int c = x + k.nx * (y + k.ny * z);
+    if (rho_out) rho_out[c] = R(0);
+    if (u_out) u_out[c] = u_out[N + c] = u_out[2 * N + c] = R(0);
+    return;
+  }
+  R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += g[i];
+    acc(jx, Lat<Q>::c(i, 0), g[i]);
+    acc(jy, Lat<Q>::c(i, 1), g[i]);
+    acc(jz, Lat<Q>::c(i, 2), g[i]);
+  }
+  const R rho = R(1) + drho;
+  if (rho_out) rho_out[n.cell] = rho;
+  if (u_out) {
+    u_out[n.cell] = (jx + R(0.5) * R(k.F[0])) / rho;
+    u_out[N + n.cell] = (jy + R(0.5) * R(k.F[1])) / rho;
+    u_out[2 * N + n.cell] = (jz + R(0.5) * R(k.F[2])) / rho;
+  }
+}
+
+template <int Q, typename S, bool ODD, bool SOLID>
+__global__ __launch_bounds__(BLOCK) void k_export(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                  typename Store<S>::R *__restrict__ f, KArgs k, Tiles t) {
+  using R = typename Store<S>::R;
+  int x, y, z;
+  if (!tile_xyz(k, t, blockIdx.x, x, y, z)) return;
+  Nb n;
+  R g[Q];
+  const size_t N = (size_t)k.N;
+  const bool fluid = gather_state<Q, S, ODD, SOLID>(pop, flags, k, x, y, z, n, g);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[(size_t)i * N + n.cell] = fluid ? R(Lat<Q>::w(i)) + g[i] : R(0);
+}
+
+template <int Q, typename S, bool ODD, bool SOLID>
+__global__ __launch_bounds__(BLOCK) void k_import(S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                  const typename Store<S>::R *__restrict__ f, KArgs k, Tiles t) {
+  using R = typename Store<S>::R;
+  int x, y, z;
+  if (!tile_xyz(k, t, blockIdx.x, x, y, z)) return;
+  const Nb n = make_nb(x, y, z, k);
+  const uint8_t fl = flags[n.cell];
+  if (!(fl & FL_FLUID)) return;
+  unsigned sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  const size_t N = (size_t)k.N;
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    Store<S>::st(pop + read_slot<Q, ODD>(n, sm, i, N), f[(size_t)i * N + n.cell] - R(Lat<Q>::w(i)));
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic FP64 reductions: wave64 shuffle tree, LDS across the block's
+// four waves, one partial per block, then a single-block finalise in fixed
+// order.  Grid-stride over tiles with a fixed grid, so the summation order
+// depends only on the domain size.
+// ---------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 1024;
+constexpr int NRED = 8;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double *__restrict__ out) {
+  __shared__ double sh[BLOCK / 64][NRED];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < NV; ++a) v[a] = wave_sum(v[a]);
+  if (lane == 0)
+#pragma unroll
+    for (int a = 0; a < NV; ++a) sh[wv][a] = v[a];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int q = 0; q < BLOCK / 64; ++q) s += sh[q][threadIdx.x];
+    out[(size_t)blockIdx.x * NRED + threadIdx.x] = s;
+  }
+}
+
+// mode 0: {sum drho, sum jx, sum jy, sum jz, fluid cells} over fluid cells.
+// mode 1: {sum rho at x = p0, sum rho at x = p1, sum rho|u|^2/2, cells at
+//          x = p0, cells at x = p1, fluid cells}.
+template <int Q, typename S, bool ODD, bool SOLID>
+__global__ __launch_bounds__(BLOCK) void k_reduce(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                  KArgs k, Tiles t, int mode, int p0, int p1,
+                                                  double *__restrict__ partial) {
+  using R = typename Store<S>::R;
+  double v[NRED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (unsigned b = blockIdx.x; b < t.nblocks; b += gridDim.x) {
+    int x, y, z;
+    if (!tile_xyz(k, t, b, x, y, z)) continue;
+    Nb n;
+    R g[Q];
+    if (!gather_state<Q, S, ODD, SOLID>(pop, flags, k, x, y, z, n, g)) continue;
+    double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double gi = (double)g[i];
+      drho += gi;
+      acc(jx, Lat<Q>::c(i, 0), gi);
+      acc(jy, Lat<Q>::c(i, 1), gi);
+      acc(jz, Lat<Q>::c(i, 2), gi);
+    }
+    if (mode == 0) {
+      v[0] += drho;
+      v[1] += jx;
+      v[2] += jy;
+      v[3] += jz;
+      v[4] += 1.0;
+    } else {
+      const double rho = 1.0 + drho;
+      const double mx = jx + 0.5 * k.F[0], my = jy + 0.5 * k.F[1], mz = jz + 0.5 * k.F[2];
+      if (x == p0) {
+        v[0] += rho;
+        v[3] += 1.0;
+      }
+      if (x == p1) {
+        v[1] += rho;
+        v[4] += 1.0;
+      }
+      v[2] += 0.5 * (mx * mx + my * my + mz * mz) / rho;
+      v[5] += 1.0;
+    }
+  }
+  block_sum_store<NRED>(v, partial);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_finalise(const double *__restrict__ partial, int nparts,
+                                                    double *__restrict__ result, int offset) {
+  double v[NRED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x)
+#pragma unroll
+    for (int a = 0; a < NRED; ++a) v[a] += partial[(size_t)b * NRED + a];
+  __shared__ double sh[BLOCK][NRED];
+#pragma unroll
+  for (int a = 0; a < NRED; ++a) sh[threadIdx.x][a] = v[a];
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+#pragma unroll
+      for (int a = 0; a < NRED; ++a) sh[threadIdx.x][a] += sh[threadIdx.x + s][a];
+    __syncthreads();
+  }
+  if (threadIdx.x < NRED) result[offset + threadIdx.x] = sh[0][threadIdx.x];
+}
+
+__global__ void k_fill_zero(uint32_t *__restrict__ p, size_t n4) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void k_header(long long *__restrict__ h, long long steps, long long q, long long N, long long storage) {
+  if (threadIdx.x == 0) {
+    h[0] = 0x4c424d5354415445LL;  // "LBMSTATE"
+    h[1] = steps;
+    h[2] = q;
+    h[3] = N;
+    h[4] = storage;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+int hip_fail(lbm_ctx *ctx, hipError_t e, const char *what) {
+  ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+  return LBM_EHIP;
+}
+
+static int check_launch(lbm_ctx *ctx, const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, what);
+  return LBM_OK;
+}
+
+// Calls f.template operator()<Q, S>() for the context's lattice and storage.
+template <typename F>
+static int dispatch(lbm_ctx *ctx, F &&f) {
+  if (ctx->q == 19) {
+    if (ctx->p.storage == LBM_F64) return f.template operator()<19, double>();
+    if (ctx->p.storage == LBM_F32DEV) return f.template operator()<19, float>();
+    return f.template operator()<19, _Float16>();
+  }
+  if (ctx->p.storage == LBM_F64) return f.template operator()<27, double>();
+  if (ctx->p.storage == LBM_F32DEV) return f.template operator()<27, float>();
+  return f.template operator()<27, _Float16>();
+}
+
+int dev_init_equilibrium(lbm_ctx *ctx, const double *rho0, const double *u0) {
+  const Tiles t = tiles_of(ctx->ka);
+  return dispatch(ctx, [&]<int Q, typename S>() {
+    k_init_eq<Q, S><<<t.nblocks, BLOCK, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, rho0, u0, ctx->ka, t);
+    return check_launch(ctx, "k_init_eq");
+  });
+}
+
+template <int Q, typename S, bool ODD>
+static void launch_bulk(lbm_ctx *ctx, Tiles t) {
+  using R = typename Store<S>::R;
+  S *pop = (S *)ctx->pop;
+  const R *phi = (const R *)ctx->phi;
+  auto go = [&](auto kern) { kern<<<t.nblocks, BLOCK, 0, ctx->stream>>>(pop, ctx->flags, phi, ctx->ka, t, ctx->errflag); };
+  if (ctx->porous) {
+    if (ctx->has_solid) go(k_bulk<Q, S, ODD, true, true>);
+    else go(k_bulk<Q, S, ODD, true, false>);
+  } else {
+    if (ctx->has_solid) go(k_bulk<Q, S, ODD, false, true>);
+    else go(k_bulk<Q, S, ODD, false, false>);
+  }
+}
+
+int dev_step(lbm_ctx *ctx) {
+  const Tiles t = tiles_of(ctx->ka);
+  const bool odd = (ctx->steps & 1) != 0;
+  return dispatch(ctx, [&]<int Q, typename S>() {
+    const int nw = ctx->nwall;
+    const int wb = (nw + 255) / 256;
+    if (nw > 0) {
+      if (odd)
+        k_wall_prepass<Q, S, true><<<wb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->wcell,
+                                                                ctx->wref, ctx->wrec, nw, ctx->ka, ctx->errflag);
+      else
+        k_wall_prepass<Q, S, false><<<wb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->wcell,
+                                                                 ctx->wref, ctx->wrec, nw, ctx->ka, ctx->errflag);
+    }
+    if (odd) launch_bulk<Q, S, true>(ctx, t);
+    else launch_bulk<Q, S, false>(ctx, t);
+    if (nw > 0) {
+      if (odd)
+        k_wall<Q, S, true><<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wrec, nw,
+                                                        ctx->ka, ctx->errflag);
+      else
+        k_wall<Q, S, false><<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wrec, nw,
+                                                         ctx->ka, ctx->errflag);
+    }
+    return check_launch(ctx, "step kernels");
+  });
+}
+
+// Runs g.template operator()<ODD, SOLID>() for the current parity and geometry.
+template <typename G>
+static int by_parity(lbm_ctx *ctx, G &&g) {
+  const bool odd = (ctx->steps & 1) != 0;
+  if (odd) return ctx->has_solid ? g.template operator()<true, true>() : g.template operator()<true, false>();
+  return ctx->has_solid ? g.template operator()<false, true>() : g.template operator()<false, false>();
+}
+
+int dev_moments(lbm_ctx *ctx, void *rho, void *u) {
+  const Tiles t = tiles_of(ctx->ka);
+  return dispatch(ctx, [&]<int Q, typename S>() {
+    using R = typename Store<S>::R;
+    return by_parity(ctx, [&]<bool ODD, bool SOLID>() {
+      k_moments<Q, S, ODD, SOLID><<<t.nblocks, BLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, (R *)rho,
+                                                                        (R *)u, ctx->ka, t);
+      return check_launch(ctx, "k_moments");
+    });
+  });
+}
+
+int dev_export(lbm_ctx *ctx, void *f) {
+  const Tiles t = tiles_of(ctx->ka);
+  return dispatch(ctx, [&]<int Q, typename S>() {
+    using R = typename Store<S>::R;
+    return by_parity(ctx, [&]<bool ODD, bool SOLID>() {
+      k_export<Q, S, ODD, SOLID><<<t.nblocks, BLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, (R *)f,
+                                                                       ctx->ka, t);
+      return check_launch(ctx, "k_export");
+    });
+  });
+}
+
+int dev_import(lbm_ctx *ctx, const void *f) {
+  const Tiles t = tiles_of(ctx->ka);
+  return dispatch(ctx, [&]<int Q, typename S>() {
+    using R = typename Store<S>::R;
+    return by_parity(ctx, [&]<bool ODD, bool SOLID>() {
+      k_import<Q, S, ODD, SOLID><<<t.nblocks, BLOCK, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, (const R *)f,
+                                                                       ctx->ka, t);
+      return check_launch(ctx, "k_import");
+    });
+  });
+}
+
+static int reduce(lbm_ctx *ctx, int mode, int p0, int p1, int offset) {
+  const Tiles t = tiles_of(ctx->ka);
+  const int grid = (int)std::min<unsigned>(t.nblocks, (unsigned)std::min(RED_BLOCKS, ctx->npartial));
+  return dispatch(ctx, [&]<int Q, typename S>() {
+    int rc = by_parity(ctx, [&]<bool ODD, bool SOLID>() {
+      k_reduce<Q, S, ODD, SOLID><<<grid, BLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->ka, t, mode,
+                                                                  p0, p1, ctx->partial);
+      return check_launch(ctx, "k_reduce");
+    });
+    if (rc != LBM_OK) return rc;
+    k_finalise<<<1, BLOCK, 0, ctx->stream>>>(ctx->partial, grid, ctx->result, offset);
+    return check_launch(ctx, "k_finalise");
+  });
+}
+
+int dev_reduce_diag(lbm_ctx *ctx) { return reduce(ctx, 0, -1, -1, 0); }
+int dev_objective(lbm_ctx *ctx, const int planes[2]) { return reduce(ctx, 1, planes[0], planes[1], 8); }
+
+int dev_fill(lbm_ctx *ctx, void *ptr, size_t bytes) {
+  const size_t n4 = bytes / 4;
+  if (n4 == 0) return LBM_OK;
+  const size_t want = (n4 + 255) / 256;
+  const unsigned grid = (unsigned)std::min<size_t>(want, 65536);
+  k_fill_zero<<<grid, 256, 0, ctx->stream>>>((uint32_t *)ptr, n4);
+  return check_launch(ctx, "k_fill_zero");
+}
+
+int dev_write_header(lbm_ctx *ctx, void *dst) {
+  k_header<<<1, 64, 0, ctx->stream>>>((long long *)dst, ctx->steps, ctx->q, ctx->N, ctx->p.storage);
+  return check_launch(ctx, "k_header");
+}
+
+}  // namespace lbmk

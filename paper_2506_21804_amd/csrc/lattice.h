@@ -1,0 +1,175 @@
+// Velocity sets, storage conversions and the per-lane neighbour geometry of
+// the AA in-place streaming scheme, for the gfx950 kernels.
+//
+// D3Q19 is the stencil of the paper (Sec. 2.2, lattice figure); D3Q27 adds
+// the eight corner directions.  Order: rest, nine "positive" directions
+// (D3Q27: then four corners with +x), then the negatives in the same order,
+// so the opposite of i is i +- (q-1)/2.  Weights: D3Q19 1/3, 1/18, 1/36;
+// D3Q27 8/27, 2/27, 1/54, 1/216 (rest, axis, edge, corner).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace lbmk {
+
+template <int Q>
+struct Lat {
+  static_assert(Q == 19 || Q == 27, "D3Q19 or D3Q27");
+  static constexpr int H = (Q - 1) / 2;  // number of "positive" directions
+  __host__ __device__ static constexpr int c(int i, int a) {
+    constexpr int pos[13][3] = {{1, 0, 0}, {0, 1, 0},  {0, 0, 1},  {1, 1, 0},  {1, -1, 0},
+                                {1, 0, 1}, {1, 0, -1}, {0, 1, 1},  {0, 1, -1}, {1, 1, 1},
+                                {1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
+    return i == 0 ? 0 : (i <= H ? pos[i - 1][a] : -pos[i - 1 - H][a]);
+  }
+  __host__ __device__ static constexpr int opp(int i) { return i == 0 ? 0 : (i <= H ? i + H : i - H); }
+  __host__ __device__ static constexpr int n2(int i) {
+    return c(i, 0) * c(i, 0) + c(i, 1) * c(i, 1) + c(i, 2) * c(i, 2);
+  }
+  __host__ __device__ static constexpr double w(int i) {
+    return Q == 19 ? (n2(i) == 0 ? 1.0 / 3.0 : n2(i) == 1 ? 1.0 / 18.0 : 1.0 / 36.0)
+                   : (n2(i) == 0 ? 8.0 / 27.0 : n2(i) == 1 ? 2.0 / 27.0 : n2(i) == 2 ? 1.0 / 54.0 : 1.0 / 216.0);
+  }
+};
+
+// s += c * v for a lattice component c in {-1, 0, 1} known at compile time
+// after unrolling (no multiplication, no 0*v).
+template <typename R>
+__device__ __forceinline__ void acc(R &s, int c, R v) {
+  if (c > 0) s += v;
+  else if (c < 0) s -= v;
+}
+template <typename R>
+__device__ __forceinline__ R dot3(int cx, int cy, int cz, R x, R y, R z) {
+  R s = R(0);
+  acc(s, cx, x);
+  acc(s, cy, y);
+  acc(s, cz, z);
+  return s;
+}
+
+// Stored value type -> compute type.
+template <typename S>
+struct Store;
+template <>
+struct Store<double> {
+  using R = double;
+  static __device__ __forceinline__ R ld(const double *p) { return *p; }
+  static __device__ __forceinline__ void st(double *p, R v) { *p = v; }
+};
+template <>
+struct Store<float> {
+  using R = float;
+  static __device__ __forceinline__ R ld(const float *p) { return *p; }
+  static __device__ __forceinline__ void st(float *p, R v) { *p = v; }
+};
+template <>
+struct Store<_Float16> {
+  using R = float;
+  static __device__ __forceinline__ R ld(const _Float16 *p) { return (float)*p; }
+  static __device__ __forceinline__ void st(_Float16 *p, R v) { *p = (_Float16)v; }  // round to nearest even
+};
+
+// Neighbour geometry of one cell: offsets (in cells) to the -1 / +1 neighbour
+// along each axis with periodic wrap, and which moves leave the domain
+// through a non-periodic face (those links count as solid).
+struct Nb {
+  int cell;
+  int d[3][2];
+  unsigned out;  // bit 2a: -1 along axis a leaves the domain; bit 2a+1: +1 does
+};
+
+__device__ __forceinline__ Nb make_nb(int x, int y, int z, const KArgs &k) {
+  Nb n;
+  const int sy = k.nx, sz = k.nx * k.ny;
+  n.cell = x + sy * y + sz * z;
+  n.d[0][0] = (x == 0) ? (k.nx - 1) : -1;
+  n.d[0][1] = (x == k.nx - 1) ? -(k.nx - 1) : 1;
+  n.d[1][0] = (y == 0) ? (k.ny - 1) * sy : -sy;
+  n.d[1][1] = (y == k.ny - 1) ? -(k.ny - 1) * sy : sy;
+  n.d[2][0] = (z == 0) ? (k.nz - 1) * sz : -sz;
+  n.d[2][1] = (z == k.nz - 1) ? -(k.nz - 1) * sz : sz;
+  unsigned o = 0;
+  if (!k.per[0]) o |= (x == 0 ? 1u : 0u) | (x == k.nx - 1 ? 2u : 0u);
+  if (!k.per[1]) o |= (y == 0 ? 4u : 0u) | (y == k.ny - 1 ? 8u : 0u);
+  if (!k.per[2]) o |= (z == 0 ? 16u : 0u) | (z == k.nz - 1 ? 32u : 0u);
+  n.out = o;
+  return n;
+}
+
+__device__ __forceinline__ void cell_xyz(int c, const KArgs &k, int &x, int &y, int &z) {
+  x = c % k.nx;
+  int t = c / k.nx;
+  y = t % k.ny;
+  z = t / k.ny;
+}
+
+// Offset of the cell at + sgn * c_i.
+template <int Q>
+__device__ __forceinline__ int nb_off(const Nb &n, int i, int sgn) {
+  int o = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int c = sgn * Lat<Q>::c(i, a);
+    if (c < 0) o += n.d[a][0];
+    else if (c > 0) o += n.d[a][1];
+  }
+  return o;
+}
+template <int Q>
+__device__ __forceinline__ bool nb_out(const Nb &n, int i, int sgn) {
+  bool r = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int c = sgn * Lat<Q>::c(i, a);
+    if (c < 0) r = r || ((n.out >> (2 * a)) & 1u);
+    else if (c > 0) r = r || ((n.out >> (2 * a + 1)) & 1u);
+  }
+  return r;
+}
+
+// Bit i set when the upstream cell (cell - c_i) is solid or outside.
+template <int Q>
+__device__ __forceinline__ unsigned solid_mask(const Nb &n, const uint8_t *__restrict__ flags) {
+  unsigned m = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const bool s = nb_out<Q>(n, i, -1) || !(flags[n.cell + nb_off<Q>(n, i, -1)] & FL_FLUID);
+    m |= (s ? 1u : 0u) << i;
+  }
+  return m;
+}
+
+// AA pattern (in-place, one buffer A[i][cell]).
+// Even parity: the state f_i(x) sits at A[i][x]; the post-collision f*_i(x)
+//   is written to A[opp i][x].
+// Odd parity: the state f_i(x) is A[opp i][x - c_i] if that cell is fluid,
+//   else A[i][x] (halfway bounce-back); f*_i(x) goes to A[i][x + c_i] if that
+//   cell is fluid, else to A[opp i][x].
+// Each cell reads and writes the same set of slots, and the sets of two cells
+// are disjoint, so every cell can be updated concurrently in place.
+template <int Q, bool ODD>
+__device__ __forceinline__ size_t read_slot(const Nb &n, unsigned sm, int i, size_t N) {
+  if (!ODD) return (size_t)i * N + (size_t)n.cell;
+  if ((sm >> i) & 1u) return (size_t)i * N + (size_t)n.cell;
+  return (size_t)Lat<Q>::opp(i) * N + (size_t)(n.cell + nb_off<Q>(n, i, -1));
+}
+template <int Q, bool ODD>
+__device__ __forceinline__ size_t write_slot(const Nb &n, unsigned sm, int i, size_t N) {
+  if (!ODD) return (size_t)Lat<Q>::opp(i) * N + (size_t)n.cell;
+  if ((sm >> Lat<Q>::opp(i)) & 1u) return (size_t)Lat<Q>::opp(i) * N + (size_t)n.cell;
+  return (size_t)i * N + (size_t)(n.cell + nb_off<Q>(n, i, +1));
+}
+
+// XCD-aware block order: hardware hands block b to XCD b % 8; give each XCD
+// a contiguous run of tiles so that neighbouring tiles share its L2.
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
+  const unsigned q = nb >> 3, r = nb & 7u, x = b & 7u, s = b >> 3;
+  return x * q + (x < r ? x : r) + s;
+}
+
+}  // namespace lbmk

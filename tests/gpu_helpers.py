@@ -1,0 +1,40 @@
+"""Shared helpers of the GPU parity tests: run the same seeded case on the
+oracle (FP64 CPU) and through the HIP library's C ABI, and compare."""
+import sys
+
+import numpy as np
+
+import oracle as O
+
+
+def oracle_for(case, steps=0, tangent=False, wall_dist="case"):
+    p = O.make_params(case.q, case.shape, periodic=case.periodic, tau0=case.tau0, cs_smag=case.cs_smag,
+                      force=case.force, wall_model=case.wall_model, kappa=case.kappa, E=case.E,
+                      fringe_len=case.fringe_len, u_ref=case.u_ref, z0=case.z0, lid=case.lid)
+    wd = case.wall_dist if isinstance(wall_dist, str) else wall_dist
+    s = O.Oracle(p, mask=case.mask, wall_dist=wd, porosity=case.porosity, rho0=case.rho0, u0=case.u0,
+                 tangent=tangent)
+    if steps:
+        s.step(steps)
+    return s
+
+
+def rel_maxnorm(a, b, ref=None):
+    """max |a - b| / max |ref| (ref defaults to b)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    r = np.abs(b if ref is None else ref).max()
+    return float(np.abs(a - b).max() / max(r, 1e-300))
+
+
+def moment_errors(gpu_rho, gpu_u, orc_rho, orc_u):
+    """Errors of density deviation and velocity, each relative to the max-norm
+    of the oracle's field (density: of rho - 1)."""
+    e_rho = rel_maxnorm(gpu_rho - 1.0, orc_rho - 1.0)
+    e_u = rel_maxnorm(gpu_u, orc_u)
+    return e_rho, e_u
+
+
+def announce(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
