@@ -1,0 +1,269 @@
+"""Benchmark of the fused collide-and-stream step on one MI355X.
+
+Default workload: the body-force-driven D3Q27 Smagorinsky channel with the
+Spalding wall model on both walls, 384 x 192 x 192 cells, FP32 deviation
+storage (14.2 M cells, 1.53 GB of populations).  One step = wall prepass +
+fused bulk collide-and-stream + wall reconstruction over the whole domain.
+
+Prints one JSON line: MLUPS over all cells (value), the roofline entry of the
+dominant kernel (the bulk collide-and-stream kernel, timed with HIP events
+recorded on its own stream over the timed steps), and the FP64 CPU oracle
+timed on a bounded crop of the same workload on the host cores.
+
+Usage: python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+Workloads: channel (default), channel16, urban, urban16, tgv, adjoint.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
+
+
+def storage_bytes(storage):
+    return {"f64": 8, "f32": 4, "f16": 2}[storage]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "lattice.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2506_21804_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_case(name):
+    from paper_2506_21804_amd import inputs as I
+    if name in ("channel", "channel16"):
+        return I.channel(384, 192, 192, q=27), ("f16" if name.endswith("16") else "f32"), \
+            "channel384x192x192_d3q27_smag_wallmodel"
+    if name in ("urban", "urban16"):
+        return I.urban(768, 768, 256, q=27, with_wall_dist=False), ("f16" if name.endswith("16") else "f32"), \
+            "urban768x768x256_d3q27_smag_wallmodel_fringe_lid"
+    if name == "tgv":
+        return I.taylor_green(32, q=19), "f64", "tgv32_d3q19_smag"
+    if name == "adjoint":
+        return I.porous_channel(128), "f32", "porous_channel128_d3q19_adjoint"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(name, budget_s=20.0):
+    """The FP64 oracle on a bounded crop of the workload (same x-y plane,
+    fewer z planes), timed around its step loop on the host cores."""
+    import oracle as O
+    from paper_2506_21804_amd import inputs as I
+    if name.startswith("channel"):
+        case = I.channel(384, 192, 24, q=27)
+        sample = "channel crop 384x192x24 (walls at z), D3Q27 FP64"
+    elif name.startswith("urban"):
+        case = I.urban(192, 192, 64, q=27, fringe_len=32, x_lo=16, x_hi=144, h_mean=20.0, h_max=48)
+        sample = "urban crop 192x192x64 (buildings, fringe, lid), D3Q27 FP64"
+    elif name == "tgv":
+        case = I.taylor_green(32, q=19)
+        sample = "tgv 32^3 D3Q19 FP64 (full)"
+    else:
+        case = I.porous_channel(shape=(128, 128, 16))
+        sample = "porous channel crop 128x128x16 D3Q19 FP64"
+    p = O.make_params(case.q, case.shape, periodic=case.periodic, tau0=case.tau0, cs_smag=case.cs_smag,
+                      force=case.force, wall_model=case.wall_model, kappa=case.kappa, E=case.E,
+                      fringe_len=case.fringe_len, u_ref=case.u_ref, z0=case.z0, lid=case.lid)
+    s = O.Oracle(p, mask=case.mask, wall_dist=case.wall_dist, porosity=case.porosity, rho0=case.rho0, u0=case.u0)
+    t0 = time.perf_counter()
+    s.step(1)
+    one = time.perf_counter() - t0
+    n = max(1, min(50, int(budget_s / max(one, 1e-6)) - 1))
+    t0 = time.perf_counter()
+    s.step(n)
+    dt = time.perf_counter() - t0
+    return {"value": round(case.ncells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(),
+            "kind": "oracle", "sample": f"{sample}, {n} steps, {dt:.1f} s"}
+
+
+def copy_ceiling(torch, nbytes=4 << 30):
+    """Device-to-device copy GB/s (read + write) of a plain torch copy of
+    nbytes: a practical ceiling next to the 8 TB/s peak."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    reps = 10
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="channel")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2506_21804_amd as lbm
+
+    lbm.load()
+    torch.cuda.set_device(0)
+    case, storage, wname = make_case(args.workload)
+    print(f"[bench] workload {wname} storage {storage} cells {case.ncells}", file=sys.stderr, flush=True)
+    if args.workload == "adjoint":
+        return bench_adjoint(args, torch, lbm, case, storage, wname)
+
+    lat = lbm.Lattice(case, storage=storage, wall_dist=None if case.wall_dist is None else "case")
+    N = case.ncells
+    nfluid = case.nfluid()
+    nwall = lbm.lbm_wall_count(lat.ctx)
+    del case
+    stream = lat.stream
+    lat.step(args.warmup)
+    lat.sync()
+    print(f"[bench] warmup {args.warmup} done, wall cells {nwall}", file=sys.stderr, flush=True)
+
+    # timed region: exactly K steps, bracketed by device synchronisation
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    lat.step(args.steps)
+    ev1.record(stream)
+    lat.sync()
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    mlups = N * args.steps / (ms_total * 1e-3) / 1e6
+    print(f"[bench] timed {args.steps} steps: {ms_step:.4f} ms/step, {mlups:.1f} MLUPS (host {wall_s:.3f} s)",
+          file=sys.stderr, flush=True)
+
+    # per-kernel times over the same number of steps, events on the library's stream
+    lbm.lbm_profile(lat.ctx, True)
+    lat.step(args.steps)
+    lbm.lbm_profile(lat.ctx, False)
+    kms, kcount = lbm.lbm_profile_read(lat.ctx)
+    lat.sync()
+    k2_ms = kms[1] / max(kcount[1], 1)
+    q = lat.q
+    sb = storage_bytes(storage)
+    # algorithmic bytes of one bulk launch: every cell's flag byte, q loads and
+    # q stores for each fluid cell it updates (all fluid cells but the wall cells)
+    k2_bytes = N * 1 + (nfluid - nwall) * 2 * q * sb
+    achieved = k2_bytes / (k2_ms * 1e-3) / 1e9
+    step_bytes = nfluid * (2 * q * sb + 1)
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", f"k_bulk_{args.workload}_traffic.json")
+    if os.path.exists(tf):
+        with open(tf) as fh:
+            t = json.load(fh)
+        if t.get("kernel_hash") == kernel_source_hash():
+            traffic = t.get("bytes_per_launch")
+    diag = lat.diagnostics()
+    out = {
+        "metric": "MLUPS (million lattice-cell updates per second) per GPU",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32 (fp32 deviation storage)", "f16": "f32 compute, f16 deviation storage",
+                  "f64": "f64"}[storage],
+        "data": "synthetic",
+        "config": {"workload": wname, "cells": N, "fluid_cells": nfluid, "wall_cells": nwall, "lattice": f"D3Q{q}",
+                   "storage": storage},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "kernel": "k_bulk", "avg_launch_ms": round(k2_ms, 5), "alg_bytes_per_launch": k2_bytes},
+        "step_alg_gbs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "kernel_ms_per_step": {"wall_prepass": round(kms[0] / max(kcount[0], 1), 5), "bulk": round(k2_ms, 5),
+                               "wall_collide": round(kms[2] / max(kcount[2], 1), 5)},
+        "mass_drift_rel": None,
+    }
+    out["mass"] = float(diag[0])
+    del lat
+    torch.cuda.empty_cache()
+    if not args.no_copy:
+        out["copy_ceiling_gbs"] = round(copy_ceiling(torch), 1)
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    out.pop("mass_drift_rel")
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args, torch, lbm, case, storage, wname):
+    """Forward step vs hand-written reverse step on the porosity workload,
+    and one full checkpointed gradient."""
+    lat = lbm.Lattice(case, storage=storage)
+    N = case.ncells
+    planes = case.extra["planes"]
+    lat.step(args.warmup)
+    lat.sync()
+    stream = lat.stream
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    K = args.steps
+    torch.cuda.synchronize()
+    e[0].record(stream)
+    lat.step(K)
+    e[1].record(stream)
+    lat.sync()
+    fwd_ms = e[0].elapsed_time(e[1]) / K
+    lam = lat.new_adjoint()
+    grad = torch.zeros(N, dtype=lat.rdtype, device="cuda")
+    lbm.lbm_adjoint_seed(lat.ctx, planes, lam)
+    lat.sync()
+    e[2].record(stream)
+    for _ in range(K):
+        lbm.lbm_adjoint_step(lat.ctx, lam, grad)
+    e[3].record(stream)
+    lat.sync()
+    adj_ms = e[2].elapsed_time(e[3]) / K
+    T, nsnap = 400, 20
+    snaps = torch.empty(nsnap * lbm.lbm_state_bytes(lat.ctx), dtype=torch.uint8, device="cuda")
+    t0 = time.perf_counter()
+    J, nfwd = lbm.lbm_gradient(lat.ctx, T, planes, snaps, nsnap, lam, grad)
+    grad_s = time.perf_counter() - t0
+    out = {
+        "metric": "adjoint/forward step time ratio",
+        "value": round(adj_ms / fwd_ms, 3),
+        "unit": "ratio",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(fwd_ms, 5),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wname, "cells": N},
+        "forward_mlups": round(N / (fwd_ms * 1e-3) / 1e6, 1),
+        "adjoint_ms_per_step": round(adj_ms, 5),
+        "gradient": {"T": T, "snapshots": nsnap, "forward_steps": nfwd, "seconds": round(grad_s, 3),
+                     "J": J, "forward_only_seconds": round(T * fwd_ms * 1e-3, 3)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

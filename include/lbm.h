@@ -172,6 +172,15 @@ int lbm_wall_count(const lbm_ctx *ctx);
 int lbm_wall_records(lbm_ctx *ctx, int *cell, int *ref, double *normal, double *utau, double *G,
                      double *tau);
 
+/* Per-kernel timing of the step kernels with HIP events recorded on the
+ * context's stream around each launch: index 0 the wall prepass, 1 the bulk
+ * collide-and-stream kernel, 2 the wall reconstruction.  lbm_profile(ctx, 1)
+ * starts recording (creates the events once), lbm_profile(ctx, 0) stops it;
+ * lbm_profile_read waits for the recorded launches and returns, then
+ * resets, the accumulated milliseconds and launch counts. */
+int lbm_profile(lbm_ctx *ctx, int enable);
+int lbm_profile_read(lbm_ctx *ctx, double ms[3], long long count[3]);
+
 const char *lbm_last_error(const lbm_ctx *ctx);
 /* Releases the context (host memory only; the workspace stays the caller's). */
 void lbm_free(lbm_ctx *ctx);

@@ -19,7 +19,8 @@ __all__ = [
     "lbm_diagnostics", "lbm_sync", "lbm_steps_done", "lbm_get_populations", "lbm_set_populations",
     "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes",
     "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural",
-    "lbm_gradient", "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_last_error", "lbm_free",
+    "lbm_gradient", "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
+    "lbm_last_error", "lbm_free",
     "Lattice", "D3Q19", "D3Q27", "F64", "F32DEV", "F16DEV",
 ]
 
@@ -89,6 +90,8 @@ def load():
         "lbm_revolve_cost": (ll, [i, i]),
         "lbm_wall_count": (i, [vp]),
         "lbm_wall_records": (i, [vp, vp, vp, vp, vp, vp, vp]),
+        "lbm_profile": (i, [vp, i]),
+        "lbm_profile_read": (i, [vp, vp, vp]),
         "lbm_last_error": (C.c_char_p, [vp]),
         "lbm_free": (None, [vp]),
     }
@@ -105,7 +108,8 @@ def exported_symbols():
             "lbm_steps_done", "lbm_get_populations", "lbm_set_populations", "lbm_state_bytes",
             "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes", "lbm_adjoint_seed",
             "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural", "lbm_gradient",
-            "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_last_error", "lbm_free"]
+            "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
+            "lbm_last_error", "lbm_free"]
 
 
 def _dptr(t):
@@ -254,6 +258,17 @@ def lbm_wall_records(ctx):
     _check(ctx, load().lbm_wall_records(ctx, _hptr(cell), _hptr(ref), _hptr(normal), _hptr(utau), _hptr(G),
                                         _hptr(tau)))
     return dict(cells=cell, refs=ref, normal=normal, utau=utau, G=G, tau=tau)
+
+
+def lbm_profile(ctx, enable):
+    _check(ctx, load().lbm_profile(ctx, 1 if enable else 0))
+
+
+def lbm_profile_read(ctx):
+    ms = (C.c_double * 3)()
+    cnt = (C.c_longlong * 3)()
+    _check(ctx, load().lbm_profile_read(ctx, ms, cnt))
+    return np.array(ms[:]), np.array(cnt[:])
 
 
 def lbm_last_error(ctx) -> str:

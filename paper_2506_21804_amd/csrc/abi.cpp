@@ -141,6 +141,35 @@ std::vector<unsigned char> to_compute(const std::vector<double> &v, int storage)
 
 }  // namespace
 
+namespace lbmk {
+
+static void drain_slot(KernelTimer &t, int s) {
+  if (!t.pending[s]) return;
+  float ms = 0.f;
+  if (hipEventSynchronize(t.stop[s]) == hipSuccess && hipEventElapsedTime(&ms, t.start[s], t.stop[s]) == hipSuccess) {
+    t.ms += ms;
+    t.count += 1;
+  }
+  t.pending[s] = false;
+}
+
+void prof_begin(lbm_ctx *ctx, int k) {
+  if (!ctx->profiling) return;
+  KernelTimer &t = ctx->timers[k];
+  drain_slot(t, t.head);
+  hipEventRecord(t.start[t.head], ctx->stream);
+}
+
+void prof_end(lbm_ctx *ctx, int k) {
+  if (!ctx->profiling) return;
+  KernelTimer &t = ctx->timers[k];
+  hipEventRecord(t.stop[t.head], ctx->stream);
+  t.pending[t.head] = true;
+  t.head = (t.head + 1) % PROF_RING;
+}
+
+}  // namespace lbmk
+
 extern "C" {
 
 size_t lbm_workspace_bytes(const lbm_params *p, const uint8_t *mask, int porous) {
@@ -492,6 +521,49 @@ int lbm_wall_records(lbm_ctx *ctx, int *cell, int *ref, double *normal, double *
 
 const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err.c_str() : g_static_error.c_str(); }
 
-void lbm_free(lbm_ctx *ctx) { delete ctx; }
+int lbm_profile(lbm_ctx *ctx, int enable) {
+  if (!ctx) return LBM_EINVAL;
+  if (enable && !ctx->timers) {
+    ctx->timers = new (std::nothrow) KernelTimer[3];
+    if (!ctx->timers) return set_err(ctx, LBM_EINVAL, "out of host memory");
+    for (int k = 0; k < 3; ++k)
+      for (int s = 0; s < PROF_RING; ++s) {
+        hipError_t e = hipEventCreate(&ctx->timers[k].start[s]);
+        if (e == hipSuccess) e = hipEventCreate(&ctx->timers[k].stop[s]);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate");
+      }
+  }
+  ctx->profiling = enable != 0;
+  return LBM_OK;
+}
+
+int lbm_profile_read(lbm_ctx *ctx, double ms[3], long long count[3]) {
+  if (!ctx || !ms || !count) return ctx ? set_err(ctx, LBM_EINVAL, "null output") : LBM_EINVAL;
+  for (int k = 0; k < 3; ++k) {
+    ms[k] = 0.0;
+    count[k] = 0;
+    if (!ctx->timers) continue;
+    KernelTimer &t = ctx->timers[k];
+    for (int s = 0; s < PROF_RING; ++s) drain_slot(t, s);
+    ms[k] = t.ms;
+    count[k] = t.count;
+    t.ms = 0.0;
+    t.count = 0;
+  }
+  return LBM_OK;
+}
+
+void lbm_free(lbm_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->timers) {
+    for (int k = 0; k < 3; ++k)
+      for (int s = 0; s < PROF_RING; ++s) {
+        if (ctx->timers[k].start[s]) hipEventDestroy(ctx->timers[k].start[s]);
+        if (ctx->timers[k].stop[s]) hipEventDestroy(ctx->timers[k].stop[s]);
+      }
+    delete[] ctx->timers;
+  }
+  delete ctx;
+}
 
 }  // extern "C"

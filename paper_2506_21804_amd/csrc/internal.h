@@ -52,6 +52,20 @@ struct KArgs {
 
 }  // namespace lbmk
 
+namespace lbmk {
+// Per-kernel event timing of the step kernels (K1 wall prepass, K2 bulk,
+// K3 wall collide), enabled by lbm_profile.  A ring of event pairs per
+// kernel; a slot is read back before it is reused.
+constexpr int PROF_RING = 256;
+struct KernelTimer {
+  hipEvent_t start[PROF_RING]{}, stop[PROF_RING]{};
+  bool pending[PROF_RING]{};
+  int head = 0;
+  double ms = 0.0;
+  long long count = 0;
+};
+}  // namespace lbmk
+
 struct lbm_ctx {
   lbm_params p{};
   int q = 0;
@@ -77,6 +91,8 @@ struct lbm_ctx {
   int *errflag = nullptr;     // [1] bit 0 non-finite, bit 1 Newton
   long long steps = 0;
   std::string err;
+  bool profiling = false;
+  lbmk::KernelTimer *timers = nullptr;  // [3] when profiling was ever enabled
 };
 
 namespace lbmk {
@@ -123,5 +139,8 @@ int dev_fill(lbm_ctx *ctx, void *ptr, size_t bytes);  // zero fill with a kernel
 int dev_write_header(lbm_ctx *ctx, void *dst);
 
 int hip_fail(lbm_ctx *ctx, hipError_t e, const char *what);
+// Event brackets around step kernel k (0: K1, 1: K2, 2: K3); no-ops unless profiling.
+void prof_begin(lbm_ctx *ctx, int k);
+void prof_end(lbm_ctx *ctx, int k);
 
 }  // namespace lbmk

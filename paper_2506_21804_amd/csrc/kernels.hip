@@ -641,22 +641,28 @@ int dev_step(lbm_ctx *ctx) {
     const int nw = ctx->nwall;
     const int wb = (nw + 255) / 256;
     if (nw > 0) {
+      prof_begin(ctx, 0);
       if (odd)
         k_wall_prepass<Q, S, true><<<wb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->wcell,
                                                                 ctx->wref, ctx->wrec, nw, ctx->ka, ctx->errflag);
       else
         k_wall_prepass<Q, S, false><<<wb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->wcell,
                                                                  ctx->wref, ctx->wrec, nw, ctx->ka, ctx->errflag);
+      prof_end(ctx, 0);
     }
+    prof_begin(ctx, 1);
     if (odd) launch_bulk<Q, S, true>(ctx, t);
     else launch_bulk<Q, S, false>(ctx, t);
+    prof_end(ctx, 1);
     if (nw > 0) {
+      prof_begin(ctx, 2);
       if (odd)
         k_wall<Q, S, true><<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wrec, nw,
                                                         ctx->ka, ctx->errflag);
       else
         k_wall<Q, S, false><<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wrec, nw,
                                                          ctx->ka, ctx->errflag);
+      prof_end(ctx, 2);
     }
     return check_launch(ctx, "step kernels");
   });

@@ -1,0 +1,157 @@
+"""Discrete adjoint of the HIP path checked against the oracle's forward-mode
+(dual-number) derivatives and central finite differences.
+
+ - transpose test: <L v, w> from the oracle's tangent step equals <v, L^T w>
+   from one GPU reverse step (populations and porosity directions), FP64;
+ - the checkpointed GPU gradient dJ/dphi equals the oracle's tangent
+   derivative at sampled cells (FP64, 1e-10);
+ - the checkpointed gradient is bitwise equal to the full-storage one and
+   takes the binomial-optimal number of forward steps;
+ - the FP32 gradient matches FP64 central differences of the oracle within
+   1e-4 (|g - g_FD| / max(|g_FD|, 1e-3 max|g_FD|)).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2506_21804_amd import inputs as I
+from gpu_helpers import announce, oracle_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(shape=(20, 12, 8)):
+    return I.porous_channel(shape=shape)
+
+
+def test_transpose_one_step(gpu):
+    case = _case()
+    q, N = case.q, case.ncells
+    c, w, _ = O.velocity_set(q)
+    f_n = I.random_state(w, N, seed_offset=21, amp=0.05)
+    rng = np.random.default_rng(22)
+    v = rng.standard_normal((q, N))
+    dphi = rng.standard_normal(N)
+    wv = rng.standard_normal((q, N))
+    for parity in (0, 1):
+        announce(f"transpose test parity {parity}")
+        # oracle: tangent of one step from f_n in direction (v, dphi)
+        orc = oracle_for(case, tangent=True)
+        orc.set_populations(f_n, v)
+        orc.set_phi_tangent(dphi)
+        orc.step(1)
+        _, Lv = orc.populations(with_tangent=True)
+        lhs = float((Lv * wv).sum())
+        # GPU: state f_n at step count n with the requested parity
+        lat = gpu.Lattice(case, storage="f64")
+        if parity:
+            lat.step(1)
+        lat.set_populations(torch.as_tensor(f_n))
+        snap = lat.new_state_buffer()
+        lat.save_state(snap)
+        lat.step(1)
+        lam = lat.new_adjoint()
+        gpu.lbm_adjoint_from_natural(lat.ctx, torch.as_tensor(wv), lam)
+        lat.load_state(snap)
+        grad = torch.zeros(N, dtype=torch.float64, device="cuda")
+        gpu.lbm_adjoint_step(lat.ctx, lam, grad)
+        nat = torch.empty_like(lam)
+        gpu.lbm_adjoint_to_natural(lat.ctx, lam, nat)
+        lat.sync()
+        rhs = float((v * nat.cpu().numpy()).sum() + (dphi * grad.cpu().numpy()).sum())
+        announce(f"<Lv,w> {lhs:.15e} <v,L^T w> {rhs:.15e}")
+        assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+
+
+def test_gradient_matches_oracle_tangent(gpu):
+    case = _case((16, 12, 8))
+    planes = (2, 13)
+    T = 20
+    lat = gpu.Lattice(case, storage="f64")
+    N = case.ncells
+    lam = lat.new_adjoint()
+    grad = torch.zeros(N, dtype=torch.float64, device="cuda")
+    snaps = lat.new_state_buffer(4)
+    J, nfwd = gpu.lbm_gradient(lat.ctx, T, planes, snaps, 4, lam, grad)
+    g = grad.cpu().numpy()
+    assert nfwd == T + gpu.lbm_revolve_cost(T, 4)
+    Jo, _ = oracle_for(case, T).objective(planes)
+    assert abs(J - Jo) <= 1e-12 * abs(Jo)
+    for cell in I.sample_cells(N, 6, seed_offset=5):
+        orc = oracle_for(case, tangent=True)
+        e = np.zeros(N)
+        e[cell] = 1.0
+        orc.set_phi_tangent(e)
+        orc.step(T)
+        _, dJ = orc.objective(planes)
+        announce(f"cell {cell}: gpu {g[cell]:.12e} tangent {dJ:.12e}")
+        assert abs(g[cell] - dJ) <= 1e-10 * max(abs(dJ), 1e-3 * np.abs(g).max())
+    assert lat.steps == 0  # the context is back at step 0
+
+
+def test_checkpointed_equals_full_storage(gpu):
+    case = _case((16, 12, 8))
+    planes = (2, 13)
+    T = 33
+    N = case.ncells
+    out = []
+    for nsnap in (3, T + 1):
+        lat = gpu.Lattice(case, storage="f32")
+        lam = lat.new_adjoint()
+        grad = torch.zeros(N, dtype=torch.float32, device="cuda")
+        snaps = lat.new_state_buffer(nsnap)
+        J, nfwd = gpu.lbm_gradient(lat.ctx, T, planes, snaps, nsnap, lam, grad)
+        assert nfwd == T + gpu.lbm_revolve_cost(T, nsnap)
+        out.append(grad.cpu().numpy())
+    assert gpu.lbm_revolve_cost(T, T + 1) == 0
+    assert np.array_equal(out[0], out[1])
+
+
+def test_fp32_gradient_vs_central_differences(gpu):
+    case = _case((32, 24, 16))
+    planes = (4, 28)
+    T = 100
+    N = case.ncells
+    lat = gpu.Lattice(case, storage="f32")
+    lam = lat.new_adjoint()
+    grad = torch.zeros(N, dtype=torch.float32, device="cuda")
+    snaps = lat.new_state_buffer(11)
+    gpu.lbm_gradient(lat.ctx, T, planes, snaps, 11, lam, grad)
+    g = grad.cpu().numpy().astype(np.float64)
+    cells = I.sample_cells(N, 8, seed_offset=5)
+    fd = []
+    h = 1e-6
+    for cell in cells:
+        Js = []
+        for sgn in (1, -1):
+            c2 = _case((32, 24, 16))
+            c2.porosity = case.porosity.copy()
+            c2.porosity[cell] += sgn * h
+            Js.append(oracle_for(c2, T).objective(planes)[0])
+        fd.append((Js[0] - Js[1]) / (2 * h))
+    fd = np.array(fd)
+    scale = np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
+    err = np.abs(g[cells] - fd) / scale
+    announce(f"fp32 gradient vs FD: max rel {err.max():.3e}")
+    assert err.max() <= 1e-4
+
+
+def test_autograd_function(gpu):
+    from paper_2506_21804_amd.autograd import objective
+    case = _case((16, 12, 8))
+    planes = (2, 13)
+    phi = torch.tensor(case.porosity, dtype=torch.float64, requires_grad=True)
+    J = objective(phi, case, storage="f64", T=12, planes=planes, nsnap=3)
+    J.backward()
+    orc = oracle_for(case, 12)
+    assert abs(J.item() - orc.objective(planes)[0]) <= 1e-12 * abs(J.item())
+    cell = int(I.sample_cells(case.ncells, 1, seed_offset=9)[0])
+    t = oracle_for(case, tangent=True)
+    e = np.zeros(case.ncells)
+    e[cell] = 1.0
+    t.set_phi_tangent(e)
+    t.step(12)
+    _, dJ = t.objective(planes)
+    g = phi.grad.numpy()
+    assert abs(g[cell] - dJ) <= 1e-10 * max(abs(dJ), 1e-3 * np.abs(g).max())
