@@ -112,6 +112,9 @@ int lbm_diagnostics(lbm_ctx *ctx, double out[4]);
 /* Waits for the stream and reports kernel-side faults. */
 int lbm_sync(lbm_ctx *ctx);
 
+/* Shape of a context: out = {q, nx, ny, nz, storage}. */
+int lbm_shape(const lbm_ctx *ctx, int out[5]);
+
 /* Number of time steps taken since lbm_init (or the loaded state). */
 long long lbm_steps_done(const lbm_ctx *ctx);
 

@@ -16,7 +16,7 @@ import numpy as np
 
 __all__ = [
     "load", "LbmError", "Params", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_moments",
-    "lbm_diagnostics", "lbm_sync", "lbm_steps_done", "lbm_get_populations", "lbm_set_populations",
+    "lbm_diagnostics", "lbm_sync", "lbm_steps_done", "lbm_shape", "lbm_get_populations", "lbm_set_populations",
     "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes",
     "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural",
     "lbm_gradient", "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
@@ -75,6 +75,7 @@ def load():
         "lbm_diagnostics": (i, [vp, vp]),
         "lbm_sync": (i, [vp]),
         "lbm_steps_done": (ll, [vp]),
+        "lbm_shape": (i, [vp, vp]),
         "lbm_get_populations": (i, [vp, vp]),
         "lbm_set_populations": (i, [vp, vp]),
         "lbm_state_bytes": (sz, [vp]),
@@ -105,7 +106,7 @@ def load():
 
 def exported_symbols():
     return ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_moments", "lbm_diagnostics", "lbm_sync",
-            "lbm_steps_done", "lbm_get_populations", "lbm_set_populations", "lbm_state_bytes",
+            "lbm_steps_done", "lbm_shape", "lbm_get_populations", "lbm_set_populations", "lbm_state_bytes",
             "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes", "lbm_adjoint_seed",
             "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural", "lbm_gradient",
             "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
@@ -113,8 +114,39 @@ def exported_symbols():
 
 
 def _dptr(t):
-    """Device pointer of a torch tensor (or None)."""
-    return None if t is None else C.c_void_p(t.data_ptr())
+    """Device pointer of a torch tensor (or None); refuses anything that is
+    not a contiguous tensor in GPU memory."""
+    if t is None:
+        return None
+    if not hasattr(t, "data_ptr") or not getattr(t, "is_cuda", False):
+        raise ValueError("device buffer expected: pass a torch tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("device buffer must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _dbuf(t, nbytes, what, dtype=None):
+    """Checks a device buffer's placement, size (bytes) and dtype."""
+    p = _dptr(t)
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{what}: buffer of {t.numel() * t.element_size()} bytes, need {nbytes}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what}: dtype {t.dtype}, need {dtype}")
+    return p
+
+
+def lbm_shape(ctx):
+    out = (C.c_int * 5)()
+    _check(ctx, load().lbm_shape(ctx, out))
+    return tuple(out[:])
+
+
+def _sizes(ctx):
+    """(q, N, compute dtype, compute bytes) of a context."""
+    import torch
+    q, nx, ny, nz, storage = lbm_shape(ctx)
+    f64 = storage == F64
+    return q, nx * ny * nz, (torch.float64 if f64 else torch.float32), (8 if f64 else 4)
 
 
 def _hptr(a):
@@ -152,6 +184,16 @@ def lbm_workspace_bytes(p: Params, mask=None, porous=False) -> int:
 
 
 def lbm_init(p: Params, mask, wall_dist, porosity, rho0_dev, u0_dev, workspace):
+    import torch
+    N = p.nx * p.ny * p.nz
+    for a, name in ((mask, "mask"), (wall_dist, "wall_dist"), (porosity, "porosity")):
+        if a is not None and np.asarray(a).size != N:
+            raise ValueError(f"{name} must have nx*ny*nz = {N} entries")
+    if rho0_dev is not None:
+        _dbuf(rho0_dev, 8 * N, "rho0", torch.float64)
+    if u0_dev is not None:
+        _dbuf(u0_dev, 24 * N, "u0", torch.float64)
+    _dbuf(workspace, 1, "workspace")
     keep = [None if a is None else np.ascontiguousarray(a, dtype=dt)
             for a, dt in ((mask, np.uint8), (wall_dist, np.float64), (porosity, np.float64))]
     ctx = C.c_void_p()
@@ -167,7 +209,10 @@ def lbm_step(ctx, n=1):
 
 
 def lbm_moments(ctx, rho, u):
-    _check(ctx, load().lbm_moments(ctx, _dptr(rho), _dptr(u)))
+    q, N, dt, cb = _sizes(ctx)
+    r = None if rho is None else _dbuf(rho, N * cb, "rho", dt)
+    v = None if u is None else _dbuf(u, 3 * N * cb, "u", dt)
+    _check(ctx, load().lbm_moments(ctx, r, v))
 
 
 def lbm_diagnostics(ctx):
@@ -185,11 +230,13 @@ def lbm_steps_done(ctx) -> int:
 
 
 def lbm_get_populations(ctx, f):
-    _check(ctx, load().lbm_get_populations(ctx, _dptr(f)))
+    q, N, dt, cb = _sizes(ctx)
+    _check(ctx, load().lbm_get_populations(ctx, _dbuf(f, q * N * cb, "populations", dt)))
 
 
 def lbm_set_populations(ctx, f):
-    _check(ctx, load().lbm_set_populations(ctx, _dptr(f)))
+    q, N, dt, cb = _sizes(ctx)
+    _check(ctx, load().lbm_set_populations(ctx, _dbuf(f, q * N * cb, "populations", dt)))
 
 
 def lbm_state_bytes(ctx) -> int:
@@ -197,11 +244,11 @@ def lbm_state_bytes(ctx) -> int:
 
 
 def lbm_save_state(ctx, dst):
-    _check(ctx, load().lbm_save_state(ctx, _dptr(dst)))
+    _check(ctx, load().lbm_save_state(ctx, _dbuf(dst, lbm_state_bytes(ctx), "state")))
 
 
 def lbm_load_state(ctx, src):
-    _check(ctx, load().lbm_load_state(ctx, _dptr(src)))
+    _check(ctx, load().lbm_load_state(ctx, _dbuf(src, lbm_state_bytes(ctx), "state")))
 
 
 def lbm_objective(ctx, planes) -> float:
@@ -215,28 +262,39 @@ def lbm_adjoint_bytes(ctx) -> int:
     return load().lbm_adjoint_bytes(ctx)
 
 
+def _lam(ctx, t, what="adjoint"):
+    q, N, dt, cb = _sizes(ctx)
+    return _dbuf(t, q * N * cb, what, dt)
+
+
+def _grad(ctx, t):
+    q, N, dt, cb = _sizes(ctx)
+    return _dbuf(t, N * cb, "grad_phi", dt)
+
+
 def lbm_adjoint_seed(ctx, planes, lam):
     pl = (C.c_int * 2)(*planes)
-    _check(ctx, load().lbm_adjoint_seed(ctx, pl, _dptr(lam)))
+    _check(ctx, load().lbm_adjoint_seed(ctx, pl, _lam(ctx, lam)))
 
 
 def lbm_adjoint_step(ctx, lam, grad):
-    _check(ctx, load().lbm_adjoint_step(ctx, _dptr(lam), _dptr(grad)))
+    _check(ctx, load().lbm_adjoint_step(ctx, _lam(ctx, lam), _grad(ctx, grad)))
 
 
 def lbm_adjoint_to_natural(ctx, lam, nat):
-    _check(ctx, load().lbm_adjoint_to_natural(ctx, _dptr(lam), _dptr(nat)))
+    _check(ctx, load().lbm_adjoint_to_natural(ctx, _lam(ctx, lam), _lam(ctx, nat, "natural")))
 
 
 def lbm_adjoint_from_natural(ctx, nat, lam):
-    _check(ctx, load().lbm_adjoint_from_natural(ctx, _dptr(nat), _dptr(lam)))
+    _check(ctx, load().lbm_adjoint_from_natural(ctx, _lam(ctx, nat, "natural"), _lam(ctx, lam)))
 
 
 def lbm_gradient(ctx, T, planes, snapshots, nsnap, lam, grad):
     pl = (C.c_int * 2)(*planes)
     J = C.c_double()
     nf = C.c_longlong()
-    _check(ctx, load().lbm_gradient(ctx, int(T), pl, _dptr(snapshots), int(nsnap), _dptr(lam), _dptr(grad),
+    snaps = _dbuf(snapshots, int(nsnap) * lbm_state_bytes(ctx), "snapshots")
+    _check(ctx, load().lbm_gradient(ctx, int(T), pl, snaps, int(nsnap), _lam(ctx, lam), _grad(ctx, grad),
                                     C.byref(J), C.byref(nf)))
     return J.value, nf.value
 

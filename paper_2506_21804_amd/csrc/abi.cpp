@@ -355,6 +355,16 @@ int lbm_diagnostics(lbm_ctx *ctx, double out[4]) {
 
 long long lbm_steps_done(const lbm_ctx *ctx) { return ctx ? ctx->steps : -1; }
 
+int lbm_shape(const lbm_ctx *ctx, int out[5]) {
+  if (!ctx || !out) return LBM_EINVAL;
+  out[0] = ctx->q;
+  out[1] = ctx->p.nx;
+  out[2] = ctx->p.ny;
+  out[3] = ctx->p.nz;
+  out[4] = ctx->p.storage;
+  return LBM_OK;
+}
+
 int lbm_get_populations(lbm_ctx *ctx, void *f) {
   if (!ctx || !f) return ctx ? set_err(ctx, LBM_EINVAL, "null output") : LBM_EINVAL;
   return dev_export(ctx, f);

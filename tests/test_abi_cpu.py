@@ -89,3 +89,13 @@ def test_revolve_brute_force_small():
     for l in range(1, 30):
         for snaps in range(1, 6):
             assert lbm.lbm_revolve_cost(l, snaps) == best(l, snaps - 1)
+
+
+def test_binding_refuses_host_buffers():
+    """Device pointers come only from GPU tensors: a host array or CPU tensor
+    is refused before any library call."""
+    import torch
+    with pytest.raises(ValueError):
+        lbm._dptr(torch.zeros(4))
+    with pytest.raises(ValueError):
+        lbm._dptr(np.zeros(4))

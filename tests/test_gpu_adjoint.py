@@ -52,7 +52,7 @@ def test_transpose_one_step(gpu):
         lat.save_state(snap)
         lat.step(1)
         lam = lat.new_adjoint()
-        gpu.lbm_adjoint_from_natural(lat.ctx, torch.as_tensor(wv), lam)
+        gpu.lbm_adjoint_from_natural(lat.ctx, torch.as_tensor(wv, device="cuda"), lam)
         lat.load_state(snap)
         grad = torch.zeros(N, dtype=torch.float64, device="cuda")
         gpu.lbm_adjoint_step(lat.ctx, lam, grad)
