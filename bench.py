@@ -235,7 +235,7 @@ def bench_adjoint(args, torch, lbm, case, storage, wname):
     lat.sync()
     fwd_ms = e[0].elapsed_time(e[1]) / K
     lam = lat.new_adjoint()
-    grad = torch.zeros(N, dtype=lat.rdtype, device="cuda")
+    grad = lat.new_gradient()
     lbm.lbm_adjoint_seed(lat.ctx, planes, lam)
     lat.sync()
     e[2].record(stream)

@@ -139,13 +139,14 @@ int lbm_load_state(lbm_ctx *ctx, const void *src);
 int lbm_objective(lbm_ctx *ctx, const int planes[2], double *J);
 
 /* Discrete adjoint.  An adjoint field lambda has the layout of the state
- * (q arrays of N entries of the compute type, in-memory AA order of the
- * current step parity); it is caller device memory of lbm_adjoint_bytes().
+ * (q arrays of N doubles, in-memory AA order of the current step parity) for
+ * every storage mode; it is caller device memory of lbm_adjoint_bytes().
+ * Adjoint arithmetic and grad_phi are FP64 for every storage mode.
  *  lbm_adjoint_seed: lambda = dJ/df of the current state (async).
  *  lbm_adjoint_step: given lambda = dJ/df^{n+1} and the state f^n currently
  *    held by the context (step counter n), overwrites lambda with dJ/df^n
- *    and adds dJ/dphi contributions of step n to grad_phi [N] (compute
- *    type); decrements nothing (the caller restores f^{n-1} itself). Async.
+ *    and adds dJ/dphi contributions of step n to grad_phi [N] (double);
+ *    decrements nothing (the caller restores f^{n-1} itself). Async.
  *  lbm_adjoint_to_natural / _from_natural: convert lambda between the
  *    in-memory layout of the current parity and natural [q][N] order. */
 size_t lbm_adjoint_bytes(const lbm_ctx *ctx);
@@ -157,8 +158,8 @@ int lbm_adjoint_from_natural(lbm_ctx *ctx, const void *natural, void *lambda);
 /* Gradient dJ/dphi after T steps from the current state (which becomes step
  * 0 of the sweep), by a binomial checkpointing reverse sweep (Griewank-
  * Walther): snapshots is caller device memory for nsnap >= 1 states of
- * lbm_state_bytes() each, lambda of lbm_adjoint_bytes(), grad_phi [N] of
- * the compute type (overwritten).  *J receives the objective at step T, and
+ * lbm_state_bytes() each, lambda of lbm_adjoint_bytes(), grad_phi [N] doubles
+ * (overwritten).  *J receives the objective at step T, and
  * *nforward the number of forward steps taken (T plus recomputation).  On
  * return the context holds the state of step 0 again.  Synchronises. */
 int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,

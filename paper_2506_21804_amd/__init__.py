@@ -263,13 +263,15 @@ def lbm_adjoint_bytes(ctx) -> int:
 
 
 def _lam(ctx, t, what="adjoint"):
+    import torch
     q, N, dt, cb = _sizes(ctx)
-    return _dbuf(t, q * N * cb, what, dt)
+    return _dbuf(t, q * N * 8, what, torch.float64)
 
 
 def _grad(ctx, t):
+    import torch
     q, N, dt, cb = _sizes(ctx)
-    return _dbuf(t, N * cb, "grad_phi", dt)
+    return _dbuf(t, N * 8, "grad_phi", torch.float64)
 
 
 def lbm_adjoint_seed(ctx, planes, lam):
@@ -429,7 +431,11 @@ class Lattice:
         return lbm_objective(self.ctx, planes)
 
     def new_adjoint(self):
-        return self.torch.zeros((self.q, self.N), dtype=self.rdtype, device="cuda")
+        """Adjoint populations (FP64 for every storage mode)."""
+        return self.torch.zeros((self.q, self.N), dtype=self.torch.float64, device="cuda")
+
+    def new_gradient(self):
+        return self.torch.zeros(self.N, dtype=self.torch.float64, device="cuda")
 
     def wall_records(self):
         return lbm_wall_records(self.ctx)

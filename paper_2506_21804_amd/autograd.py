@@ -29,7 +29,7 @@ class LbmObjective(torch.autograd.Function):
         lat = Lattice(c, storage=storage)
         if phi.requires_grad:
             lam = lat.new_adjoint()
-            grad = torch.zeros(lat.N, dtype=lat.rdtype, device="cuda")
+            grad = lat.new_gradient()
             snaps = torch.empty(nsnap * lbm_state_bytes(lat.ctx), dtype=torch.uint8, device="cuda")
             J, _ = lbm_gradient(lat.ctx, T, planes, snaps, nsnap, lam, grad)
             ctx.save_for_backward(grad.to(phi.device, phi.dtype).reshape(phi.shape))

@@ -425,7 +425,7 @@ int lbm_objective(lbm_ctx *ctx, const int planes[2], double *J) {
 
 size_t lbm_adjoint_bytes(const lbm_ctx *ctx) {
   if (!ctx) return 0;
-  return (size_t)ctx->q * ctx->N * compute_bytes(ctx->p.storage);
+  return (size_t)ctx->q * ctx->N * sizeof(double);
 }
 
 int lbm_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lambda) {
@@ -471,7 +471,7 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
   double Jv = 0.0;
   if ((rc = lbm_objective(ctx, planes, &Jv)) != LBM_OK) return rc;
   if ((rc = lbm_adjoint_seed(ctx, planes, lambda)) != LBM_OK) return rc;
-  if ((rc = dev_fill(ctx, grad_phi, (size_t)ctx->N * compute_bytes(ctx->p.storage))) != LBM_OK) return rc;
+  if ((rc = dev_fill(ctx, grad_phi, (size_t)ctx->N * sizeof(double))) != LBM_OK) return rc;
   // reverse sweep along the binomial schedule
   const std::vector<Action> acts = revolve_schedule(T, nsnap);
   long long have = -1;  // step index held by the context, relative to step0 (-1: not a scheduled state)

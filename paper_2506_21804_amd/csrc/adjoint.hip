@@ -12,6 +12,12 @@
 // forward step; streaming and bounce-back need no code of their own.
 // The Frobenius norm of the stress has no derivative at zero; its adjoint is
 // taken as 0 there.
+//
+// The adjoint field, the gradient and all adjoint arithmetic are FP64 for
+// every storage mode: adjoint populations carry a large per-cell common mode
+// (from the density terms of the objective) that cancels exactly in the
+// porosity sensitivity, and FP32 rounding of that cancellation swamps the
+// gradient.  The forward state is read in its stored precision and widened.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -200,10 +206,9 @@ __device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi
 
 template <int Q, typename S, bool ODD, bool POROUS, bool SOLID>
 __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
-                                                    typename Store<S>::R *__restrict__ lam,
+                                                    double *__restrict__ lam,
                                                     const typename Store<S>::R *__restrict__ phi,
-                                                    typename Store<S>::R *__restrict__ grad, KArgs k, ATiles t) {
-  using R = typename Store<S>::R;
+                                                    double *__restrict__ grad, KArgs k, ATiles t) {
   int x, y, z;
   if (!atile_xyz(k, t, x, y, z)) return;
   const Nb n = make_nb(x, y, z, k);
@@ -212,25 +217,25 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
   unsigned sm = 0;
   if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
   const size_t N = (size_t)k.N;
-  R mu[Q];
+  double mu[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) mu[i] = lam[write_slot<Q, ODD>(n, sm, i, N)];
-  R gb[Q];
+  double gb[Q];
   if (fl & FL_LID) {
     // the lid output does not depend on the state
 #pragma unroll
-    for (int i = 0; i < Q; ++i) gb[i] = R(0);
+    for (int i = 0; i < Q; ++i) gb[i] = 0.0;
   } else {
     if (x >= k.fringe_start) {
-      const R l = static_cast<const R *>(k.lam)[x];
+      const double l = (double)static_cast<const typename Store<S>::R *>(k.lam)[x];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) mu[i] *= (R(1) - l);
+      for (int i = 0; i < Q; ++i) mu[i] *= (1.0 - l);
     }
-    R g[Q];
+    double g[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
-    const R ph = POROUS ? phi[n.cell] : R(1);
-    const R phib = collide_bulk_vjp<Q, R, POROUS>(g, mu, ph, k, gb);
+    for (int i = 0; i < Q; ++i) g[i] = (double)Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+    const double ph = POROUS ? (double)phi[n.cell] : 1.0;
+    const double phib = collide_bulk_vjp<Q, double, POROUS>(g, mu, ph, k, gb);
     if (POROUS) grad[n.cell] += phib;
   }
 #pragma unroll
@@ -242,9 +247,8 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
 // counts come from the objective reduction already in cnt[0..2].
 template <int Q, typename S, bool ODD, bool SOLID>
 __global__ __launch_bounds__(ABLOCK) void k_seed(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
-                                                 typename Store<S>::R *__restrict__ lam, KArgs k, ATiles t, int p0,
+                                                 double *__restrict__ lam, KArgs k, ATiles t, int p0,
                                                  int p1, const double *__restrict__ cnt) {
-  using R = typename Store<S>::R;
   int x, y, z;
   if (!atile_xyz(k, t, x, y, z)) return;
   const Nb n = make_nb(x, y, z, k);
@@ -273,7 +277,7 @@ __global__ __launch_bounds__(ABLOCK) void k_seed(const S *__restrict__ pop, cons
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double cu = dot3(Lat<Q>::c(i, 0), Lat<Q>::c(i, 1), Lat<Q>::c(i, 2), ux, uy, uz);
-    lam[read_slot<Q, ODD>(n, sm, i, N)] = (R)(base + (cu - 0.5 * uu) * inf);
+    lam[read_slot<Q, ODD>(n, sm, i, N)] = base + (cu - 0.5 * uu) * inf;
   }
 }
 
@@ -329,8 +333,8 @@ int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv) {
   const ATiles t = atiles_of(ctx->ka);
   return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
     using R = typename Store<S>::R;
-    R *lam = (R *)lamv;
-    R *grad = (R *)gradv;
+    double *lam = (double *)lamv;
+    double *grad = (double *)gradv;
     const R *phi = (const R *)ctx->phi;
     if (ctx->porous)
       k_adjoint<Q, S, ODD, true, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, lam,
@@ -347,8 +351,7 @@ int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lamv) {
   if (rc != LBM_OK) return rc;
   const ATiles t = atiles_of(ctx->ka);
   return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
-    using R = typename Store<S>::R;
-    k_seed<Q, S, ODD, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, (R *)lamv, ctx->ka,
+    k_seed<Q, S, ODD, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, (double *)lamv, ctx->ka,
                                                                    t, planes[0], planes[1], ctx->result + 8 + 3);
     return check(ctx, "k_seed");
   });
@@ -357,9 +360,8 @@ int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lamv) {
 int dev_layout_to_natural(lbm_ctx *ctx, const void *lamv, void *natv) {
   const ATiles t = atiles_of(ctx->ka);
   return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
-    using R = typename Store<S>::R;
-    k_relayout<Q, ODD, SOLID, true, R><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, (const R *)lamv, (R *)natv,
-                                                                           ctx->ka, t);
+    k_relayout<Q, ODD, SOLID, true, double><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, (const double *)lamv,
+                                                                                (double *)natv, ctx->ka, t);
     return check(ctx, "k_relayout");
   });
 }
@@ -367,9 +369,8 @@ int dev_layout_to_natural(lbm_ctx *ctx, const void *lamv, void *natv) {
 int dev_layout_from_natural(lbm_ctx *ctx, const void *natv, void *lamv) {
   const ATiles t = atiles_of(ctx->ka);
   return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
-    using R = typename Store<S>::R;
-    k_relayout<Q, ODD, SOLID, false, R><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, (const R *)natv, (R *)lamv,
-                                                                            ctx->ka, t);
+    k_relayout<Q, ODD, SOLID, false, double><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, (const double *)natv,
+                                                                                 (double *)lamv, ctx->ka, t);
     return check(ctx, "k_relayout");
   });
 }
