@@ -158,10 +158,14 @@ int lbm_adjoint_from_natural(lbm_ctx *ctx, const void *natural, void *lambda);
 /* Gradient dJ/dphi after T steps from the current state (which becomes step
  * 0 of the sweep), by a binomial checkpointing reverse sweep (Griewank-
  * Walther): snapshots is caller device memory for nsnap >= 1 states of
- * lbm_state_bytes() each, lambda of lbm_adjoint_bytes(), grad_phi [N] doubles
- * (overwritten).  *J receives the objective at step T, and
- * *nforward the number of forward steps taken (T plus recomputation).  On
- * return the context holds the state of step 0 again.  Synchronises. */
+ * lbm_state_bytes() each, lambda of lbm_adjoint_bytes(), grad_phi [N]
+ * doubles (overwritten).  The schedule's first descent doubles as the
+ * forward sweep: it stores checkpoints on its way to step T-1, takes one
+ * more step for the objective and the seed, and re-advances from the last
+ * checkpoint to T-1.  *J receives the objective at step T and *nforward the
+ * forward steps taken (lbm_revolve_cost(T, nsnap) + 1 + that re-advance; T
+ * exactly when nsnap > T).  On return the context holds the state of step 0
+ * again.  Synchronises.  Not available with the wall model. */
 int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
                  void *grad_phi, double *J, long long *nforward);
 

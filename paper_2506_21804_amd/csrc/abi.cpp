@@ -465,19 +465,22 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
   int rc = lbm_save_state(ctx, slot(0));
   if (rc != LBM_OK) return rc;
   const long long step0 = ctx->steps;
-  // forward sweep to T for the objective and the seed
-  if ((rc = lbm_step(ctx, T)) != LBM_OK) return rc;
-  fwd += T;
-  double Jv = 0.0;
-  if ((rc = lbm_objective(ctx, planes, &Jv)) != LBM_OK) return rc;
-  if ((rc = lbm_adjoint_seed(ctx, planes, lambda)) != LBM_OK) return rc;
   if ((rc = dev_fill(ctx, grad_phi, (size_t)ctx->N * sizeof(double))) != LBM_OK) return rc;
-  // reverse sweep along the binomial schedule
+  // The binomial schedule's first descent is the forward sweep: it stores
+  // its checkpoints on the way to step T-1.  There, one more step gives the
+  // final state for the objective and the seed; then the last restored
+  // checkpoint is advanced back to T-1 and the reverse sweep starts.
   const std::vector<Action> acts = revolve_schedule(T, nsnap);
-  long long have = -1;  // step index held by the context, relative to step0 (-1: not a scheduled state)
+  long long have = 0;  // step index held by the context, relative to step0
+  int last_slot = 0;
+  long long last_step = 0;
+  bool seeded = false;
+  double Jv = 0.0;
   for (const Action &a : acts) {
     switch (a.kind) {
       case ACT_RESTORE:
+        last_slot = a.arg;
+        last_step = a.step;
         if (have != a.step) {
           if ((rc = lbm_load_state(ctx, slot(a.arg))) != LBM_OK) return rc;
           have = a.step;
@@ -492,6 +495,20 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
         if ((rc = lbm_save_state(ctx, slot(a.arg))) != LBM_OK) return rc;
         break;
       case ACT_REVERSE:
+        if (!seeded) {
+          if (a.arg != T - 1 || have != T - 1) return set_err(ctx, LBM_EINVAL, "internal: schedule out of step");
+          if ((rc = lbm_step(ctx, 1)) != LBM_OK) return rc;
+          fwd += 1;
+          if ((rc = lbm_objective(ctx, planes, &Jv)) != LBM_OK) return rc;
+          if ((rc = lbm_adjoint_seed(ctx, planes, lambda)) != LBM_OK) return rc;
+          if ((rc = lbm_load_state(ctx, slot(last_slot))) != LBM_OK) return rc;
+          if (T - 1 > last_step) {
+            if ((rc = lbm_step(ctx, (int)(T - 1 - last_step))) != LBM_OK) return rc;
+            fwd += T - 1 - last_step;
+          }
+          have = T - 1;
+          seeded = true;
+        }
         if (ctx->steps != step0 + a.arg) return set_err(ctx, LBM_EINVAL, "internal: schedule out of step");
         if ((rc = dev_adjoint_step(ctx, lambda, grad_phi)) != LBM_OK) return rc;
         break;
