@@ -47,14 +47,23 @@ class Params(C.Structure):
 
 
 _lib = None
+_lib_override = None  # path of an alternative build (mutation tests)
+
+
+def use_library(path):
+    """Points the loader at another build of the oracle (None = the normal
+    one); used by the mutation tests to load deliberately broken copies."""
+    global _lib, _lib_override
+    _lib = None
+    _lib_override = path
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _lib_override is None and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(_lib_override or _LIB)
         vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
         L.orc_create.restype = vp
         L.orc_create.argtypes = [C.POINTER(Params), vp, vp, vp, vp, vp, C.c_int]

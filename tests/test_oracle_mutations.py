@@ -1,0 +1,83 @@
+"""Mutation check of the oracle's pins: each case plants one plausible
+mistake in a copy of the oracle's source (a dropped or changed term, a wrong
+sign, a swapped index or direction), builds that copy on the CPU, and runs
+the pin tests against it.  Every mutant must fail at least one pin; a mutant
+that passes them all would mean the pins leave that part of the oracle
+unchecked."""
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle as O
+import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(O.__file__), "lbm_oracle.cpp")
+
+# (name, exact text in the oracle, replacement)
+MUTATIONS = [
+    ("half-force velocity shift dropped", "u[a] = (j[a] + 0.5 * p.force[a]) / rho;\n    T feq[27];",
+     "u[a] = (j[a] + 0.0 * p.force[a]) / rho;\n    T feq[27];"),
+    ("Guo source prefactor sign", "(1.0 - 0.5 / tau) * guo_term(vs, i, u, p.force)",
+     "(1.0 + 0.5 / tau) * guo_term(vs, i, u, p.force)"),
+    ("equilibrium second-order coefficient", "4.5 * cv * cv", "3.0 * cv * cv"),
+    ("Smagorinsky coefficient", "18.0 * std::sqrt(2.0)", "9.0 * std::sqrt(2.0)"),
+    ("stress tensor index", "double(vs.c[i][a] * vs.c[i][b]) * fneq", "double(vs.c[i][a] * vs.c[i][a]) * fneq"),
+    ("streaming direction in x", "neighbor_xyz(x, y, z, -vs.c[i][0], -vs.c[i][1], -vs.c[i][2])",
+     "neighbor_xyz(x, y, z, vs.c[i][0], -vs.c[i][1], -vs.c[i][2])"),
+    ("bounce-back into the same direction", "fs[(size_t)vs.opp[i] * N + c]", "fs[(size_t)i * N + c]"),
+    ("porosity ignored", "uh[a] = phi[c] * u[a];", "uh[a] = u[a];"),
+    ("Spalding cubic term", "0.5 * k * k - k * k * k / 6.0", "0.5 * k * k - k * k * k / 3.0"),
+    ("wall non-equilibrium sign", "T ffd = -3.0 * vs.w[i]", "T ffd = 3.0 * vs.w[i]"),
+    ("stress-consistent strain", "4.0 * cs2 * utau * utau", "2.0 * cs2 * utau * utau"),
+    ("fringe ramp", "s * s * (3.0 - 2.0 * s)", "s * (3.0 - 2.0 * s)"),
+    ("D3Q27 corner weight", "1.0 / 216.0", "1.0 / 108.0"),
+    ("wall normal velocity kept", "uw[a] = wutan[k] * t[a] + un * n[a];", "uw[a] = wutan[k] * t[a];"),
+]
+
+PIN_TESTS = [
+    (pins.test_velocity_set_isotropy_exact, [(27, {0: pins.Fraction(8, 27), 1: pins.Fraction(2, 27),
+                                                  2: pins.Fraction(1, 54), 3: pins.Fraction(1, 216)})]),
+    (pins.test_equilibrium_moments, [(19,), (27,)]),
+    (pins.test_smagorinsky_relation, [(19,)]),
+    (pins.test_porosity_and_force_momentum, [(19,)]),
+    (pins.test_conservation_periodic, [(19,)]),
+    (pins.test_taylor_green_decay, [()]),
+    (pins.test_advected_shear_wave, [()]),
+    (pins.test_poiseuille_magic_tau, [()]),
+    (pins.test_spalding_closed_form_values, [()]),
+    (pins.test_wall_reconstruction_stress, [()]),
+    (pins.test_wall_model_channel_records, [(27,)]),
+    (pins.test_fringe_and_lid, [()]),
+]
+
+
+def _caught(lib_path):
+    O.use_library(lib_path)
+    failed = []
+    try:
+        for fn, arglists in PIN_TESTS:
+            for args in arglists:
+                try:
+                    fn(*args)
+                except (AssertionError, O.OracleError):
+                    failed.append(fn.__name__)
+                    break
+    finally:
+        O.use_library(None)
+    return failed
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_mutant(name, old, new, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site not unique: {old!r}"
+    mut = tmp_path / "mutant.cpp"
+    mut.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    cmd = [c if c != O._SRC else str(mut) for c in O.BUILD_CMD]
+    cmd[cmd.index(O._LIB)] = str(lib)
+    subprocess.run(cmd, check=True)
+    failed = _caught(str(lib))
+    assert failed, f"mutant '{name}' passed every pin"
