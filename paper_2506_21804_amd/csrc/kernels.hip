@@ -156,19 +156,15 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
 // ---------------------------------------------------------------------------
 // K2: fused gather / collide / scatter over all non-wall fluid cells.
 // ---------------------------------------------------------------------------
-template <int Q, typename S, bool ODD, bool POROUS, bool SOLID>
-__global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8_t *__restrict__ flags,
-                                                const typename Store<S>::R *__restrict__ phi, KArgs k,
-                                                Tiles t, int *__restrict__ errflag) {
+// Gather, collide, scatter of one cell.  With LINKS = false the cell has no
+// solid link (sm = 0) and every slot address is the plain AA one.
+template <int Q, typename S, bool ODD, bool POROUS, bool LINKS>
+__device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename Store<S>::R *__restrict__ phi,
+                                          const KArgs &k, const Nb &n, unsigned sm, uint8_t fl, int x, int z,
+                                          int *__restrict__ errflag) {
   using R = typename Store<S>::R;
-  int x, y, z;
-  if (!tile_xyz(k, t, blockIdx.x, x, y, z)) return;
-  const Nb n = make_nb(x, y, z, k);
-  const uint8_t fl = flags[n.cell];
-  if (!(fl & FL_FLUID) || (fl & FL_WALL)) return;
-  unsigned sm = 0;
-  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
   const size_t N = (size_t)k.N;
+  if (!LINKS) sm = 0u;
   R g[Q];
   if (fl & FL_LID) {
     lid_equilibrium<Q, R>(g, k);
@@ -181,6 +177,22 @@ __global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8
   fringe_blend<Q, R>(g, x, z, k);
 #pragma unroll
   for (int i = 0; i < Q; ++i) Store<S>::st(pop + write_slot<Q, ODD>(n, sm, i, N), g[i]);
+}
+
+template <int Q, typename S, bool ODD, bool POROUS, bool SOLID>
+__global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                const typename Store<S>::R *__restrict__ phi, KArgs k,
+                                                Tiles t, int *__restrict__ errflag) {
+  int x, y, z;
+  if (!tile_xyz(k, t, blockIdx.x, x, y, z)) return;
+  const Nb n = make_nb(x, y, z, k);
+  const uint8_t fl = flags[n.cell];
+  if (!(fl & FL_FLUID) || (fl & FL_WALL)) return;
+  unsigned sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  // cells without solid links (all but a thin layer) take the plain-address path
+  if (SOLID && ODD && sm != 0u) bulk_cell<Q, S, ODD, POROUS, true>(pop, phi, k, n, sm, fl, x, z, errflag);
+  else bulk_cell<Q, S, ODD, POROUS, false>(pop, phi, k, n, sm, fl, x, z, errflag);
 }
 
 // ---------------------------------------------------------------------------

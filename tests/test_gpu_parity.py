@@ -148,6 +148,19 @@ def test_porosity_fp64(gpu):
     assert abs(J - Jo) <= 1e-12 * abs(Jo), (J, Jo)
 
 
+def test_porosity_fp32(gpu):
+    case = I.porous_channel(shape=(40, 24, 12))
+    lat, orc, rho, u, orho, ou = _run_both(gpu, case, 100, "f32")
+    e_rho, e_u = rel_maxnorm(rho, orho), rel_maxnorm(u, ou)
+    msg = f"porous f32: rho {e_rho:.3e} u {e_u:.3e}"
+    announce(msg)
+    assert e_rho <= 1e-5 and e_u <= 1e-5, msg
+    J = lat.objective(case.extra["planes"])
+    Jo, _ = orc.objective(case.extra["planes"])
+    announce(f"porous f32 objective rel err {abs(J - Jo) / abs(Jo):.3e}")
+    assert abs(J - Jo) <= 1e-5 * abs(Jo), (J, Jo)
+
+
 def test_conservation_and_diagnostics(gpu):
     case = I.taylor_green(24, u0=0.05, q=27, cs_smag=0.1)
     lat = gpu.Lattice(case, storage="f64")
