@@ -8,8 +8,8 @@
  - the checkpointed gradient is bitwise equal to the full-storage one, and
    the sweep takes the binomial-optimal number of forward steps (plus the
    step to T and the re-advance to T-1);
- - the FP32 gradient matches FP64 central differences of the oracle within
-   1e-4 (|g - g_FD| / max(|g_FD|, 1e-3 max|g_FD|)).
+ - the FP32 gradient matches FP64 central differences (h = 1e-4) of the
+   oracle within 1e-4 (|g - g_FD| / max(|g_FD|, 1e-3 max|g_FD|)).
 """
 import numpy as np
 import pytest
@@ -126,7 +126,9 @@ def test_fp32_gradient_vs_central_differences(gpu):
     g = grad.cpu().numpy().astype(np.float64)
     cells = I.sample_cells(N, 8, seed_offset=5)
     fd = []
-    h = 1e-6
+    # central differences with h = 1e-4: rounding of J (about 1e-16 |J|) over 2h
+    # stays below 1e-6 of these gradients, truncation is O(h^2) ~ 1e-8
+    h = 1e-4
     for cell in cells:
         Js = []
         for sgn in (1, -1):
