@@ -13,11 +13,14 @@
 // The Frobenius norm of the stress has no derivative at zero; its adjoint is
 // taken as 0 there.
 //
-// The adjoint field, the gradient and all adjoint arithmetic are FP64 for
-// every storage mode: adjoint populations carry a large per-cell common mode
-// (from the density terms of the objective) that cancels exactly in the
-// porosity sensitivity, and FP32 rounding of that cancellation swamps the
-// gradient.  The forward state is read in its stored precision and widened.
+// Precision.  Adjoint populations carry a large per-cell common mode (from
+// the density terms of the objective) next to small informative parts, so
+// the adjoint field and the gradient are stored in FP64 for every storage
+// mode.  The collision conserves mass for every state and porosity, so its
+// vector-Jacobian product maps a constant vector m 1 to itself and gives it
+// no porosity sensitivity: each cell subtracts m = mu_0 (in FP64), pushes
+// only the deviations mu_i - m through the product in the compute precision
+// (FP32 for FP32/FP16 storage), and adds m back when it stores.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -49,11 +52,12 @@ __device__ __forceinline__ bool atile_xyz(const KArgs &k, ATiles t, int &x, int 
   return x < k.nx && y < k.ny;
 }
 
-// Vector-Jacobian product of the bulk collision: given the populations g
-// (deviations) and the adjoints mu of the outputs, returns the adjoints of
-// the inputs in gb and the porosity adjoint.
-template <int Q, typename R, bool POROUS>
-__device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi, const KArgs &k, R gb[Q]) {
+// Vector-Jacobian product of the bulk collision in precision R.  g holds the
+// state deviations, mu the adjoints of the outputs; the adjoint of input
+// population i is handed to out(i, value) as soon as it is known, and the
+// porosity adjoint is returned.
+template <int Q, typename R, bool POROUS, typename OUT>
+__device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi, const KArgs &k, OUT out) {
   // ---- forward recomputation
   R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
   R mxx = R(0), myy = R(0), mzz = R(0), mxy = R(0), mxz = R(0), myz = R(0);
@@ -95,32 +99,33 @@ __device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi
   const R uF = ux * Fx + uy * Fy + uz * Fz;
 
   // ---- reverse through the output combination
+  //   out_i = gv_i + c1 (g_i - gu_i) + c2 guo_i
   R c1b = R(0), c2b = R(0);
-  R au0 = R(0), au1 = R(0), aux = R(0), auy = R(0), auz = R(0);  // from gu (equilibrium at u)
-  R av0 = R(0), av1 = R(0), avx = R(0), avy = R(0), avz = R(0);  // from gv (equilibrium at v)
-  R b0 = R(0), bx = R(0), by = R(0), bz = R(0);                  // from the Guo term
+  R au0 = R(0), au1 = R(0), aux = R(0), auy = R(0), auz = R(0);  // equilibrium at u (and at v = u)
+  R av0 = R(0), av1 = R(0), avx = R(0), avy = R(0), avz = R(0);  // equilibrium at v = phi u
+  R b0 = R(0), bx = R(0), by = R(0), bz = R(0);                  // Guo term
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
     const R w = R(Lat<Q>::w(i));
     const R cu = dot3(cx, cy, cz, ux, uy, uz);
     const R cF = dot3(cx, cy, cz, Fx, Fy, Fz);
-    const R gu = w * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+    const R eu = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+    const R gu = w * (drho + rho * eu);
     const R guo = w * (R(3) * (cF - uF) + R(9) * cu * cF);
     const R m = mu[i];
     c1b += m * (g[i] - gu);
     c2b += m * guo;
-    gb[i] = c1 * m;
-    // adjoint of gu: -c1 m ; of gv: m ; of guo: c2 m (each times w folded below)
-    const R su = -c1 * m * w;
+    // adjoint weights of gu (-c1 m), gv (m) and guo (c2 m), each times w
+    const R su = POROUS ? -c1 * m * w : (R(1) - c1) * m * w;
     au0 += su;
-    au1 += su * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+    au1 += su * eu;
     const R tu = su * (R(3) + R(9) * cu);
     acc(aux, cx, tu);
     acc(auy, cy, tu);
     acc(auz, cz, tu);
-    const R sv = m * w;
     if (POROUS) {
+      const R sv = m * w;
       const R cv = dot3(cx, cy, cz, vx, vy, vz);
       av0 += sv;
       av1 += sv * (R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv);
@@ -128,14 +133,6 @@ __device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi
       acc(avx, cx, tv);
       acc(avy, cy, tv);
       acc(avz, cz, tv);
-    } else {
-      // v = u: accumulate into the u terms directly
-      au0 += sv;
-      au1 += sv * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
-      const R tv = sv * (R(3) + R(9) * cu);
-      acc(aux, cx, tv);
-      acc(auy, cy, tv);
-      acc(auz, cz, tv);
     }
     const R sg = c2 * m * w;
     b0 += sg;
@@ -185,11 +182,11 @@ __device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi
   irb += uxb * mx + uyb * my + uzb * mz;
   rhob -= irb * ir * ir;
   drhob += rhob;
-  // moments -> populations
+  // moments -> populations, plus the direct c1 path of g_i
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
-    R s = drhob;
+    R s = drhob + c1 * mu[i];
     acc(s, cx, mxb);
     acc(s, cy, myb);
     acc(s, cz, mzb);
@@ -199,7 +196,7 @@ __device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi
     acc(s, cx * cy, pxyb);
     acc(s, cx * cz, pxzb);
     acc(s, cy * cz, pyzb);
-    gb[i] += s;
+    out(i, s);
   }
   return phib;
 }
@@ -209,6 +206,7 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
                                                     double *__restrict__ lam,
                                                     const typename Store<S>::R *__restrict__ phi,
                                                     double *__restrict__ grad, KArgs k, ATiles t) {
+  using R = typename Store<S>::R;
   int x, y, z;
   if (!atile_xyz(k, t, x, y, z)) return;
   const Nb n = make_nb(x, y, z, k);
@@ -217,29 +215,27 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
   unsigned sm = 0;
   if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
   const size_t N = (size_t)k.N;
-  double mu[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) mu[i] = lam[write_slot<Q, ODD>(n, sm, i, N)];
-  double gb[Q];
   if (fl & FL_LID) {
     // the lid output does not depend on the state
 #pragma unroll
-    for (int i = 0; i < Q; ++i) gb[i] = 0.0;
-  } else {
-    if (x >= k.fringe_start) {
-      const double l = (double)static_cast<const typename Store<S>::R *>(k.lam)[x];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) mu[i] *= (1.0 - l);
-    }
-    double g[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) g[i] = (double)Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
-    const double ph = POROUS ? (double)phi[n.cell] : 1.0;
-    const double phib = collide_bulk_vjp<Q, double, POROUS>(g, mu, ph, k, gb);
-    if (POROUS) grad[n.cell] += phib;
+    for (int i = 0; i < Q; ++i) lam[read_slot<Q, ODD>(n, sm, i, N)] = 0.0;
+    return;
   }
+  // common mode m (the rest direction's adjoint) in FP64, deviations in R
+  double scale = 1.0;
+  if (x >= k.fringe_start) scale = 1.0 - (double)static_cast<const R *>(k.lam)[x];
+  const double m = scale * lam[write_slot<Q, ODD>(n, sm, 0, N)];
+  R dmu[Q];
+  dmu[0] = R(0);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) lam[read_slot<Q, ODD>(n, sm, i, N)] = gb[i];
+  for (int i = 1; i < Q; ++i) dmu[i] = (R)(scale * lam[write_slot<Q, ODD>(n, sm, i, N)] - m);
+  R g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+  const R ph = POROUS ? phi[n.cell] : R(1);
+  const R phib = collide_bulk_vjp<Q, R, POROUS>(
+      g, dmu, ph, k, [&](int i, R v) { lam[read_slot<Q, ODD>(n, sm, i, N)] = m + (double)v; });
+  if (POROUS) grad[n.cell] += (double)phib;
 }
 
 // lam = dJ/df of the current state for the terminal objective
