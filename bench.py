@@ -11,7 +11,10 @@ recorded on its own stream over the timed steps), and the FP64 CPU oracle
 timed on a bounded crop of the same workload on the host cores.
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
-Workloads: channel (default), channel16, urban, urban16, tgv, adjoint.
+Workloads: channel (default), channel16, urban, urban16, big, big16 (1024^3
+urban-style domain, the largest that fits one GPU), tgv, adjoint (reverse /
+forward step time), precision (FP32 and FP16 storage against FP64 on the
+same GPU).
 """
 from __future__ import annotations
 
@@ -48,6 +51,10 @@ def make_case(name):
     if name in ("urban", "urban16"):
         return I.urban(768, 768, 256, q=27, with_wall_dist=False), ("f16" if name.endswith("16") else "f32"), \
             "urban768x768x256_d3q27_smag_wallmodel_fringe_lid"
+    if name in ("big", "big16"):
+        case = I.urban(1024, 1024, 1024, q=27, with_wall_dist=False, x_lo=64, x_hi=896, host_fields=False)
+        case.u0 = I.urban_u0_device(case)
+        return case, ("f16" if name.endswith("16") else "f32"), "urban1024x1024x1024_d3q27_smag_wallmodel_fringe_lid"
     if name == "tgv":
         return I.taylor_green(32, q=19), "f64", "tgv32_d3q19_smag"
     if name == "adjoint":
@@ -63,7 +70,7 @@ def cpu_baseline(name, budget_s=20.0):
     if name.startswith("channel"):
         case = I.channel(384, 192, 24, q=27)
         sample = "channel crop 384x192x24 (walls at z), D3Q27 FP64"
-    elif name.startswith("urban"):
+    elif name.startswith("urban") or name.startswith("big"):
         case = I.urban(192, 192, 64, q=27, fringe_len=32, x_lo=16, x_hi=144, h_mean=20.0, h_max=48)
         sample = "urban crop 192x192x64 (buildings, fringe, lid), D3Q27 FP64"
     elif name == "tgv":
@@ -128,6 +135,8 @@ def main():
 
     lbm.load()
     torch.cuda.set_device(0)
+    if args.workload == "precision":
+        return bench_precision(args, torch, lbm)
     case, storage, wname = make_case(args.workload)
     print(f"[bench] workload {wname} storage {storage} cells {case.ncells}", file=sys.stderr, flush=True)
     if args.workload == "adjoint":
@@ -138,6 +147,7 @@ def main():
     nfluid = case.nfluid()
     nwall = lbm.lbm_wall_count(lat.ctx)
     del case
+    torch.cuda.empty_cache()
     stream = lat.stream
     lat.step(args.warmup)
     lat.sync()
@@ -214,6 +224,43 @@ def main():
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
     out.pop("mass_drift_rel")
+    print(json.dumps(out), flush=True)
+
+
+def bench_precision(args, torch, lbm):
+    """FP32- and FP16-deviation storage against FP64 storage on the same GPU
+    after the same number of steps from the same initial state (the FP64 path
+    matches the CPU oracle to 1e-14).  Errors are max-norms relative to the
+    FP64 field's max-norm."""
+    from paper_2506_21804_amd import inputs as I
+    steps = args.steps
+    rows = {}
+    for wname, make in (("channel384x192x192", lambda: I.channel(384, 192, 192, q=27)),
+                        ("urban768x768x256", lambda: I.urban(768, 768, 256, q=27, with_wall_dist=False))):
+        case = make()
+        res = {}
+        ref = None
+        for storage in ("f64", "f32", "f16"):
+            lat = lbm.Lattice(case, storage=storage, wall_dist=None if case.wall_dist is None else "case")
+            lat.step(steps)
+            rho, u = lat.moments()
+            rho, u = rho.double(), u.double()
+            if ref is None:
+                ref = (rho, u)
+            else:
+                res[storage] = {"rho": float((rho - ref[0]).abs().max() / ref[0].abs().max()),
+                                "u": float((u - ref[1]).abs().max() / ref[1].abs().max()),
+                                "u_rms": float(((u - ref[1]) ** 2).mean().sqrt() / (ref[1] ** 2).mean().sqrt())}
+            del lat, rho, u
+            torch.cuda.empty_cache()
+        rows[wname] = res
+        del case, ref
+        print(f"[bench] precision {wname}: {res}", file=sys.stderr, flush=True)
+    out = {"metric": "moment error of FP32/FP16 deviation storage vs FP64 storage (same GPU, same steps)",
+           "value": rows["channel384x192x192"]["f16"]["u"], "unit": "max-norm relative error of u (FP16, channel)",
+           "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 compute", "data": "synthetic",
+           "config": {"workload": "channel384x192x192 and urban768x768x256, D3Q27"}, "errors": rows}
     print(json.dumps(out), flush=True)
 
 

@@ -369,8 +369,15 @@ class Lattice:
         off = (-self.workspace.data_ptr()) % 256
         self.ws = self.workspace[off:off + nbytes]
         dev = torch.device("cuda")
-        rho0 = None if case.rho0 is None else torch.as_tensor(np.ascontiguousarray(case.rho0), device=dev)
-        u0 = None if case.u0 is None else torch.as_tensor(np.ascontiguousarray(case.u0), device=dev)
+
+        def to_dev(a):
+            if a is None:
+                return None
+            if isinstance(a, torch.Tensor):
+                return a.to(device=dev, dtype=torch.float64).contiguous()
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+
+        rho0, u0 = to_dev(case.rho0), to_dev(case.u0)
         wd = case.wall_dist if isinstance(wall_dist, str) else wall_dist
         with torch.cuda.stream(stream):
             self.ctx = lbm_init(self.p, case.mask, wd, case.porosity, rho0, u0, self.ws)
