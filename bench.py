@@ -211,8 +211,8 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": "k_bulk", "avg_launch_ms": round(k2_ms, 5), "alg_bytes_per_launch": k2_bytes},
         "step_alg_gbs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
-        "kernel_ms_per_step": {"wall_prepass": round(kms[0] / max(kcount[0], 1), 5), "bulk": round(k2_ms, 5),
-                               "wall_collide": round(kms[2] / max(kcount[2], 1), 5)},
+        "kernel_ms_per_step": {"wall_prepass_refwall": round(kms[0] / max(kcount[0], 1), 5),
+                               "wall": round(kms[2] / max(kcount[2], 1), 5), "bulk": round(k2_ms, 5)},
         "mass_drift_rel": None,
     }
     out["mass"] = float(diag[0])

@@ -94,9 +94,10 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
              const double *porosity, const double *rho0, const double *u0, void *workspace,
              size_t workspace_bytes);
 
-/* Advances n >= 0 time steps (async).  Each step: wall prepass (u_tau by
- * Newton in FP64 from the Spalding law at the reference cell), then the
- * fused collide-and-stream of all fluid cells and the wall reconstruction. */
+/* Advances n >= 0 time steps (async).  Each step: the wall records (u_tau by
+ * Newton in FP64 from the Spalding law at each wall cell's reference cell)
+ * and the wall reconstruction, then the fused collide-and-stream of all other
+ * fluid cells. */
 int lbm_step(lbm_ctx *ctx, int n);
 
 /* Density and velocity u = (j + F/2)/rho of the current state into device
@@ -181,8 +182,9 @@ int lbm_wall_records(lbm_ctx *ctx, int *cell, int *ref, double *normal, double *
                      double *tau);
 
 /* Per-kernel timing of the step kernels with HIP events recorded on the
- * context's stream around each launch: index 0 the wall prepass, 1 the bulk
- * collide-and-stream kernel, 2 the wall reconstruction.  lbm_profile(ctx, 1)
+ * context's stream around each launch: index 0 the separate wall prepass (for
+ * wall cells whose reference cell is a wall cell), 1 the bulk
+ * collide-and-stream kernel, 2 the wall kernel (records and reconstruction).  lbm_profile(ctx, 1)
  * starts recording (creates the events once), lbm_profile(ctx, 0) stops it;
  * lbm_profile_read waits for the recorded launches and returns, then
  * resets, the accumulated milliseconds and launch counts. */

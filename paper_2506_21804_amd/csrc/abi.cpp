@@ -85,7 +85,7 @@ bool params_ok(const lbm_params *p, std::string &msg) {
 }
 
 struct Layout {
-  size_t pop, flags, phi, tables, wcell, wref, wrec, partial, result, errflag, total;
+  size_t pop, flags, phi, tables, wcell, wref, wrefwall, wlist, wrec, partial, result, errflag, total;
 };
 
 Layout layout_of(const lbm_params &p, long long nwall, bool porous) {
@@ -104,6 +104,10 @@ Layout layout_of(const lbm_params &p, long long nwall, bool porous) {
   L.wcell = off;
   off += align_up((size_t)nwall * sizeof(int));
   L.wref = off;
+  off += align_up((size_t)nwall * sizeof(int));
+  L.wrefwall = off;
+  off += align_up((size_t)nwall);
+  L.wlist = off;
   off += align_up((size_t)nwall * sizeof(int));
   L.wrec = off;
   off += align_up((size_t)nwall * WR_COUNT * sizeof(double));
@@ -237,6 +241,8 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   ctx->nwall = (int)nwall;
   ctx->wcell = (int *)(base + L.wcell);
   ctx->wref = (int *)(base + L.wref);
+  ctx->wrefwall = (uint8_t *)(base + L.wrefwall);
+  ctx->wlist_refwall = (int *)(base + L.wlist);
   ctx->wrec = (double *)(base + L.wrec);
   ctx->partial = (double *)(base + L.partial);
   ctx->npartial = PARTIAL_SLOTS;
@@ -295,6 +301,21 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   if (porosity && (e = hipMemcpy(ctx->phi, phic.data(), phic.size(), hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e, "upload porosity");
   if (nwall > 0) {
+    // records whose reference cell is a wall cell get their own prepass launch
+    std::vector<uint8_t> refwall((size_t)nwall, 0);
+    std::vector<int> list;
+    for (long long k = 0; k < nwall; ++k)
+      if (g.flags[(size_t)g.wref[k]] & FL_WALL) {
+        refwall[k] = 1;
+        list.push_back((int)k);
+      }
+    ctx->nwall_refwall = (int)list.size();
+    if ((e = hipMemcpy(ctx->wrefwall, refwall.data(), (size_t)nwall, hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e, "upload wall reference classes");
+    if (!list.empty() &&
+        (e = hipMemcpy(ctx->wlist_refwall, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+      return fail(e, "upload wall reference list");
     if ((e = hipMemcpy(ctx->wcell, g.wcell.data(), nwall * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
       return fail(e, "upload wall cells");
     if ((e = hipMemcpy(ctx->wref, g.wref.data(), nwall * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)

@@ -84,6 +84,9 @@ struct lbm_ctx {
   int nwall = 0;
   int *wcell = nullptr;       // [nwall]
   int *wref = nullptr;        // [nwall]
+  uint8_t *wrefwall = nullptr;   // [nwall] 1 when the reference cell is itself a wall cell
+  int *wlist_refwall = nullptr;  // [nwall_refwall] indices of those records
+  int nwall_refwall = 0;
   double *wrec = nullptr;     // [WR_COUNT][nwall]
   double *partial = nullptr;  // reduction partials
   int npartial = 0;           // number of partial slots (blocks) available
@@ -139,7 +142,8 @@ int dev_fill(lbm_ctx *ctx, void *ptr, size_t bytes);  // zero fill with a kernel
 int dev_write_header(lbm_ctx *ctx, void *dst);
 
 int hip_fail(lbm_ctx *ctx, hipError_t e, const char *what);
-// Event brackets around step kernel k (0: K1, 1: K2, 2: K3); no-ops unless profiling.
+// Event brackets around step kernel k (0: wall prepass, 1: bulk, 2: wall
+// step); no-ops unless profiling.
 void prof_begin(lbm_ctx *ctx, int k);
 void prof_end(lbm_ctx *ctx, int k);
 

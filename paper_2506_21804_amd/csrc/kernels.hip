@@ -1,18 +1,21 @@
 // Forward kernels of the wall-modeled LBM-LES step for gfx950 (wave64).
 //
-// One time step at parity p is three launches on the context's stream:
-//   K1 k_wall_prepass  one thread per wall cell: friction velocity from the
-//                      Spalding law (Sec. 2.2.1, Eq. (17)) by Newton in FP64
-//                      at the reference cell, modeled tangential velocity and
-//                      strain; reads only, so it must finish before K2/K3;
+// One time step at parity p is two or three launches on the context's stream:
+//   K1 k_wall_prepass  only for wall cells whose reference cell is itself a
+//                      wall cell: friction velocity from the Spalding law
+//                      (Sec. 2.2.1, Eq. (17)) by Newton in FP64 at the
+//                      reference cell, modeled tangential velocity and strain;
+//   K3 k_wall          one thread per wall cell: the same record for the
+//                      other wall cells (their reference cells are bulk cells
+//                      that no wall thread writes), then the sigma = 0
+//                      reconstruction (equilibrium at the modeled velocity
+//                      plus the non-equilibrium of Eq. (10) built from the
+//                      wall-law strain) and the AA scatter;
 //   K2 k_bulk          one thread per cell (64x4 tiles): AA gather, BGK
 //                      collision with the Smagorinsky tau_eff (Eqs. (3),(4),
 //                      (14)), homogenized velocity (Eq. (12)), Guo forcing,
-//                      fringe/lid, AA scatter; skips wall cells;
-//   K3 k_wall          one thread per wall cell: sigma = 0 reconstruction
-//                      (equilibrium at the modeled velocity plus the
-//                      non-equilibrium of Eq. (10) built from the wall-law
-//                      strain), then the same scatter.
+//                      fringe/lid, AA scatter; skips wall cells.  It runs last
+//                      because it writes the reference cells K1/K3 read.
 // K2 and K3 touch disjoint slot sets (AA read set = write set per cell).
 // The path is bound by HBM traffic: q loads and q stores per cell plus the
 // flag byte, no contraction, so no MFMA.
@@ -221,14 +224,12 @@ __device__ __forceinline__ double spalding_d(double up, double kappa, double E) 
   return 1.0 + kappa * r / E;
 }
 
+// Wall record of wall cell w (reference cell r, wall cell b): reads the
+// reference cell's current populations and writes t, u_tau u+_b, G, tau_eff.
 template <int Q, typename S, bool ODD>
-__global__ __launch_bounds__(256) void k_wall_prepass(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
-                                                      const int *__restrict__ wcell, const int *__restrict__ wref,
-                                                      double *__restrict__ rec, int nwall, KArgs k,
-                                                      int *__restrict__ errflag) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= nwall) return;
-  const int r = wref[w];
+__device__ __forceinline__ void wall_record(const S *__restrict__ pop, const uint8_t *__restrict__ flags, int w, int b,
+                                            int r, double *__restrict__ rec, int nwall, const KArgs &k,
+                                            int *__restrict__ errflag) {
   int x, y, z;
   cell_xyz(r, k, x, y, z);
   const Nb n = make_nb(x, y, z, k);
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(256) void k_wall_prepass(const S *__restrict__ pop,
       }
     }
     double up = U / ut;
-    if (conv && r != wcell[w]) {
+    if (conv && r != b) {
       // u+ at the wall cell: g(u+) = y+_b by Newton from an upper bound of
       // the root (g convex increasing: the iterates decrease monotonically).
       const double ypb = yb * ut / nu;
@@ -317,17 +318,34 @@ __global__ __launch_bounds__(256) void k_wall_prepass(const S *__restrict__ pop,
   rec[WR_UTAU * M + w] = utau;
 }
 
+template <int Q, typename S, bool ODD>
+__global__ __launch_bounds__(256) void k_wall_prepass(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                      const int *__restrict__ wcell, const int *__restrict__ wref,
+                                                      const int *__restrict__ list, int nlist,
+                                                      double *__restrict__ rec, int nwall, KArgs k,
+                                                      int *__restrict__ errflag) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nlist) return;
+  const int w = list[j];
+  wall_record<Q, S, ODD>(pop, flags, w, wcell[w], wref[w], rec, nwall, k, errflag);
+}
+
 // ---------------------------------------------------------------------------
 // K3: wall reconstruction (sigma = 0, solid velocity = modeled velocity).
 // ---------------------------------------------------------------------------
 template <int Q, typename S, bool ODD>
 __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t *__restrict__ flags,
-                                              const int *__restrict__ wcell, const double *__restrict__ rec,
+                                              const int *__restrict__ wcell, const int *__restrict__ wref,
+                                              const uint8_t *__restrict__ refwall, double *__restrict__ rec,
                                               int nwall, KArgs k, int *__restrict__ errflag) {
   using R = typename Store<S>::R;
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nwall) return;
   const int b = wcell[w];
+  // the record of a wall cell whose reference is not a wall cell is computed
+  // here (no other thread of this launch writes that reference); the others
+  // were computed by k_wall_prepass before this launch
+  if (!refwall[w]) wall_record<Q, S, ODD>(pop, flags, w, b, wref[w], rec, nwall, k, errflag);
   int x, y, z;
   cell_xyz(b, k, x, y, z);
   const Nb n = make_nb(x, y, z, k);
@@ -652,30 +670,36 @@ int dev_step(lbm_ctx *ctx) {
   return dispatch(ctx, [&]<int Q, typename S>() {
     const int nw = ctx->nwall;
     const int wb = (nw + 255) / 256;
-    if (nw > 0) {
+    const int nb = ctx->nwall_refwall;
+    // wall records whose reference cell is itself a wall cell, before any wall cell is written
+    if (nb > 0) {
       prof_begin(ctx, 0);
+      const int lb = (nb + 255) / 256;
       if (odd)
-        k_wall_prepass<Q, S, true><<<wb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->wcell,
-                                                                ctx->wref, ctx->wrec, nw, ctx->ka, ctx->errflag);
+        k_wall_prepass<Q, S, true><<<lb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wref,
+                                                                ctx->wlist_refwall, nb, ctx->wrec, nw, ctx->ka,
+                                                                ctx->errflag);
       else
-        k_wall_prepass<Q, S, false><<<wb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->wcell,
-                                                                 ctx->wref, ctx->wrec, nw, ctx->ka, ctx->errflag);
+        k_wall_prepass<Q, S, false><<<lb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->wcell,
+                                                                 ctx->wref, ctx->wlist_refwall, nb, ctx->wrec, nw,
+                                                                 ctx->ka, ctx->errflag);
       prof_end(ctx, 0);
+    }
+    // wall cells (their reference cells are read before the bulk kernel writes them)
+    if (nw > 0) {
+      prof_begin(ctx, 2);
+      if (odd)
+        k_wall<Q, S, true><<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wref,
+                                                        ctx->wrefwall, ctx->wrec, nw, ctx->ka, ctx->errflag);
+      else
+        k_wall<Q, S, false><<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wref,
+                                                         ctx->wrefwall, ctx->wrec, nw, ctx->ka, ctx->errflag);
+      prof_end(ctx, 2);
     }
     prof_begin(ctx, 1);
     if (odd) launch_bulk<Q, S, true>(ctx, t);
     else launch_bulk<Q, S, false>(ctx, t);
     prof_end(ctx, 1);
-    if (nw > 0) {
-      prof_begin(ctx, 2);
-      if (odd)
-        k_wall<Q, S, true><<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wrec, nw,
-                                                        ctx->ka, ctx->errflag);
-      else
-        k_wall<Q, S, false><<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wrec, nw,
-                                                         ctx->ka, ctx->errflag);
-      prof_end(ctx, 2);
-    }
     return check_launch(ctx, "step kernels");
   });
 }
