@@ -56,6 +56,10 @@ bool params_ok(const lbm_params *p, std::string &msg) {
     msg = "storage must be LBM_F64, LBM_F32DEV or LBM_F16DEV";
     return false;
   }
+  if ((unsigned long long)N * storage_bytes(p->storage) > (1ULL << 32)) {
+    msg = "one population array would exceed 4 GiB (N * bytes per value > 2^32)";
+    return false;
+  }
   if (!(p->tau0 > 0.5) || !std::isfinite(p->tau0)) {
     msg = "tau0 must be finite and exceed 1/2";
     return false;

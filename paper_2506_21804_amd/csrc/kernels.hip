@@ -100,24 +100,31 @@ __device__ __forceinline__ void lid_equilibrium(R g[Q], const KArgs &k) {
 
 // Bulk collision on deviations g (sigma = 1): BGK with tau_eff from the
 // non-equilibrium stress, homogenized velocity u_hat = phi u, Guo forcing.
+// Opposite directions i and i+H share everything but a sign: with
+//   f^eq_i - w = A + B, f^eq_ibar - w = A - B   (A even, B odd in c_i),
+//   Guo_i = C + D,        Guo_ibar = C - D,
+// the outputs are g*_i = c1 g_i + P + Qo and g*_ibar = c1 g_ibar + P - Qo.
 // Returns false for a non-finite or non-positive density.
 template <int Q, typename R, bool POROUS>
 __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
-  R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+  constexpr int H = Lat<Q>::H;
+  // moments from pair sums s = g_i + g_ibar (even moments) and differences d = g_i - g_ibar (odd)
+  R drho = g[0], jx = R(0), jy = R(0), jz = R(0);
   R mxx = R(0), myy = R(0), mzz = R(0), mxy = R(0), mxz = R(0), myz = R(0);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 1; i <= H; ++i) {
     const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
-    drho += g[i];
-    acc(jx, cx, g[i]);
-    acc(jy, cy, g[i]);
-    acc(jz, cz, g[i]);
-    acc(mxx, cx * cx, g[i]);
-    acc(myy, cy * cy, g[i]);
-    acc(mzz, cz * cz, g[i]);
-    acc(mxy, cx * cy, g[i]);
-    acc(mxz, cx * cz, g[i]);
-    acc(myz, cy * cz, g[i]);
+    const R sp = g[i] + g[i + H], dp = g[i] - g[i + H];
+    drho += sp;
+    acc(jx, cx, dp);
+    acc(jy, cy, dp);
+    acc(jz, cz, dp);
+    acc(mxx, cx * cx, sp);
+    acc(myy, cy * cy, sp);
+    acc(mzz, cz * cz, sp);
+    acc(mxy, cx * cy, sp);
+    acc(mxz, cx * cz, sp);
+    acc(myz, cy * cz, sp);
   }
   const R rho = R(1) + drho;
   const bool ok = finite_pos(rho);
@@ -141,17 +148,34 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
   const R vx = POROUS ? phi * ux : ux, vy = POROUS ? phi * uy : uy, vz = POROUS ? phi * uz : uz;
   const R vv = vx * vx + vy * vy + vz * vz;
   const R uF = ux * Fx + uy * Fy + uz * Fz;
+  // rest population: A = w0 (drho - 3/2 rho v.v), B = C - (-3 w0 u.F) = D = 0
+  {
+    const R w = R(Lat<Q>::w(0));
+    const R au = w * (drho - R(1.5) * rho * uu);
+    const R av = POROUS ? w * (drho - R(1.5) * rho * vv) : au;
+    g[0] = c1 * g[0] + (av - c1 * au) + c2 * (R(-3) * w * uF);
+  }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 1; i <= H; ++i) {
     const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
     const R w = R(Lat<Q>::w(i));
     const R cu = dot3(cx, cy, cz, ux, uy, uz);
-    const R gu = geq_dev(w, drho, rho, cu, uu);
-    R gv = gu;
-    if (POROUS) gv = geq_dev(w, drho, rho, dot3(cx, cy, cz, vx, vy, vz), vv);
     const R cF = dot3(cx, cy, cz, Fx, Fy, Fz);
-    const R guo = w * (R(3) * (cF - uF) + R(9) * cu * cF);
-    g[i] = gv + c1 * (g[i] - gu) + c2 * guo;
+    const R Au = w * (drho + rho * (R(4.5) * cu * cu - R(1.5) * uu));
+    const R Bu = R(3) * w * rho * cu;
+    R Av = Au, Bv = Bu;
+    if (POROUS) {
+      const R cv = dot3(cx, cy, cz, vx, vy, vz);
+      Av = w * (drho + rho * (R(4.5) * cv * cv - R(1.5) * vv));
+      Bv = R(3) * w * rho * cv;
+    }
+    const R C = w * (R(9) * cu * cF - R(3) * uF);
+    const R D = R(3) * w * cF;
+    const R P = (Av - c1 * Au) + c2 * C;
+    const R Qo = (Bv - c1 * Bu) + c2 * D;
+    const R gi = g[i], gj = g[i + H];
+    g[i] = c1 * gi + P + Qo;
+    g[i + H] = c1 * gj + P - Qo;
   }
   return ok;
 }
@@ -160,26 +184,42 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
 // K2: fused gather / collide / scatter over all non-wall fluid cells.
 // ---------------------------------------------------------------------------
 // Gather, collide, scatter of one cell.  With LINKS = false the cell has no
-// solid link (sm = 0) and every slot address is the plain AA one.
+// solid link and every slot is the plain AA one (32-bit offsets from a
+// per-direction base); with LINKS = true slots follow the bounce-back map.
 template <int Q, typename S, bool ODD, bool POROUS, bool LINKS>
 __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename Store<S>::R *__restrict__ phi,
                                           const KArgs &k, const Nb &n, unsigned sm, uint8_t fl, int x, int z,
                                           int *__restrict__ errflag) {
   using R = typename Store<S>::R;
   const size_t N = (size_t)k.N;
-  if (!LINKS) sm = 0u;
   R g[Q];
   if (fl & FL_LID) {
     lid_equilibrium<Q, R>(g, k);
   } else {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+    for (int i = 0; i < Q; ++i) {
+      if (LINKS) {
+        g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+      } else {
+        int dir;
+        const int idx = plain_read<Q, ODD>(n, i, dir);
+        g[i] = Store<S>::ld(slot_at(pop, dir, N, idx));
+      }
+    }
     const R ph = POROUS ? phi[n.cell] : R(1);
     if (!collide_bulk<Q, R, POROUS>(g, ph, k)) atomicOr(errflag, 1);
   }
   fringe_blend<Q, R>(g, x, z, k);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) Store<S>::st(pop + write_slot<Q, ODD>(n, sm, i, N), g[i]);
+  for (int i = 0; i < Q; ++i) {
+    if (LINKS) {
+      Store<S>::st(pop + write_slot<Q, ODD>(n, sm, i, N), g[i]);
+    } else {
+      int dir;
+      const int idx = plain_write<Q, ODD>(n, i, dir);
+      Store<S>::st(slot_at(pop, dir, N, idx), g[i]);
+    }
+  }
 }
 
 template <int Q, typename S, bool ODD, bool POROUS, bool SOLID>

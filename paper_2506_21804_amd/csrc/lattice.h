@@ -165,6 +165,28 @@ __device__ __forceinline__ size_t write_slot(const Nb &n, unsigned sm, int i, si
   return (size_t)i * N + (size_t)(n.cell + nb_off<Q>(n, i, +1));
 }
 
+// Plain-path slot addressing (cells with no solid link): direction of the
+// slot and its element index within that direction's array.  The element
+// index is a 32-bit offset from a per-direction base that is uniform across
+// the wavefront, which keeps the address arithmetic in 32 bits.
+template <int Q, bool ODD>
+__device__ __forceinline__ int plain_read(const Nb &n, int i, int &dir) {
+  dir = ODD ? Lat<Q>::opp(i) : i;
+  return ODD ? n.cell + nb_off<Q>(n, i, -1) : n.cell;
+}
+template <int Q, bool ODD>
+__device__ __forceinline__ int plain_write(const Nb &n, int i, int &dir) {
+  dir = ODD ? i : Lat<Q>::opp(i);
+  return ODD ? n.cell + nb_off<Q>(n, i, +1) : n.cell;
+}
+// Element idx of direction array dir; requires N * sizeof(S) <= 2^32 (checked
+// when the context is created).
+template <typename S>
+__device__ __forceinline__ S *slot_at(S *pop, int dir, size_t N, int idx) {
+  return reinterpret_cast<S *>(reinterpret_cast<char *>(pop + (size_t)dir * N) +
+                               (size_t)((uint32_t)idx * (uint32_t)sizeof(S)));
+}
+
 // XCD-aware block order: hardware hands block b to XCD b % 8; give each XCD
 // a contiguous run of tiles so that neighbouring tiles share its L2.
 __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
