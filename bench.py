@@ -62,7 +62,7 @@ def make_case(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(name, budget_s=20.0):
+def cpu_baseline(name, budget_s=12.0):
     """The FP64 oracle on a bounded crop of the workload (same x-y plane,
     fewer z planes), timed around its step loop on the host cores."""
     import oracle as O
@@ -86,7 +86,7 @@ def cpu_baseline(name, budget_s=20.0):
     t0 = time.perf_counter()
     s.step(1)
     one = time.perf_counter() - t0
-    n = max(1, min(50, int(budget_s / max(one, 1e-6)) - 1))
+    n = max(1, min(1000, int(budget_s / max(one, 1e-6)) - 1))
     t0 = time.perf_counter()
     s.step(n)
     dt = time.perf_counter() - t0

@@ -165,13 +165,15 @@ void prof_begin(lbm_ctx *ctx, int k) {
   if (!ctx->profiling) return;
   KernelTimer &t = ctx->timers[k];
   drain_slot(t, t.head);
-  hipEventRecord(t.start[t.head], ctx->stream);
+  t.started = hipEventRecord(t.start[t.head], ctx->stream) == hipSuccess;
 }
 
 void prof_end(lbm_ctx *ctx, int k) {
   if (!ctx->profiling) return;
   KernelTimer &t = ctx->timers[k];
-  hipEventRecord(t.stop[t.head], ctx->stream);
+  // A launch whose events could not both be recorded is left out of the sums.
+  if (!t.started || hipEventRecord(t.stop[t.head], ctx->stream) != hipSuccess) return;
+  t.started = false;
   t.pending[t.head] = true;
   t.head = (t.head + 1) % PROF_RING;
 }
@@ -610,8 +612,8 @@ void lbm_free(lbm_ctx *ctx) {
   if (ctx->timers) {
     for (int k = 0; k < 3; ++k)
       for (int s = 0; s < PROF_RING; ++s) {
-        if (ctx->timers[k].start[s]) hipEventDestroy(ctx->timers[k].start[s]);
-        if (ctx->timers[k].stop[s]) hipEventDestroy(ctx->timers[k].stop[s]);
+        if (ctx->timers[k].start[s]) (void)hipEventDestroy(ctx->timers[k].start[s]);
+        if (ctx->timers[k].stop[s]) (void)hipEventDestroy(ctx->timers[k].stop[s]);
       }
     delete[] ctx->timers;
   }

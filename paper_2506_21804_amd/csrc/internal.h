@@ -61,6 +61,7 @@ struct KernelTimer {
   hipEvent_t start[PROF_RING]{}, stop[PROF_RING]{};
   bool pending[PROF_RING]{};
   int head = 0;
+  bool started = false;  // the start event of slot head was recorded
   double ms = 0.0;
   long long count = 0;
 };

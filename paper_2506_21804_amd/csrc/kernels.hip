@@ -694,7 +694,16 @@ static void launch_bulk(lbm_ctx *ctx, Tiles t) {
   using R = typename Store<S>::R;
   S *pop = (S *)ctx->pop;
   const R *phi = (const R *)ctx->phi;
-  auto go = [&](auto kern) { kern<<<t.nblocks, BLOCK, 0, ctx->stream>>>(pop, ctx->flags, phi, ctx->ka, t, ctx->errflag); };
+  // Residency cap for 4-byte storage.  K2 uses no LDS, but an LDS reservation
+  // of 32 KiB per 256-thread block admits at most five blocks (five waves per
+  // SIMD) on a CU's 160 KiB.  FP32 streams measurably faster at five waves
+  // than at the seven to eight its register count would allow (more requests
+  // in flight contend in HBM); FP16, with half the bytes per cell, is fastest
+  // uncapped.
+  constexpr size_t lds_cap = sizeof(S) == 4 ? 32768 : 0;
+  auto go = [&](auto kern) {
+    kern<<<t.nblocks, BLOCK, lds_cap, ctx->stream>>>(pop, ctx->flags, phi, ctx->ka, t, ctx->errflag);
+  };
   if (ctx->porous) {
     if (ctx->has_solid) go(k_bulk<Q, S, ODD, true, true>);
     else go(k_bulk<Q, S, ODD, true, false>);
