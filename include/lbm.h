@@ -139,17 +139,23 @@ int lbm_load_state(lbm_ctx *ctx, const void *src);
  * velocity.  Synchronises; *J in FP64. */
 int lbm_objective(lbm_ctx *ctx, const int planes[2], double *J);
 
-/* Discrete adjoint.  An adjoint field lambda has the layout of the state
- * (q arrays of N doubles, in-memory AA order of the current step parity) for
- * every storage mode; it is caller device memory of lbm_adjoint_bytes().
- * Adjoint arithmetic and grad_phi are FP64 for every storage mode.
+/* Discrete adjoint.  An adjoint field lambda is caller device memory of
+ * lbm_adjoint_bytes(), 8-byte aligned, in the library's own form: per fluid
+ * cell one FP64 common mode, plus q deviations in the compute type (FP64
+ * for FP64 storage, FP32 otherwise) in the in-memory AA order of the current
+ * step parity.  Its values are read and written in natural order through
+ * lbm_adjoint_to_natural / _from_natural.  The common mode is handled in
+ * FP64 and the deviations pass through the collision's vector-Jacobian
+ * product in the compute precision; grad_phi is FP64.  Misaligned buffers
+ * give LBM_EINVAL.
  *  lbm_adjoint_seed: lambda = dJ/df of the current state (async).
  *  lbm_adjoint_step: given lambda = dJ/df^{n+1} and the state f^n currently
  *    held by the context (step counter n), overwrites lambda with dJ/df^n
  *    and adds dJ/dphi contributions of step n to grad_phi [N] (double);
  *    decrements nothing (the caller restores f^{n-1} itself). Async.
- *  lbm_adjoint_to_natural / _from_natural: convert lambda between the
- *    in-memory layout of the current parity and natural [q][N] order. */
+ *  lbm_adjoint_to_natural / _from_natural: convert lambda between its
+ *    in-memory form at the current parity and natural [q][N] order (FP64
+ *    values; solid cells read as 0). */
 size_t lbm_adjoint_bytes(const lbm_ctx *ctx);
 int lbm_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lambda);
 int lbm_adjoint_step(lbm_ctx *ctx, void *lambda, void *grad_phi);

@@ -262,10 +262,14 @@ def lbm_adjoint_bytes(ctx) -> int:
     return load().lbm_adjoint_bytes(ctx)
 
 
-def _lam(ctx, t, what="adjoint"):
+def _lam(ctx, t):
+    return _dbuf(t, lbm_adjoint_bytes(ctx), "adjoint")
+
+
+def _nat(ctx, t):
     import torch
     q, N, dt, cb = _sizes(ctx)
-    return _dbuf(t, q * N * 8, what, torch.float64)
+    return _dbuf(t, q * N * 8, "natural", torch.float64)
 
 
 def _grad(ctx, t):
@@ -284,11 +288,11 @@ def lbm_adjoint_step(ctx, lam, grad):
 
 
 def lbm_adjoint_to_natural(ctx, lam, nat):
-    _check(ctx, load().lbm_adjoint_to_natural(ctx, _lam(ctx, lam), _lam(ctx, nat, "natural")))
+    _check(ctx, load().lbm_adjoint_to_natural(ctx, _lam(ctx, lam), _nat(ctx, nat)))
 
 
 def lbm_adjoint_from_natural(ctx, nat, lam):
-    _check(ctx, load().lbm_adjoint_from_natural(ctx, _lam(ctx, nat, "natural"), _lam(ctx, lam)))
+    _check(ctx, load().lbm_adjoint_from_natural(ctx, _nat(ctx, nat), _lam(ctx, lam)))
 
 
 def lbm_gradient(ctx, T, planes, snapshots, nsnap, lam, grad):
@@ -438,7 +442,12 @@ class Lattice:
         return lbm_objective(self.ctx, planes)
 
     def new_adjoint(self):
-        """Adjoint populations (FP64 for every storage mode)."""
+        """Buffer for an adjoint field in the library's in-memory form
+        (read it in natural order with lbm_adjoint_to_natural)."""
+        return self.torch.zeros(lbm_adjoint_bytes(self.ctx), dtype=self.torch.uint8, device="cuda")
+
+    def new_natural(self):
+        """Natural-order [q][N] FP64 buffer for adjoint values."""
         return self.torch.zeros((self.q, self.N), dtype=self.torch.float64, device="cuda")
 
     def new_gradient(self):

@@ -452,29 +452,36 @@ int lbm_objective(lbm_ctx *ctx, const int planes[2], double *J) {
 
 size_t lbm_adjoint_bytes(const lbm_ctx *ctx) {
   if (!ctx) return 0;
-  return (size_t)ctx->q * ctx->N * sizeof(double);
+  return adj_layout(ctx->N, ctx->q, ctx->p.storage == LBM_F64 ? 8 : 4).bytes;
 }
+
+static bool adj_aligned(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 
 int lbm_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lambda) {
   if (!ctx || !planes || !lambda) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
   if (planes[0] < 0 || planes[0] >= ctx->p.nx || planes[1] < 0 || planes[1] >= ctx->p.nx)
     return set_err(ctx, LBM_EINVAL, "objective planes outside the domain");
+  if (!adj_aligned(lambda)) return set_err(ctx, LBM_EINVAL, "adjoint buffer not 8-byte aligned");
   return dev_adjoint_seed(ctx, planes, lambda);
 }
 
 int lbm_adjoint_step(lbm_ctx *ctx, void *lambda, void *grad_phi) {
   if (!ctx || !lambda || !grad_phi) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
   if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
+  if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
+    return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   return dev_adjoint_step(ctx, lambda, grad_phi);
 }
 
 int lbm_adjoint_to_natural(lbm_ctx *ctx, const void *lambda, void *natural) {
   if (!ctx || !lambda || !natural) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
+  if (!adj_aligned(lambda) || !adj_aligned(natural)) return set_err(ctx, LBM_EINVAL, "buffer not 8-byte aligned");
   return dev_layout_to_natural(ctx, lambda, natural);
 }
 
 int lbm_adjoint_from_natural(lbm_ctx *ctx, const void *natural, void *lambda) {
   if (!ctx || !lambda || !natural) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
+  if (!adj_aligned(lambda) || !adj_aligned(natural)) return set_err(ctx, LBM_EINVAL, "buffer not 8-byte aligned");
   return dev_layout_from_natural(ctx, natural, lambda);
 }
 
@@ -486,6 +493,8 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
   if (T < 1 || nsnap < 1 || !snapshots || !lambda || !grad_phi || !planes)
     return set_err(ctx, LBM_EINVAL, "gradient needs T >= 1, nsnap >= 1 and non-null buffers");
   if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
+  if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
+    return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   const size_t sb = lbm_state_bytes(ctx);
   auto slot = [&](int k) { return (char *)snapshots + (size_t)k * sb; };
   long long fwd = 0;

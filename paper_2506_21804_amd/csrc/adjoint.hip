@@ -2,7 +2,7 @@
 // gradients of a terminal objective with respect to the per-cell porosity of
 // the homogenized velocity (Sec. 2.2, Eq. (12)).
 //
-// An adjoint field lam has the state's in-memory AA layout.  One reverse step
+// An adjoint field has the state's in-memory AA layout.  One reverse step
 // at parity n is the transpose of the forward step: for each cell, the
 // adjoints of its post-collision outputs are read from the slots the forward
 // step wrote (its write set), pushed back through the collision by the
@@ -13,14 +13,20 @@
 // The Frobenius norm of the stress has no derivative at zero; its adjoint is
 // taken as 0 there.
 //
-// Precision.  Adjoint populations carry a large per-cell common mode (from
-// the density terms of the objective) next to small informative parts, so
-// the adjoint field and the gradient are stored in FP64 for every storage
-// mode.  The collision conserves mass for every state and porosity, so its
+// Precision and storage.  Adjoint populations carry a large per-cell common
+// mode (from the density terms of the objective) next to small informative
+// parts.  The collision conserves mass for every state and porosity, so its
 // vector-Jacobian product maps a constant vector m 1 to itself and gives it
-// no porosity sensitivity: each cell subtracts m = mu_0 (in FP64), pushes
-// only the deviations mu_i - m through the product in the compute precision
-// (FP32 for FP32/FP16 storage), and adds m back when it stores.
+// no porosity sensitivity: each cell takes m = mu_0 in FP64, pushes only the
+// deviations mu_i - m through the product in the compute precision (FP32 for
+// FP32/FP16 storage), and stores its outputs as m (one FP64 value per cell)
+// plus q deviations in the compute type.  A reader recovers the value of a
+// slot as the writer's m plus the stored deviation; the writer of the
+// adjoint a cell reads for direction i is its downstream neighbour x + c_i,
+// or the cell itself when that link is solid, at either parity.  The common
+// modes are double-buffered by layout parity (readers take the previous
+// step's, writers fill the current one), so no cell overwrites a value a
+// neighbour still needs.  The gradient is accumulated in FP64.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -201,9 +207,17 @@ __device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi
   return phib;
 }
 
+// Cell that wrote the adjoint that cell n reads for direction i (see above).
+template <int Q, bool SOLID>
+__device__ __forceinline__ int writer_of(const Nb &n, unsigned sm, int i) {
+  if (SOLID && ((sm >> Lat<Q>::opp(i)) & 1u)) return n.cell;
+  return n.cell + nb_off<Q>(n, i, +1);
+}
+
 template <int Q, typename S, bool ODD, bool POROUS, bool SOLID>
 __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
-                                                    double *__restrict__ lam,
+                                                    typename Store<S>::R *__restrict__ dev,
+                                                    const double *__restrict__ m_prev, double *__restrict__ m_next,
                                                     const typename Store<S>::R *__restrict__ phi,
                                                     double *__restrict__ grad, KArgs k, ATiles t) {
   using R = typename Store<S>::R;
@@ -213,37 +227,46 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
   const uint8_t fl = flags[n.cell];
   if (!(fl & FL_FLUID)) return;
   unsigned sm = 0;
-  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  if (SOLID && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
   const size_t N = (size_t)k.N;
   if (fl & FL_LID) {
     // the lid output does not depend on the state
 #pragma unroll
-    for (int i = 0; i < Q; ++i) lam[read_slot<Q, ODD>(n, sm, i, N)] = 0.0;
+    for (int i = 0; i < Q; ++i) dev[read_slot<Q, ODD>(n, sm, i, N)] = R(0);
+    m_next[n.cell] = 0.0;
     return;
   }
-  // common mode m (the rest direction's adjoint) in FP64, deviations in R
   double scale = 1.0;
   if (x >= k.fringe_start) scale = 1.0 - (double)static_cast<const R *>(k.lam)[x];
-  const double m = scale * lam[write_slot<Q, ODD>(n, sm, 0, N)];
+  // mu_i = scale (M[writer_i] + d_i); the rest direction's writer is the cell itself
+  const double mx = m_prev[n.cell];
+  const double d0 = (double)dev[write_slot<Q, ODD>(n, sm, 0, N)];
+  const double m = scale * (mx + d0);
   R dmu[Q];
   dmu[0] = R(0);
 #pragma unroll
-  for (int i = 1; i < Q; ++i) dmu[i] = (R)(scale * lam[write_slot<Q, ODD>(n, sm, i, N)] - m);
+  for (int i = 1; i < Q; ++i) {
+    const double mw = m_prev[writer_of<Q, SOLID>(n, sm, i)];
+    const double di = (double)dev[write_slot<Q, ODD>(n, sm, i, N)];
+    dmu[i] = (R)(scale * ((mw - mx) + (di - d0)));
+  }
   R g[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
   const R ph = POROUS ? phi[n.cell] : R(1);
-  const R phib = collide_bulk_vjp<Q, R, POROUS>(
-      g, dmu, ph, k, [&](int i, R v) { lam[read_slot<Q, ODD>(n, sm, i, N)] = m + (double)v; });
+  const R phib = collide_bulk_vjp<Q, R, POROUS>(g, dmu, ph, k,
+                                                [&](int i, R v) { dev[read_slot<Q, ODD>(n, sm, i, N)] = v; });
+  m_next[n.cell] = m;
   if (POROUS) grad[n.cell] += (double)phib;
 }
 
-// lam = dJ/df of the current state for the terminal objective
+// Adjoint field = dJ/df of the current state for the terminal objective
 // J = c_s^2 (<rho>_{x=p0} - <rho>_{x=p1}) + <rho |u|^2 / 2>; the fluid-cell
 // counts come from the objective reduction already in cnt[0..2].
 template <int Q, typename S, bool ODD, bool SOLID>
 __global__ __launch_bounds__(ABLOCK) void k_seed(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
-                                                 double *__restrict__ lam, KArgs k, ATiles t, int p0,
+                                                 typename Store<S>::R *__restrict__ dev, double *__restrict__ m_cur, KArgs k,
+                                                 ATiles t, int p0,
                                                  int p1, const double *__restrict__ cnt) {
   int x, y, z;
   if (!atile_xyz(k, t, x, y, z)) return;
@@ -270,36 +293,56 @@ __global__ __launch_bounds__(ABLOCK) void k_seed(const S *__restrict__ pop, cons
   if (x == p0) base += 1.0 / (3.0 * cnt[0]);
   if (x == p1) base -= 1.0 / (3.0 * cnt[1]);
   const double inf = 1.0 / cnt[2];
+  using R = typename Store<S>::R;
+  m_cur[n.cell] = base;  // common mode; the deviations carry the kinetic-energy part
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double cu = dot3(Lat<Q>::c(i, 0), Lat<Q>::c(i, 1), Lat<Q>::c(i, 2), ux, uy, uz);
-    lam[read_slot<Q, ODD>(n, sm, i, N)] = base + (cu - 0.5 * uu) * inf;
+    dev[read_slot<Q, ODD>(n, sm, i, N)] = (R)((cu - 0.5 * uu) * inf);
   }
 }
 
-// Natural order [q][N] <-> in-memory layout of the current parity.
-template <int Q, bool ODD, bool SOLID, bool TO_NATURAL, typename R>
-__global__ __launch_bounds__(ABLOCK) void k_relayout(const uint8_t *__restrict__ flags, const R *__restrict__ src,
-                                                     R *__restrict__ dst, KArgs k, ATiles t) {
+// Natural order [q][N] (FP64 values) <-> in-memory form of the current
+// parity (common mode + deviations; a cell's own read slots are its writes).
+template <int Q, bool ODD, bool SOLID, typename R>
+__global__ __launch_bounds__(ABLOCK) void k_to_natural(const uint8_t *__restrict__ flags,
+                                                       const double *__restrict__ m_cur,
+                                                       const R *__restrict__ dev, double *__restrict__ nat,
+                                                       KArgs k, ATiles t) {
   int x, y, z;
   if (!atile_xyz(k, t, x, y, z)) return;
   const Nb n = make_nb(x, y, z, k);
   const uint8_t fl = flags[n.cell];
   const size_t N = (size_t)k.N;
   if (!(fl & FL_FLUID)) {
-    if (TO_NATURAL)
 #pragma unroll
-      for (int i = 0; i < Q; ++i) dst[(size_t)i * N + n.cell] = R(0);
+    for (int i = 0; i < Q; ++i) nat[(size_t)i * N + n.cell] = 0.0;
     return;
   }
   unsigned sm = 0;
   if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  const double m = m_cur[n.cell];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const size_t s = read_slot<Q, ODD>(n, sm, i, N);
-    if (TO_NATURAL) dst[(size_t)i * N + n.cell] = src[s];
-    else dst[s] = src[(size_t)i * N + n.cell];
-  }
+  for (int i = 0; i < Q; ++i) nat[(size_t)i * N + n.cell] = m + (double)dev[read_slot<Q, ODD>(n, sm, i, N)];
+}
+
+template <int Q, bool ODD, bool SOLID, typename R>
+__global__ __launch_bounds__(ABLOCK) void k_from_natural(const uint8_t *__restrict__ flags,
+                                                         const double *__restrict__ nat,
+                                                         double *__restrict__ m_cur, R *__restrict__ dev,
+                                                         KArgs k, ATiles t) {
+  int x, y, z;
+  if (!atile_xyz(k, t, x, y, z)) return;
+  const Nb n = make_nb(x, y, z, k);
+  const uint8_t fl = flags[n.cell];
+  if (!(fl & FL_FLUID)) return;
+  const size_t N = (size_t)k.N;
+  unsigned sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  const double m = nat[n.cell];
+  m_cur[n.cell] = m;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) dev[read_slot<Q, ODD>(n, sm, i, N)] = (R)(nat[(size_t)i * N + n.cell] - m);
 }
 
 // ---------------------------------------------------------------------------
@@ -325,19 +368,34 @@ static int adispatch(lbm_ctx *ctx, F &&f) {
   return by_geo.template operator()<27, _Float16>();
 }
 
+// Pointers into an adjoint buffer: the common-mode arrays of the current
+// and the other parity, and the deviations.
+struct AdjPtrs {
+  double *m_cur, *m_other;
+  void *dev;
+};
+static AdjPtrs adj_ptrs(lbm_ctx *ctx, void *lamv) {
+  const AdjLayout L = adj_layout(ctx->N, ctx->q, ctx->p.storage == LBM_F64 ? 8 : 4);
+  double *m0 = (double *)lamv, *m1 = m0 + ctx->N;
+  const bool odd = (ctx->steps & 1) != 0;
+  return {odd ? m1 : m0, odd ? m0 : m1, (char *)lamv + L.d_off};
+}
+
 int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv) {
   const ATiles t = atiles_of(ctx->ka);
+  const AdjPtrs a = adj_ptrs(ctx, lamv);
   return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
     using R = typename Store<S>::R;
-    double *lam = (double *)lamv;
+    R *dev = (R *)a.dev;
     double *grad = (double *)gradv;
     const R *phi = (const R *)ctx->phi;
+    // reads the common modes of the later state (the other parity), writes this parity's
     if (ctx->porous)
-      k_adjoint<Q, S, ODD, true, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, lam,
-                                                                              phi, grad, ctx->ka, t);
+      k_adjoint<Q, S, ODD, true, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(
+          (const S *)ctx->pop, ctx->flags, dev, a.m_other, a.m_cur, phi, grad, ctx->ka, t);
     else
-      k_adjoint<Q, S, ODD, false, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags,
-                                                                               lam, phi, grad, ctx->ka, t);
+      k_adjoint<Q, S, ODD, false, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(
+          (const S *)ctx->pop, ctx->flags, dev, a.m_other, a.m_cur, phi, grad, ctx->ka, t);
     return check(ctx, "k_adjoint");
   });
 }
@@ -346,28 +404,35 @@ int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lamv) {
   int rc = dev_objective(ctx, planes);  // fills the fluid-cell counts
   if (rc != LBM_OK) return rc;
   const ATiles t = atiles_of(ctx->ka);
+  const AdjPtrs a = adj_ptrs(ctx, lamv);
   return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
-    k_seed<Q, S, ODD, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, (double *)lamv, ctx->ka,
-                                                                   t, planes[0], planes[1], ctx->result + 8 + 3);
+    using R = typename Store<S>::R;
+    k_seed<Q, S, ODD, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, (R *)a.dev,
+                                                                   a.m_cur, ctx->ka, t, planes[0], planes[1],
+                                                                   ctx->result + 8 + 3);
     return check(ctx, "k_seed");
   });
 }
 
 int dev_layout_to_natural(lbm_ctx *ctx, const void *lamv, void *natv) {
   const ATiles t = atiles_of(ctx->ka);
+  const AdjPtrs a = adj_ptrs(ctx, const_cast<void *>(lamv));
   return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
-    k_relayout<Q, ODD, SOLID, true, double><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, (const double *)lamv,
-                                                                                (double *)natv, ctx->ka, t);
-    return check(ctx, "k_relayout");
+    using R = typename Store<S>::R;
+    k_to_natural<Q, ODD, SOLID, R><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, a.m_cur, (const R *)a.dev,
+                                                                         (double *)natv, ctx->ka, t);
+    return check(ctx, "k_to_natural");
   });
 }
 
 int dev_layout_from_natural(lbm_ctx *ctx, const void *natv, void *lamv) {
   const ATiles t = atiles_of(ctx->ka);
+  const AdjPtrs a = adj_ptrs(ctx, lamv);
   return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
-    k_relayout<Q, ODD, SOLID, false, double><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, (const double *)natv,
-                                                                                 (double *)lamv, ctx->ka, t);
-    return check(ctx, "k_relayout");
+    using R = typename Store<S>::R;
+    k_from_natural<Q, ODD, SOLID, R><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, (const double *)natv,
+                                                                           a.m_cur, (R *)a.dev, ctx->ka, t);
+    return check(ctx, "k_from_natural");
   });
 }
 

@@ -50,6 +50,21 @@ struct KArgs {
   const void *lam;   // [nx] fringe blend weight, compute type (0 before the fringe)
 };
 
+// Adjoint field in caller memory (lbm_adjoint_bytes).  The value of a slot is
+// M[w] + d[slot]: w is the cell that wrote the slot, M[w] its common mode
+// (FP64, one array per layout parity) and d the deviation in the compute type
+// (FP64 for FP64 storage, FP32 otherwise).  Two arrays of N doubles, then q
+// arrays of N deviations from a 256-byte boundary.
+struct AdjLayout {
+  size_t d_off, bytes;
+};
+inline AdjLayout adj_layout(long long N, int q, size_t dev_bytes) {
+  AdjLayout L;
+  L.d_off = ((size_t)2 * (size_t)N * sizeof(double) + 255) & ~(size_t)255;
+  L.bytes = L.d_off + (size_t)q * (size_t)N * dev_bytes;
+  return L;
+}
+
 }  // namespace lbmk
 
 namespace lbmk {

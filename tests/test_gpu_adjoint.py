@@ -58,7 +58,7 @@ def test_transpose_one_step(gpu):
         lat.load_state(snap)
         grad = torch.zeros(N, dtype=torch.float64, device="cuda")
         gpu.lbm_adjoint_step(lat.ctx, lam, grad)
-        nat = torch.empty_like(lam)
+        nat = lat.new_natural()
         gpu.lbm_adjoint_to_natural(lat.ctx, lam, nat)
         lat.sync()
         rhs = float((v * nat.cpu().numpy()).sum() + (dphi * grad.cpu().numpy()).sum())
