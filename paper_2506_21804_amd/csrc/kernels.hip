@@ -11,7 +11,7 @@
 //                      reconstruction (equilibrium at the modeled velocity
 //                      plus the non-equilibrium of Eq. (10) built from the
 //                      wall-law strain) and the AA scatter;
-//   K2 k_bulk          one thread per cell (64x4 tiles): AA gather, BGK
+//   K2 k_bulk          one thread per cell (128x2 tiles): AA gather, BGK
 //                      collision with the Smagorinsky tau_eff (Eqs. (3),(4),
 //                      (14)), homogenized velocity (Eq. (12)), Guo forcing,
 //                      fringe/lid, AA scatter; skips wall cells.  It runs last
@@ -29,8 +29,14 @@
 
 namespace lbmk {
 
-constexpr int TX = 64;  // tile width in x (one wavefront)
-constexpr int TY = 4;   // tile height in y (four wavefronts per block)
+// Tile of one block: two rows of 128 cells, each row two wavefronts wide.
+// On odd steps the x-shifted accesses of a wavefront straddle cache lines;
+// with the neighbouring wavefront of the same row in the same block, the
+// partial lines are completed while still in L2 (measured: 1-2 % faster K2
+// than 64 x 4 tiles on the channel and the urban canopy; 256 x 1 loses on
+// widths that are not multiples of 256).
+constexpr int TX = 128;  // tile width in x (power of two)
+constexpr int TY = 2;    // tile height in y
 constexpr int BLOCK = TX * TY;
 
 struct Tiles {
@@ -239,29 +245,40 @@ __global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8
 }
 
 // ---------------------------------------------------------------------------
-// K1: wall prepass (FP64).  Spalding function g(u+) = u+ + R(kappa u+)/E
-// with R(a) = exp(a) - 1 - a - a^2/2 - a^3/6, and its derivative; below
-// a = 1/2 the remainders are summed as power series (no cancellation).
+// Wall record (FP64).  Spalding function g(u+) = u+ + R4(kappa u+)/E with
+// R_m(a) = exp(a) - sum_{n<m} a^n/n!, and g'(u+) = 1 + kappa R3(kappa u+)/E.
+// Below a = 1/2 the remainders are summed as their power series (no
+// cancellation), by Horner over 24 terms with reciprocal factorials as
+// compile-time constants.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double series_tail(double a, int from) {
-  double term = 1.0;
-  for (int n = 1; n <= from; ++n) term *= a / n;
-  double sum = 0.0;
-  for (int n = from; n < from + 24; ++n) {
-    sum += term;
-    term *= a / (n + 1);
+__host__ __device__ constexpr double inv_factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return 1.0 / f;
+}
+template <int M>
+__device__ __forceinline__ double exp_tail(double a) {
+  double p = inv_factorial(M + 23);
+#pragma unroll
+  for (int n = M + 22; n >= M; --n) p = fma(p, a, inv_factorial(n));
+  double am = a;
+#pragma unroll
+  for (int n = 1; n < M; ++n) am *= a;
+  return p * am;
+}
+// g and g' at u+ (one exponential for both); inv_E = 1/E.
+__device__ __forceinline__ void spalding_gd(double up, double kappa, double inv_E, double &g, double &gd) {
+  const double a = kappa * up;
+  double r3, r4;
+  if (a >= 0.0 && a < 0.5) {
+    r4 = exp_tail<4>(a);
+    r3 = exp_tail<3>(a);
+  } else {
+    r3 = exp(a) - 1.0 - a - 0.5 * a * a;
+    r4 = r3 - a * a * a * (1.0 / 6.0);
   }
-  return sum;
-}
-__device__ __forceinline__ double spalding(double up, double kappa, double E) {
-  const double a = kappa * up;
-  const double r = (a >= 0.0 && a < 0.5) ? series_tail(a, 4) : exp(a) - 1.0 - a - 0.5 * a * a - a * a * a / 6.0;
-  return up + r / E;
-}
-__device__ __forceinline__ double spalding_d(double up, double kappa, double E) {
-  const double a = kappa * up;
-  const double r = (a >= 0.0 && a < 0.5) ? series_tail(a, 3) : exp(a) - 1.0 - a - 0.5 * a * a;
-  return 1.0 + kappa * r / E;
+  g = up + r4 * inv_E;
+  gd = 1.0 + kappa * r3 * inv_E;
 }
 
 // Wall record of wall cell w (reference cell r, wall cell b): reads the
@@ -298,17 +315,32 @@ __device__ __forceinline__ void wall_record(const S *__restrict__ pop, const uin
   bool fail = false;
   if (U > 1e-300) {
     const double yr = rec[WR_YR * M + w], yb = rec[WR_YB * M + w];
-    // F(u) = g(U/u) - yr u / nu, convex and decreasing; start at the laminar
-    // value sqrt(nu U / yr) where F >= 0, so Newton climbs monotonically.
-    double ut = sqrt(nu * U / yr);
+    // F(u) = g(U/u) - yr u / nu is convex and decreasing in u, and the
+    // laminar value ulam = sqrt(nu U / yr) is a lower bound of its root.  From
+    // any start, the first Newton step lands at or below the root; clamping
+    // every iterate to ulam keeps it in range, and from there the iterates
+    // climb monotonically.  The start is the log-law friction velocity (two
+    // fixed-point steps of u = kappa U / ln(E yr u / nu) from ulam), within a
+    // few per cent of the root: at y+ of 100-250 Newton then needs about 5
+    // iterations instead of 17-29 from ulam.  The root is the same.
+    const double ulam = sqrt(nu * U / yr);
+    double ut = ulam;
+    for (int j = 0; j < 2; ++j) {
+      const double L = log(E * yr * ut / nu);
+      if (L > 1.0) ut = fmax(ulam, kap * U / L);
+    }
     bool conv = false;
-    if (kap * U / ut <= 700.0) {
+    const double inv_E = 1.0 / E, a_r = yr / nu;  // F(u) = g(U/u) - a_r u
+    if (kap * U / ulam <= 700.0) {
       for (int it = 0; it < 100; ++it) {
-        const double xx = U / ut;
-        const double Fv = spalding(xx, kap, E) - yr * ut / nu;
-        const double dF = -spalding_d(xx, kap, E) * U / (ut * ut) - yr / nu;
+        const double iu = 1.0 / ut;
+        const double xx = U * iu;
+        double gv, gdv;
+        spalding_gd(xx, kap, inv_E, gv, gdv);
+        const double Fv = gv - a_r * ut;
+        const double dF = -gdv * xx * iu - a_r;
         const double st = -Fv / dF;
-        ut += st;
+        ut = fmax(ut + st, ulam);
         if (fabs(st) <= 1e-15 * ut) {
           conv = true;
           break;
@@ -322,11 +354,13 @@ __device__ __forceinline__ void wall_record(const S *__restrict__ pop, const uin
       const double ypb = yb * ut / nu;
       const double K = kap * ypb;
       double s = fmin(ypb, log(E * ypb + 1.0 + K + 0.5 * K * K + K * K * K / 6.0) / kap);
-      if (yr >= yb) s = fmin(s, U / ut);
+      if (yr >= yb) s = fmin(s, up);
       conv = false;
       if (kap * s <= 700.0) {
         for (int it = 0; it < 100; ++it) {
-          const double st = -(spalding(s, kap, E) - ypb) / spalding_d(s, kap, E);
+          double gv, gdv;
+          spalding_gd(s, kap, inv_E, gv, gdv);
+          const double st = -(gv - ypb) / gdv;
           s += st;
           if (fabs(st) <= 1e-15 * fabs(s)) {
             conv = true;
@@ -382,10 +416,6 @@ __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nwall) return;
   const int b = wcell[w];
-  // the record of a wall cell whose reference is not a wall cell is computed
-  // here (no other thread of this launch writes that reference); the others
-  // were computed by k_wall_prepass before this launch
-  if (!refwall[w]) wall_record<Q, S, ODD>(pop, flags, w, b, wref[w], rec, nwall, k, errflag);
   int x, y, z;
   cell_xyz(b, k, x, y, z);
   const Nb n = make_nb(x, y, z, k);
@@ -401,6 +431,11 @@ __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t
     acc(jy, Lat<Q>::c(i, 1), g[i]);
     acc(jz, Lat<Q>::c(i, 2), g[i]);
   }
+  // The record of a wall cell whose reference is not a wall cell is computed
+  // here (no other thread of this launch writes that reference); the others
+  // were computed by k_wall_prepass before this launch.  It comes after the
+  // loads above, so that their latency overlaps the Newton solves.
+  if (!refwall[w]) wall_record<Q, S, ODD>(pop, flags, w, b, wref[w], rec, nwall, k, errflag);
   const R rho = R(1) + drho;
   if (!finite_pos(rho)) atomicOr(errflag, 1);
   const R Fx = R(k.F[0]), Fy = R(k.F[1]), Fz = R(k.F[2]);
