@@ -57,6 +57,8 @@ def make_case(name):
         return case, ("f16" if name.endswith("16") else "f32"), "urban1024x1024x1024_d3q27_smag_wallmodel_fringe_lid"
     if name == "tgv":
         return I.taylor_green(32, q=19), "f64", "tgv32_d3q19_smag"
+    if name in ("cavity", "cavity16"):
+        return I.cavity(575, q=19), ("f16" if name.endswith("16") else "f32"), "cavity575_d3q19_smag_lid"
     if name == "adjoint":
         return I.porous_channel(128), "f32", "porous_channel128_d3q19_adjoint"
     raise SystemExit(f"unknown workload {name}")
@@ -76,6 +78,9 @@ def cpu_baseline(name, budget_s=12.0):
     elif name == "tgv":
         case = I.taylor_green(32, q=19)
         sample = "tgv 32^3 D3Q19 FP64 (full)"
+    elif name.startswith("cavity"):
+        case = I.cavity(128, q=19)
+        sample = "cavity 128^3 D3Q19 FP64 (same recipe, smaller box)"
     else:
         case = I.porous_channel(shape=(128, 128, 16))
         sample = "porous channel crop 128x128x16 D3Q19 FP64"
@@ -123,6 +128,8 @@ def main():
     ap.add_argument("--workload", default="channel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=2000,
+                    help="precision workload: second horizon, with mean-profile errors")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -228,37 +235,69 @@ def main():
 
 
 def bench_precision(args, torch, lbm):
-    """FP32- and FP16-deviation storage against FP64 storage on the same GPU
-    after the same number of steps from the same initial state (the FP64 path
-    matches the CPU oracle to 1e-14).  Errors are max-norms relative to the
-    FP64 field's max-norm."""
+    """FP32- and FP16-deviation storage against FP64 storage on the same GPU,
+    from the same initial state (the FP64 path matches the CPU oracle to
+    1e-14).  Pointwise errors of rho and u after 100 steps (max-norms relative
+    to the FP64 field's max-norm, and the rms of u), and after
+    ``--profile-steps`` steps the same plus the error of the mean streamwise
+    velocity profile <u_x>(z) (plane averages over fluid cells, relative to
+    the FP64 profile's maximum)."""
     from paper_2506_21804_amd import inputs as I
-    steps = args.steps
+    horizons = (100, args.profile_steps)
     rows = {}
+
+    def errors(ref, rho, u, mask3):
+        out = {"rho": float((rho - ref[0]).abs().max() / ref[0].abs().max()),
+               "u": float((u - ref[1]).abs().max() / ref[1].abs().max()),
+               "u_rms": float(((u - ref[1]) ** 2).mean().sqrt() / (ref[1] ** 2).mean().sqrt())}
+        return out
+
+    def profile(u, mask3, shape):
+        nx, ny, nz = shape
+        ux = u[0].reshape(nz, ny, nx)
+        cnt = mask3.sum(dim=(1, 2)).clamp(min=1)
+        return (ux * mask3).sum(dim=(1, 2)) / cnt
+
     for wname, make in (("channel384x192x192", lambda: I.channel(384, 192, 192, q=27)),
                         ("urban768x768x256", lambda: I.urban(768, 768, 256, q=27, with_wall_dist=False))):
         case = make()
-        res = {}
-        ref = None
+        nx, ny, nz = case.shape
+        mask3 = (torch.ones((nz, ny, nx), dtype=torch.float64, device="cuda") if case.mask is None else
+                 torch.as_tensor(case.mask.reshape(nz, ny, nx), device="cuda").to(torch.float64))
+        res = {f"{h} steps": {} for h in horizons}
+        refs = {}
         for storage in ("f64", "f32", "f16"):
             lat = lbm.Lattice(case, storage=storage, wall_dist=None if case.wall_dist is None else "case")
-            lat.step(steps)
-            rho, u = lat.moments()
-            rho, u = rho.double(), u.double()
-            if ref is None:
-                ref = (rho, u)
-            else:
-                res[storage] = {"rho": float((rho - ref[0]).abs().max() / ref[0].abs().max()),
-                                "u": float((u - ref[1]).abs().max() / ref[1].abs().max()),
-                                "u_rms": float(((u - ref[1]) ** 2).mean().sqrt() / (ref[1] ** 2).mean().sqrt())}
-            del lat, rho, u
+            done = 0
+            try:
+                for h in horizons:
+                    lat.step(h - done)
+                    done = h
+                    rho, u = lat.moments()
+                    rho, u = rho.double(), u.double()
+                    prof = profile(u, mask3, case.shape)
+                    key = f"{h} steps"
+                    if storage == "f64":
+                        refs[h] = (rho, u, prof)
+                    else:
+                        ref = refs[h]
+                        e = errors(ref, rho, u, mask3)
+                        e["mean_profile_ux"] = float((prof - ref[2]).abs().max() / ref[2].abs().max())
+                        res[key][storage] = e
+                    del rho, u
+            except RuntimeError as exc:  # a run that stops (e.g. non-finite state) is reported, not hidden
+                res.setdefault(f"failed by step {done}", {})[storage] = str(exc)
+            print(f"[bench] precision {wname} {storage}: {done} steps done", file=sys.stderr, flush=True)
+            del lat
             torch.cuda.empty_cache()
         rows[wname] = res
-        del case, ref
+        del case, refs, mask3
+        torch.cuda.empty_cache()
         print(f"[bench] precision {wname}: {res}", file=sys.stderr, flush=True)
+    ch = rows["channel384x192x192"].get("100 steps", {}).get("f16", {})
     out = {"metric": "moment error of FP32/FP16 deviation storage vs FP64 storage (same GPU, same steps)",
-           "value": rows["channel384x192x192"]["f16"]["u"], "unit": "max-norm relative error of u (FP16, channel)",
-           "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+           "value": ch.get("u"), "unit": "max-norm relative error of u (FP16, channel, 100 steps)",
+           "n_gpus": 1, "steps": horizons[-1], "warmup": 0, "ms_per_step": None, "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32 compute", "data": "synthetic",
            "config": {"workload": "channel384x192x192 and urban768x768x256, D3Q27"}, "errors": rows}
     print(json.dumps(out), flush=True)

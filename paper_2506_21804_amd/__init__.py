@@ -390,11 +390,16 @@ class Lattice:
     def __del__(self):
         ctx = getattr(self, "ctx", None)
         if ctx:
+            # at interpreter shutdown the module's globals may already be gone;
+            # the process then releases everything itself
             try:
                 lbm_sync(ctx)
             except Exception:
                 pass
-            lbm_free(ctx)
+            try:
+                lbm_free(ctx)
+            except Exception:
+                pass
             self.ctx = None
 
     def step(self, n=1):

@@ -245,6 +245,17 @@ def urban_u0_device(case: Case):
     return u.reshape(3, -1)
 
 
+def cavity(n=575, q: int = 19, u_lid: float = 0.05, tau0: float = 0.51, cs_smag: float = 0.1) -> Case:
+    """Lid-driven cavity: a box of fluid (n^3, or n = (nx, ny, nz)) with every
+    axis non-periodic, so all six faces are halfway bounce-back walls, and the
+    top plane held at the lid equilibrium of velocity u_lid along x.  Starts at
+    rest; no wall model, no force.  575^3 is the smallest of the paper's
+    scaling problems and one GPU's share of 1449^3 on 16 GPUs."""
+    shape = (n, n, n) if isinstance(n, int) else tuple(n)
+    name = f"cavity{shape[0]}" if len(set(shape)) == 1 else "cavity{}x{}x{}".format(*shape)
+    return Case(name=name, q=q, shape=shape, periodic=(0, 0, 0), tau0=tau0, cs_smag=cs_smag, u_ref=u_lid, lid=1)
+
+
 def porosity_field(shape, seed_offset: int = 4, passes: int = 3, width: int = 9) -> np.ndarray:
     """Smoothed noise in [0, 1]: U(0,1) noise, ``passes`` periodic box filters
     of ``width`` cells along each axis, then min-max normalisation."""
