@@ -43,6 +43,7 @@ class Params(C.Structure):
         ("fringe_len", C.c_int),
         ("u_ref", C.c_double), ("z0", C.c_double),
         ("lid", C.c_int),
+        ("collision", C.c_int),
     ]
 
 
@@ -88,6 +89,8 @@ def lib():
         L.orc_tau_eff.restype = C.c_double
         L.orc_tau_eff.argtypes = [C.c_double] * 4
         L.orc_collide_bulk.argtypes = [C.c_int, C.c_double, C.c_double, vp, C.c_double, vp, vp]
+        L.orc_collide_bulk2.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, vp, C.c_double, vp, vp]
+        L.orc_equilibrium3.argtypes = [C.c_int, C.c_double, vp, vp]
         L.orc_spalding_yplus.restype = C.c_double
         L.orc_spalding_yplus.argtypes = [C.c_double] * 3
         L.orc_spalding_uplus.argtypes = [C.c_double, C.c_double, C.c_double, dp]
@@ -101,7 +104,8 @@ def _ptr(a):
 
 
 def make_params(q, shape, periodic=(1, 1, 1), tau0=0.6, cs_smag=0.0, force=(0.0, 0.0, 0.0),
-                wall_model=0, kappa=0.41, E=9.0, fringe_len=0, u_ref=0.0, z0=1.0, lid=0) -> Params:
+                wall_model=0, kappa=0.41, E=9.0, fringe_len=0, u_ref=0.0, z0=1.0, lid=0,
+                collision=0) -> Params:
     p = Params()
     p.q = q
     p.nx, p.ny, p.nz = shape
@@ -110,6 +114,7 @@ def make_params(q, shape, periodic=(1, 1, 1), tau0=0.6, cs_smag=0.0, force=(0.0,
     p.force = (C.c_double * 3)(*force)
     p.wall_model, p.kappa, p.E = wall_model, kappa, E
     p.fringe_len, p.u_ref, p.z0, p.lid = fringe_len, u_ref, z0, lid
+    p.collision = collision
     return p
 
 
@@ -229,6 +234,14 @@ def equilibrium(q, rho, u):
     return out
 
 
+def equilibrium3(q, rho, u):
+    """Third-order equilibrium of the recursive regularized collision."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.empty(q)
+    lib().orc_equilibrium3(q, float(rho), _ptr(u), _ptr(out))
+    return out
+
+
 def tau_eff(tau0, cs, pinorm, rho):
     return lib().orc_tau_eff(tau0, cs, pinorm, rho)
 
@@ -238,6 +251,15 @@ def collide_bulk(q, tau0, cs, force, phi, fin):
     force = np.ascontiguousarray(force, dtype=np.float64)
     out = np.empty(q)
     lib().orc_collide_bulk(q, tau0, cs, _ptr(force), float(phi), _ptr(fin), _ptr(out))
+    return out
+
+
+def collide_bulk_rr(q, tau0, cs, force, phi, fin):
+    """Bulk collision of the recursive regularized model (third order)."""
+    fin = np.ascontiguousarray(fin, dtype=np.float64)
+    force = np.ascontiguousarray(force, dtype=np.float64)
+    out = np.empty(q)
+    lib().orc_collide_bulk2(q, 1, tau0, cs, _ptr(force), float(phi), _ptr(fin), _ptr(out))
     return out
 
 

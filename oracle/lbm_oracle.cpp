@@ -31,7 +31,13 @@
  * Readings of the paper where it is silent or garbled (each is also listed
  * in the design document):
  *   - lattice units, dx = dt = 1, c_s^2 = 1/3;
- *   - second-order equilibrium (BGK) for the hot path;
+ *   - collision 0: second-order equilibrium (BGK); collision 1: the
+ *     recursive regularized collision of Sec. 2.2 with sigma = 1 (Eqs. (6),
+ *     (8), (9), (11)): third-order equilibrium, f^(1) rebuilt from its
+ *     Hermite coefficients of order 1 (sum xi f^(1), which the Guo velocity
+ *     makes -F/2), 2 (Pi^neq) and 3 (by the recursion u_a Pi_bc + u_b Pi_ac
+ *     + u_c Pi_ab), each third-order term projected on the Hermite
+ *     components the lattice carries (see hermite3 below);
  *   - f^(1) = f - f^eq(rho, u); f* = f^eq(rho, u_hat) + (1 - 1/tau)(f - f^eq(rho,u));
  *   - porosity phi in [0,1], 1 = fluid: u_hat = phi*u + (1-phi)*u_B, u_B = 0
  *     in the bulk (the weights of Eq. (12) read with d := 1 - phi);
@@ -51,6 +57,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <string>
 #include <vector>
 #ifdef _OPENMP
@@ -69,6 +76,7 @@ typedef struct {
   int fringe_len;
   double u_ref, z0;
   int lid;
+  int collision; /* 0: BGK (second-order equilibrium); 1: recursive regularized, third order */
 } orc_params;
 }
 
@@ -154,6 +162,107 @@ void equilibrium(const VelSet& vs, const T& rho, const T v[3], T* feq) {
     T cv = double(vs.c[i][0]) * v[0] + double(vs.c[i][1]) * v[1] + double(vs.c[i][2]) * v[2];
     feq[i] = vs.w[i] * rho * (1.0 + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
   }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Third-order Hermite terms of the recursive regularized collision         */
+/* (Sec. 2.2, Eqs. (8), (9), (11)).                                          */
+/*   H^(3)_abc(xi) = xi_a xi_b xi_c - c_s^2 (xi_a d_bc + xi_b d_ac + xi_c d_ab) */
+/* Only components the lattice can carry enter.  On D3Q27 these are the six  */
+/* of type xxy and xyz, mutually orthogonal in the weighted lattice sum      */
+/* sum_i w_i P_i Q_i (xxx vanishes: xi^3 = xi).  On D3Q19 xyz vanishes too,   */
+/* and the pairs (xxy, yzz), (xzz, xyy), (yyz, xxz) are not orthogonal there, */
+/* so their sums and differences form the basis.  A symmetric third-order     */
+/* tensor A enters as its orthogonal projection on that basis,               */
+/*   w_i sum_P P_i <A, P> / (sum_j w_j P_j^2),  <A, P> = sum of A over the    */
+/* components of P with their signs,                                         */
+/* so that every admissible third moment sum_i P_i out_i equals <A, P>.       */
+/* The norms come from the lattice itself, not from the continuous Hermite    */
+/* norms (on D3Q19 they differ).                                             */
+/* ------------------------------------------------------------------------ */
+double hermite3(const VelSet& vs, int i, int a, int b, int c) {
+  const double cs2 = 1.0 / 3.0;
+  double xa = vs.c[i][a], xb = vs.c[i][b], xc = vs.c[i][c];
+  return xa * xb * xc - cs2 * (xa * (b == c) + xb * (a == c) + xc * (a == b));
+}
+
+struct H3Basis {
+  int n = 0;
+  int ncomp[7];
+  int comp[7][2][3];
+  double sgn[7][2];
+  double P[7][27];
+  double norm[7];
+};
+
+H3Basis make_h3_basis(const VelSet& vs) {
+  enum { X = 0, Y = 1, Z = 2 };
+  H3Basis B;
+  auto add = [&](std::initializer_list<int> t1, std::initializer_list<int> t2, double s2) {
+    int k = B.n++;
+    const int* a = t1.begin();
+    for (int m = 0; m < 3; ++m) B.comp[k][0][m] = a[m];
+    B.sgn[k][0] = 1.0;
+    B.ncomp[k] = 1;
+    if (t2.size() == 3) {
+      const int* b = t2.begin();
+      for (int m = 0; m < 3; ++m) B.comp[k][1][m] = b[m];
+      B.sgn[k][1] = s2;
+      B.ncomp[k] = 2;
+    }
+  };
+  if (vs.q == 27) {
+    add({X, X, Y}, {}, 0.0);
+    add({X, X, Z}, {}, 0.0);
+    add({X, Y, Y}, {}, 0.0);
+    add({Y, Y, Z}, {}, 0.0);
+    add({X, Z, Z}, {}, 0.0);
+    add({Y, Z, Z}, {}, 0.0);
+    add({X, Y, Z}, {}, 0.0);
+  } else {
+    add({X, X, Y}, {Y, Z, Z}, 1.0);
+    add({X, X, Y}, {Y, Z, Z}, -1.0);
+    add({X, Z, Z}, {X, Y, Y}, 1.0);
+    add({X, Z, Z}, {X, Y, Y}, -1.0);
+    add({Y, Y, Z}, {X, X, Z}, 1.0);
+    add({Y, Y, Z}, {X, X, Z}, -1.0);
+  }
+  for (int k = 0; k < B.n; ++k) {
+    B.norm[k] = 0.0;
+    for (int i = 0; i < vs.q; ++i) {
+      double v = 0.0;
+      for (int m = 0; m < B.ncomp[k]; ++m)
+        v += B.sgn[k][m] * hermite3(vs, i, B.comp[k][m][0], B.comp[k][m][1], B.comp[k][m][2]);
+      B.P[k][i] = v;
+      B.norm[k] += vs.w[i] * v * v;
+    }
+  }
+  return B;
+}
+
+/* out_i = w_i sum_P P_i <A, P> / |P|^2 for a symmetric tensor A[3][3][3]. */
+template <class T>
+void third_order_term(const VelSet& vs, const H3Basis& B, const T A[3][3][3], T* out) {
+  for (int i = 0; i < vs.q; ++i) out[i] = T(0.0);
+  for (int k = 0; k < B.n; ++k) {
+    T m(0.0);
+    for (int r = 0; r < B.ncomp[k]; ++r) m += B.sgn[k][r] * A[B.comp[k][r][0]][B.comp[k][r][1]][B.comp[k][r][2]];
+    T coef = m / B.norm[k];
+    for (int i = 0; i < vs.q; ++i) out[i] += (vs.w[i] * B.P[k][i]) * coef;
+  }
+}
+
+/* Third-order equilibrium (Eq. (11) with the H^(3) term of a_0^(3) = rho v v v). */
+template <class T>
+void equilibrium3(const VelSet& vs, const H3Basis& B, const T& rho, const T v[3], T* feq) {
+  equilibrium(vs, rho, v, feq);
+  T A[3][3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c) A[a][b][c] = rho * v[a] * v[b] * v[c];
+  T t[27];
+  third_order_term(vs, B, A, t);
+  for (int i = 0; i < vs.q; ++i) feq[i] += t[i];
 }
 
 /* Guo source term for population i: w_i [3(xi_i - v) + 9 (xi_i.v) xi_i].F. */
@@ -270,6 +379,7 @@ template <class T>
 struct Sim : SimBase {
   orc_params p;
   VelSet vs;
+  H3Basis h3;
   long N = 0;
   std::vector<uint8_t> fluid, kind;
   std::vector<T> phi;
@@ -282,6 +392,11 @@ struct Sim : SimBase {
   std::vector<double> wt, wutan, wG, wtau, wutau;
 
   long idx(int x, int y, int z) const { return x + (long)p.nx * (y + (long)p.ny * z); }
+  /* The equilibrium of the selected collision model (second or third order). */
+  void eqm(const T& rho, const T v[3], T* feq) const {
+    if (p.collision == 1) equilibrium3(vs, h3, rho, v, feq);
+    else equilibrium(vs, rho, v, feq);
+  }
   void coords(long c, int& x, int& y, int& z) const {
     x = int(c % p.nx);
     y = int((c / p.nx) % p.ny);
@@ -323,7 +438,12 @@ struct Sim : SimBase {
       err = "tau0 must exceed 1/2 and C_S must be >= 0";
       return ORC_EINVAL;
     }
+    if (p.collision != 0 && p.collision != 1) {
+      err = "collision must be 0 (BGK) or 1 (recursive regularized)";
+      return ORC_EINVAL;
+    }
     vs = make_velocity_set(p.q);
+    h3 = make_h3_basis(vs);
     N = (long)p.nx * p.ny * p.nz;
     fluid.assign(N, 1);
     if (mask)
@@ -403,7 +523,7 @@ struct Sim : SimBase {
       T v[3];
       for (int a = 0; a < 3; ++a) v[a] = u0 ? T(u0[(size_t)a * N + c]) : T(0.0);
       T feq[27];
-      equilibrium(vs, r, v, feq);
+      eqm(r, v, feq);
       for (int i = 0; i < vs.q; ++i) f[(size_t)i * N + c] = feq[i];
     }
     return ORC_OK;
@@ -468,7 +588,9 @@ struct Sim : SimBase {
     return status;
   }
 
-  /* Bulk cell (sigma = 1): homogenized BGK-Smagorinsky with Guo forcing. */
+  /* Bulk cell (sigma = 1): homogenized Smagorinsky collision with Guo
+   * forcing; BGK (collision 0) keeps all of f - f^eq, the recursive
+   * regularized model (collision 1) keeps its Hermite reconstruction. */
   bool collide_bulk(long c, T* fo) const {
     T fi[27];
     T rho(0.0), j[3] = {T(0.0), T(0.0), T(0.0)};
@@ -480,7 +602,7 @@ struct Sim : SimBase {
     T u[3];
     for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * p.force[a]) / rho;
     T feq[27];
-    equilibrium(vs, rho, u, feq);
+    eqm(rho, u, feq);
     T Pi[3][3];
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) Pi[a][b] = T(0.0);
@@ -496,10 +618,37 @@ struct Sim : SimBase {
     T uh[3];
     for (int a = 0; a < 3; ++a) uh[a] = phi[c] * u[a];
     T feqh[27];
-    equilibrium(vs, rho, uh, feqh);
-    for (int i = 0; i < vs.q; ++i)
-      fo[i] = feqh[i] + (1.0 - 1.0 / tau) * (fi[i] - feq[i]) +
-              (1.0 - 0.5 / tau) * guo_term(vs, i, u, p.force);
+    eqm(rho, uh, feqh);
+    if (p.collision == 1) {
+      /* f^(1) from its Hermite coefficients (Eqs. (8), (9), n = 0..3):
+       * a^(0) = sum f^(1) = 0; a^(1) = sum xi f^(1) (with the Guo velocity
+       * this is -F/2); a^(2) = Pi; and by the recursion
+       * a^(3)_abc = u_a Pi_bc + u_b Pi_ac + u_c Pi_ab */
+      T a1[3] = {T(0.0), T(0.0), T(0.0)};
+      for (int i = 0; i < vs.q; ++i)
+        for (int a = 0; a < 3; ++a) a1[a] += double(vs.c[i][a]) * (fi[i] - feq[i]);
+      T A[3][3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          for (int g = 0; g < 3; ++g) A[a][b][g] = u[a] * Pi[b][g] + u[b] * Pi[a][g] + u[g] * Pi[a][b];
+      T t3[27];
+      third_order_term(vs, h3, A, t3);
+      T trPi = Pi[0][0] + Pi[1][1] + Pi[2][2];
+      for (int i = 0; i < vs.q; ++i) {
+        T cPc(0.0);
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) cPc += double(vs.c[i][a] * vs.c[i][b]) * Pi[a][b];
+        T ca1 = double(vs.c[i][0]) * a1[0] + double(vs.c[i][1]) * a1[1] + double(vs.c[i][2]) * a1[2];
+        /* w_i H^(1)_i . a^(1) / c_s^2 = 3 w_i xi.a1;
+         * w_i H^(2)_i : Pi / (2 c_s^4) = 9/2 w_i (xi.Pi.xi - c_s^2 tr Pi) */
+        T f1 = 3.0 * vs.w[i] * ca1 + 4.5 * vs.w[i] * (cPc - trPi / 3.0) + t3[i];
+        fo[i] = feqh[i] + (1.0 - 1.0 / tau) * f1 + (1.0 - 0.5 / tau) * guo_term(vs, i, u, p.force);
+      }
+    } else {
+      for (int i = 0; i < vs.q; ++i)
+        fo[i] = feqh[i] + (1.0 - 1.0 / tau) * (fi[i] - feq[i]) +
+                (1.0 - 0.5 / tau) * guo_term(vs, i, u, p.force);
+    }
     return std::isfinite(val(rho)) && val(rho) > 0.0;
   }
 
@@ -521,7 +670,7 @@ struct Sim : SimBase {
     for (int a = 0; a < 3; ++a) uw[a] = wutan[k] * t[a] + un * n[a];
     double tau = wtau[k], G = wG[k];
     T feq[27];
-    equilibrium(vs, rho, uw, feq);
+    eqm(rho, uw, feq);
     for (int i = 0; i < vs.q; ++i) {
       double ct = vs.c[i][0] * t[0] + vs.c[i][1] * t[1] + vs.c[i][2] * t[2];
       double cn = vs.c[i][0] * n[0] + vs.c[i][1] * n[1] + vs.c[i][2] * n[2];
@@ -547,7 +696,7 @@ struct Sim : SimBase {
           T fo[27];
           if (kind[c] == K_LID) {
             T v[3] = {T(u_in(p.nz - 0.5)), T(0.0), T(0.0)};
-            equilibrium(vs, T(1.0), v, fo);
+            eqm(T(1.0), v, fo);
           } else if (kind[c] == K_WALL) {
             if (!collide_wall(c, wall_index[c], fo)) bad = 1;
           } else {
@@ -558,7 +707,7 @@ struct Sim : SimBase {
             double lam = s * s * (3.0 - 2.0 * s);
             T v[3] = {T(u_in(z + 0.5)), T(0.0), T(0.0)};
             T fin[27];
-            equilibrium(vs, T(1.0), v, fin);
+            eqm(T(1.0), v, fin);
             for (int i = 0; i < vs.q; ++i) fo[i] = (1.0 - lam) * fo[i] + lam * fin[i];
           }
           for (int i = 0; i < vs.q; ++i) fs[(size_t)i * N + c] = fo[i];
@@ -778,23 +927,36 @@ void orc_equilibrium(int q, double rho, const double* u, double* feq) {
   double uu[3] = {u[0], u[1], u[2]};
   equilibrium(v, rho, uu, feq);
 }
+void orc_equilibrium3(int q, double rho, const double* u, double* feq) {
+  VelSet v = make_velocity_set(q);
+  H3Basis B = make_h3_basis(v);
+  double uu[3] = {u[0], u[1], u[2]};
+  equilibrium3(v, B, rho, uu, feq);
+}
 double orc_tau_eff(double tau0, double cs, double pinorm, double rho) {
   return tau_effective(tau0, cs, pinorm, rho);
 }
-/* One bulk-cell collision of populations fin (FP64), porosity phi. */
-void orc_collide_bulk(int q, double tau0, double cs, const double* force, double phi, const double* fin,
-                      double* fout) {
+/* One bulk-cell collision of populations fin (FP64), porosity phi;
+ * collision 0 = BGK, 1 = recursive regularized. */
+void orc_collide_bulk2(int q, int collision, double tau0, double cs, const double* force, double phi,
+                       const double* fin, double* fout) {
   Sim<double> s;
   s.p = orc_params{};
   s.p.q = q;
+  s.p.collision = collision;
   s.p.tau0 = tau0;
   s.p.cs_smag = cs;
   for (int a = 0; a < 3; ++a) s.p.force[a] = force[a];
   s.vs = make_velocity_set(q);
+  s.h3 = make_h3_basis(s.vs);
   s.N = 1;
   s.f.assign(fin, fin + q);
   s.phi.assign(1, phi);
   s.collide_bulk(0, fout);
+}
+void orc_collide_bulk(int q, double tau0, double cs, const double* force, double phi, const double* fin,
+                      double* fout) {
+  orc_collide_bulk2(q, 0, tau0, cs, force, phi, fin, fout);
 }
 /* One wall-cell reconstruction collision for given wall records. */
 void orc_collide_wall(int q, double tau0, double cs, const double* force, const double* fin, const double* normal,

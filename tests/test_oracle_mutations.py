@@ -12,6 +12,7 @@ import pytest
 
 import oracle as O
 import test_oracle_pins as pins
+import test_oracle_pins_rr as pins_rr
 
 SRC = os.path.join(os.path.dirname(O.__file__), "lbm_oracle.cpp")
 
@@ -19,8 +20,8 @@ SRC = os.path.join(os.path.dirname(O.__file__), "lbm_oracle.cpp")
 MUTATIONS = [
     ("half-force velocity shift dropped", "u[a] = (j[a] + 0.5 * p.force[a]) / rho;\n    T feq[27];",
      "u[a] = (j[a] + 0.0 * p.force[a]) / rho;\n    T feq[27];"),
-    ("Guo source prefactor sign", "(1.0 - 0.5 / tau) * guo_term(vs, i, u, p.force)",
-     "(1.0 + 0.5 / tau) * guo_term(vs, i, u, p.force)"),
+    ("Guo source prefactor sign", "                (1.0 - 0.5 / tau) * guo_term(vs, i, u, p.force)",
+     "                (1.0 + 0.5 / tau) * guo_term(vs, i, u, p.force)"),
     ("equilibrium second-order coefficient", "4.5 * cv * cv", "3.0 * cv * cv"),
     ("Smagorinsky coefficient", "18.0 * std::sqrt(2.0)", "9.0 * std::sqrt(2.0)"),
     ("stress tensor index", "double(vs.c[i][a] * vs.c[i][b]) * fneq", "double(vs.c[i][a] * vs.c[i][a]) * fneq"),
@@ -34,6 +35,14 @@ MUTATIONS = [
     ("fringe ramp", "s * s * (3.0 - 2.0 * s)", "s * (3.0 - 2.0 * s)"),
     ("D3Q27 corner weight", "1.0 / 216.0", "1.0 / 108.0"),
     ("wall normal velocity kept", "uw[a] = wutan[k] * t[a] + un * n[a];", "uw[a] = wutan[k] * t[a];"),
+    ("D3Q19 third-order pair sign", "add({X, X, Y}, {Y, Z, Z}, -1.0);", "add({X, X, Y}, {Y, Z, Z}, 1.0);"),
+    ("continuous instead of lattice norm", "B.norm[k] += vs.w[i] * v * v;", "B.norm[k] += vs.w[i] * v * v * 1.5;"),
+    ("recursion not symmetrised",
+     "A[a][b][g] = u[a] * Pi[b][g] + u[b] * Pi[a][g] + u[g] * Pi[a][b];", "A[a][b][g] = 3.0 * u[a] * Pi[b][g];"),
+    ("regularization skipped", "fo[i] = feqh[i] + (1.0 - 1.0 / tau) * f1 +",
+     "fo[i] = feqh[i] + (1.0 - 1.0 / tau) * (fi[i] - feq[i]) +"),
+    ("third-order equilibrium term dropped", "for (int i = 0; i < vs.q; ++i) feq[i] += t[i];",
+     "for (int i = 0; i < vs.q; ++i) feq[i] += 0.0 * t[i];"),
 ]
 
 PIN_TESTS = [
@@ -50,6 +59,9 @@ PIN_TESTS = [
     (pins.test_wall_reconstruction_stress, [()]),
     (pins.test_wall_model_channel_records, [(27,)]),
     (pins.test_fringe_and_lid, [()]),
+    (pins_rr.test_equilibrium3_moments, [(19,), (27,)]),
+    (pins_rr.test_rr_keeps_bgk_low_moments_and_sets_third, [(19,), (27,)]),
+    (pins_rr.test_rr_removes_ghost_modes, [(19,)]),
 ]
 
 
