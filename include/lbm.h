@@ -52,6 +52,15 @@ enum {
 
 enum { LBM_D3Q19 = 19, LBM_D3Q27 = 27 };
 enum { LBM_F64 = 0, LBM_F32DEV = 1, LBM_F16DEV = 2 };
+/* Collision model of the bulk (sigma = 1) update, Sec. 2.2:
+ *  LBM_BGK: second-order equilibrium, all of f - f^eq relaxed (Eq. (6));
+ *  LBM_RR3: recursive regularized, third order: third-order equilibrium
+ *    (Eq. (11)) and f^(1) rebuilt from its Hermite coefficients of order 1
+ *    to 3 (Eqs. (8), (9)), the third by the recursion u_a Pi_bc + u_b Pi_ac
+ *    + u_c Pi_ab; third-order terms projected on the Hermite components the
+ *    lattice carries.  Wall cells and the initial state then use the
+ *    third-order equilibrium as well.  The adjoint supports LBM_BGK only. */
+enum { LBM_BGK = 0, LBM_RR3 = 1 };
 
 typedef struct {
   int lattice;        /* LBM_D3Q19 or LBM_D3Q27 */
@@ -66,6 +75,7 @@ typedef struct {
   int fringe_len;     /* urban open boundary: fringe over the last planes in x (0 = off) */
   double u_ref, z0;   /* log-law inflow u_ref ln(1 + z_c/z0)/ln(1 + z_top/z0) */
   int lid;            /* 1: the top plane z = nz-1 holds the inflow equilibrium */
+  int collision;      /* LBM_BGK or LBM_RR3 */
   void *stream;       /* hipStream_t for all device work (NULL = null stream) */
 } lbm_params;
 

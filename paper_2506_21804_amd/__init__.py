@@ -30,6 +30,8 @@ OK, EINVAL, EHIP, ENONFINITE, ENEWTON, ESIZE = 0, -1, -2, -3, -4, -5
 D3Q19, D3Q27 = 19, 27
 F64, F32DEV, F16DEV = 0, 1, 2
 STORAGE_NAMES = {"f64": F64, "f32": F32DEV, "f16": F16DEV}
+BGK, RR3 = 0, 1
+COLLISION_NAMES = {"bgk": BGK, "rr3": RR3}
 
 
 class Params(C.Structure):
@@ -45,6 +47,7 @@ class Params(C.Structure):
         ("fringe_len", C.c_int),
         ("u_ref", C.c_double), ("z0", C.c_double),
         ("lid", C.c_int),
+        ("collision", C.c_int),
         ("stream", C.c_void_p),
     ]
 
@@ -159,7 +162,8 @@ def _check(ctx, rc):
 
 
 def make_params(q, shape, periodic=(1, 1, 1), storage=F64, tau0=0.6, cs_smag=0.0, force=(0.0, 0.0, 0.0),
-                wall_model=0, kappa=0.41, E=9.0, fringe_len=0, u_ref=0.0, z0=1.0, lid=0, stream=None) -> Params:
+                wall_model=0, kappa=0.41, E=9.0, fringe_len=0, u_ref=0.0, z0=1.0, lid=0, collision=0,
+                stream=None) -> Params:
     p = Params()
     p.lattice = q
     p.nx, p.ny, p.nz = shape
@@ -169,6 +173,7 @@ def make_params(q, shape, periodic=(1, 1, 1), storage=F64, tau0=0.6, cs_smag=0.0
     p.force = (C.c_double * 3)(*force)
     p.wall_model, p.kappa, p.E = wall_model, kappa, E
     p.fringe_len, p.u_ref, p.z0, p.lid = fringe_len, u_ref, z0, lid
+    p.collision = COLLISION_NAMES.get(collision, collision) if isinstance(collision, str) else collision
     p.stream = stream
     return p
 
@@ -366,7 +371,7 @@ class Lattice:
         self.p = make_params(case.q, case.shape, periodic=case.periodic, storage=self.storage, tau0=case.tau0,
                              cs_smag=case.cs_smag, force=case.force, wall_model=case.wall_model, kappa=case.kappa,
                              E=case.E, fringe_len=case.fringe_len, u_ref=case.u_ref, z0=case.z0, lid=case.lid,
-                             stream=stream.cuda_stream)
+                             collision=getattr(case, "collision", 0), stream=stream.cuda_stream)
         porous = case.porosity is not None
         nbytes = lbm_workspace_bytes(self.p, case.mask, porous)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")

@@ -85,6 +85,10 @@ bool params_ok(const lbm_params *p, std::string &msg) {
     msg = "fringe / lid need z0 > 0 and a finite u_ref";
     return false;
   }
+  if (p->collision != LBM_BGK && p->collision != LBM_RR3) {
+    msg = "collision must be LBM_BGK or LBM_RR3";
+    return false;
+  }
   return true;
 }
 
@@ -271,6 +275,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   k.E = p->E;
   k.fringe_start = p->fringe_len > 0 ? p->nx - p->fringe_len : p->nx;
   k.u_lid = p->u_ref;  // ln(1 + z_top/z0) / ln(1 + z_top/z0) = 1 at the lid plane
+  k.rr = p->collision == LBM_RR3 ? 1 : 0;
   // inflow profile u_in(z) and fringe weights lambda(x)
   std::vector<double> tab((size_t)p->nz + p->nx, 0.0);
   if (p->fringe_len > 0 || p->lid) {
@@ -468,6 +473,7 @@ int lbm_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lambda) {
 int lbm_adjoint_step(lbm_ctx *ctx, void *lambda, void *grad_phi) {
   if (!ctx || !lambda || !grad_phi) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
   if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
+  if (ctx->ka.rr) return set_err(ctx, LBM_EINVAL, "the adjoint differentiates the BGK collision only");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   return dev_adjoint_step(ctx, lambda, grad_phi);
@@ -493,6 +499,7 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
   if (T < 1 || nsnap < 1 || !snapshots || !lambda || !grad_phi || !planes)
     return set_err(ctx, LBM_EINVAL, "gradient needs T >= 1, nsnap >= 1 and non-null buffers");
   if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
+  if (ctx->ka.rr) return set_err(ctx, LBM_EINVAL, "the adjoint differentiates the BGK collision only");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   const size_t sb = lbm_state_bytes(ctx);

@@ -46,6 +46,7 @@ struct KArgs {
   double kappa, E;
   int fringe_start;  // first fringe plane in x (nx when there is no fringe)
   double u_lid;      // lid velocity (x component)
+  int rr;            // 1: recursive regularized collision (third order), 0: BGK
   const void *uin;   // [nz] fringe inflow profile, compute type
   const void *lam;   // [nx] fringe blend weight, compute type (0 before the fringe)
 };

@@ -104,6 +104,43 @@ __device__ __forceinline__ void lid_equilibrium(R g[Q], const KArgs &k) {
   }
 }
 
+// Third-order Hermite coefficients K_k = <A, P_k> / |P_k|^2 of a tensor given
+// by its components A[0..6] (xxy, xxz, xyy, yyz, xzz, yzz, xyz).
+template <int Q, typename R>
+__device__ __forceinline__ void third_coefs(const R A[7], R K[7]) {
+  constexpr H3Norms<Q> nrm = h3_norms<Q>();
+#pragma unroll
+  for (int k = 0; k < H3Basis<Q>::n; ++k) {
+    R m = A[H3Basis<Q>::c0(k)];
+    if (H3Basis<Q>::sgn(k) > 0.0) m += A[H3Basis<Q>::c1(k)];
+    if (H3Basis<Q>::sgn(k) < 0.0) m -= A[H3Basis<Q>::c1(k)];
+    K[k] = m * R(1.0 / nrm.v[k]);
+  }
+}
+// sum_k P_k(c_i) K_k (the caller multiplies by w_i).
+template <int Q, typename R>
+__device__ __forceinline__ R third_term(int i, const R K[7]) {
+  R v = R(0);
+#pragma unroll
+  for (int k = 0; k < H3Basis<Q>::n; ++k) {
+    const double p = H3Basis<Q>::P(k, i);
+    if (p != 0.0) v += R(p) * K[k];
+  }
+  return v;
+}
+// Components of rho v v v.
+template <typename R>
+__device__ __forceinline__ void cube_tensor(R rho, R vx, R vy, R vz, R A[7]) {
+  const R rx = rho * vx, ry = rho * vy;
+  A[0] = rx * vx * vy;
+  A[1] = rx * vx * vz;
+  A[2] = rx * vy * vy;
+  A[3] = ry * vy * vz;
+  A[4] = rx * vz * vz;
+  A[5] = ry * vz * vz;
+  A[6] = rx * vy * vz;
+}
+
 // Bulk collision on deviations g (sigma = 1): BGK with tau_eff from the
 // non-equilibrium stress, homogenized velocity u_hat = phi u, Guo forcing.
 // Opposite directions i and i+H share everything but a sign: with
@@ -111,7 +148,14 @@ __device__ __forceinline__ void lid_equilibrium(R g[Q], const KArgs &k) {
 //   Guo_i = C + D,        Guo_ibar = C - D,
 // the outputs are g*_i = c1 g_i + P + Qo and g*_ibar = c1 g_ibar + P - Qo.
 // Returns false for a non-finite or non-positive density.
-template <int Q, typename R, bool POROUS>
+//
+// RR = true: the recursive regularized collision (Sec. 2.2, Eqs. (6), (8),
+// (9), (11), sigma = 1).  The equilibrium is third order and f - f^eq is
+// replaced by f^(1) rebuilt from its Hermite coefficients: order 1,
+// sum c (f - f^eq) = j - rho u = -F/2 (Guo velocity); order 2, Pi^neq; order 3,
+// the recursion u_a Pi_bc + u_b Pi_ac + u_c Pi_ab.  The third-order terms are
+// odd in c and join Qo; the outputs no longer carry c1 g_i.
+template <int Q, typename R, bool POROUS, bool RR>
 __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
   constexpr int H = Lat<Q>::H;
   // moments from pair sums s = g_i + g_ibar (even moments) and differences d = g_i - g_ibar (odd)
@@ -154,6 +198,49 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
   const R vx = POROUS ? phi * ux : ux, vy = POROUS ? phi * uy : uy, vz = POROUS ? phi * uz : uz;
   const R vv = vx * vx + vy * vy + vz * vz;
   const R uF = ux * Fx + uy * Fy + uz * Fz;
+  if constexpr (RR) {
+    // third-order coefficients of f^eq(rho, v) + c1 f^(1): A = rho v v v + c1 A1
+    R A[7], A1[7], K[7];
+    cube_tensor(rho, vx, vy, vz, A);
+    A1[0] = R(2) * ux * pxy + uy * pxx;
+    A1[1] = R(2) * ux * pxz + uz * pxx;
+    A1[2] = R(2) * uy * pxy + ux * pyy;
+    A1[3] = R(2) * uy * pyz + uz * pyy;
+    A1[4] = R(2) * uz * pxz + ux * pzz;
+    A1[5] = R(2) * uz * pyz + uy * pzz;
+    A1[6] = ux * pyz + uy * pxz + uz * pxy;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) A[m] += c1 * A1[m];
+    third_coefs<Q, R>(A, K);
+    const R tr3 = (pxx + pyy + pzz) * cs2;
+    // rest: f^eq - w = w0 (drho - 3/2 rho v.v); f^(1)_0 = -9/2 w0 c_s^2 tr Pi; Guo -3 w0 u.F
+    {
+      const R w = R(Lat<Q>::w(0));
+      g[0] = w * (drho - R(1.5) * rho * vv) - c1 * R(4.5) * w * tr3 + c2 * (R(-3) * w * uF);
+    }
+#pragma unroll
+    for (int i = 1; i <= H; ++i) {
+      const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+      const R w = R(Lat<Q>::w(i));
+      const R cu = dot3(cx, cy, cz, ux, uy, uz);
+      const R cv = POROUS ? dot3(cx, cy, cz, vx, vy, vz) : cu;
+      const R cF = dot3(cx, cy, cz, Fx, Fy, Fz);
+      R cPc = R(0);  // c . Pi . c
+      acc(cPc, cx * cx, pxx);
+      acc(cPc, cy * cy, pyy);
+      acc(cPc, cz * cz, pzz);
+      acc(cPc, cx * cy, R(2) * pxy);
+      acc(cPc, cx * cz, R(2) * pxz);
+      acc(cPc, cy * cz, R(2) * pyz);
+      const R P = w * (drho + rho * (R(4.5) * cv * cv - R(1.5) * vv) + c1 * R(4.5) * (cPc - tr3) +
+                       c2 * (R(9) * cu * cF - R(3) * uF));
+      // odd part: 3 w rho c.v + w sum_k P_k K_k + c1 (3 w c.a1, a1 = -F/2) + c2 3 w c.F
+      const R Qo = w * (R(3) * rho * cv + third_term<Q, R>(i, K) + (R(3) * c2 - R(1.5) * c1) * cF);
+      g[i] = P + Qo;
+      g[i + H] = P - Qo;
+    }
+    return ok;
+  }
   // rest population: A = w0 (drho - 3/2 rho v.v), B = C - (-3 w0 u.F) = D = 0
   {
     const R w = R(Lat<Q>::w(0));
@@ -192,7 +279,7 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
 // Gather, collide, scatter of one cell.  With LINKS = false the cell has no
 // solid link and every slot is the plain AA one (32-bit offsets from a
 // per-direction base); with LINKS = true slots follow the bounce-back map.
-template <int Q, typename S, bool ODD, bool POROUS, bool LINKS>
+template <int Q, typename S, bool ODD, bool POROUS, bool LINKS, bool RR>
 __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename Store<S>::R *__restrict__ phi,
                                           const KArgs &k, const Nb &n, unsigned sm, uint8_t fl, int x, int z,
                                           int *__restrict__ errflag) {
@@ -213,7 +300,7 @@ __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename St
       }
     }
     const R ph = POROUS ? phi[n.cell] : R(1);
-    if (!collide_bulk<Q, R, POROUS>(g, ph, k)) atomicOr(errflag, 1);
+    if (!collide_bulk<Q, R, POROUS, RR>(g, ph, k)) atomicOr(errflag, 1);
   }
   fringe_blend<Q, R>(g, x, z, k);
 #pragma unroll
@@ -228,7 +315,7 @@ __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename St
   }
 }
 
-template <int Q, typename S, bool ODD, bool POROUS, bool SOLID>
+template <int Q, typename S, bool ODD, bool POROUS, bool SOLID, bool RR>
 __global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                 const typename Store<S>::R *__restrict__ phi, KArgs k,
                                                 Tiles t, int *__restrict__ errflag) {
@@ -240,8 +327,8 @@ __global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8
   unsigned sm = 0;
   if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
   // cells without solid links (all but a thin layer) take the plain-address path
-  if (SOLID && ODD && sm != 0u) bulk_cell<Q, S, ODD, POROUS, true>(pop, phi, k, n, sm, fl, x, z, errflag);
-  else bulk_cell<Q, S, ODD, POROUS, false>(pop, phi, k, n, sm, fl, x, z, errflag);
+  if (SOLID && ODD && sm != 0u) bulk_cell<Q, S, ODD, POROUS, true, RR>(pop, phi, k, n, sm, fl, x, z, errflag);
+  else bulk_cell<Q, S, ODD, POROUS, false, RR>(pop, phi, k, n, sm, fl, x, z, errflag);
 }
 
 // ---------------------------------------------------------------------------
@@ -452,6 +539,13 @@ __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t
   const R om = R(1) / tau;
   const R c1 = R(1) - om, c2 = R(1) - R(0.5) * om;
   const R fd = R(-3) * rho * tau * G;  // f^(1,FD)_i = fd * w_i (c.t)(c.n)
+  // recursive regularized model: third-order equilibrium at the modeled velocity
+  R K[7] = {};
+  if (k.rr) {
+    R A[7];
+    cube_tensor(rho, vx, vy, vz, A);
+    third_coefs<Q, R>(A, K);
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
@@ -464,6 +558,7 @@ __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t
     const R ffd = fd * w * ct * cn;
     const R guo = w * (R(3) * (cF - vF) + R(9) * cv * cF);
     g[i] = ge + c1 * ffd + c2 * guo;
+    if (k.rr) g[i] += w * third_term<Q, R>(i, K);
   }
   fringe_blend<Q, R>(g, x, z, k);
 #pragma unroll
@@ -490,10 +585,18 @@ __global__ __launch_bounds__(BLOCK) void k_init_eq(S *__restrict__ pop, const ui
   const double drho = rho0 ? rho0[c] - 1.0 : 0.0;
   const double ux = u0 ? u0[c] : 0.0, uy = u0 ? u0[N + c] : 0.0, uz = u0 ? u0[2 * N + c] : 0.0;
   const double uu = ux * ux + uy * uy + uz * uz;
+  double K[7] = {};
+  if (k.rr) {  // third-order equilibrium
+    double A[7];
+    cube_tensor(rho, ux, uy, uz, A);
+    third_coefs<Q, double>(A, K);
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double cu = dot3(Lat<Q>::c(i, 0), Lat<Q>::c(i, 1), Lat<Q>::c(i, 2), ux, uy, uz);
-    Store<S>::st(pop + (size_t)i * N + c, (typename Store<S>::R)geq_dev(Lat<Q>::w(i), drho, rho, cu, uu));
+    double gi = geq_dev(Lat<Q>::w(i), drho, rho, cu, uu);
+    if (k.rr) gi += Lat<Q>::w(i) * third_term<Q, double>(i, K);
+    Store<S>::st(pop + (size_t)i * N + c, (typename Store<S>::R)gi);
   }
 }
 
@@ -739,12 +842,16 @@ static void launch_bulk(lbm_ctx *ctx, Tiles t) {
   auto go = [&](auto kern) {
     kern<<<t.nblocks, BLOCK, lds_cap, ctx->stream>>>(pop, ctx->flags, phi, ctx->ka, t, ctx->errflag);
   };
+  auto by_model = [&]<bool POROUS, bool SOLID>() {
+    if (ctx->ka.rr) go(k_bulk<Q, S, ODD, POROUS, SOLID, true>);
+    else go(k_bulk<Q, S, ODD, POROUS, SOLID, false>);
+  };
   if (ctx->porous) {
-    if (ctx->has_solid) go(k_bulk<Q, S, ODD, true, true>);
-    else go(k_bulk<Q, S, ODD, true, false>);
+    if (ctx->has_solid) by_model.template operator()<true, true>();
+    else by_model.template operator()<true, false>();
   } else {
-    if (ctx->has_solid) go(k_bulk<Q, S, ODD, false, true>);
-    else go(k_bulk<Q, S, ODD, false, false>);
+    if (ctx->has_solid) by_model.template operator()<false, true>();
+    else by_model.template operator()<false, false>();
   }
 }
 

@@ -36,6 +36,69 @@ struct Lat {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Third-order Hermite terms of the recursive regularized collision (Sec. 2.2,
+// Eqs. (8), (9), (11)).  H3_abc(c_i) = c_a c_b c_c - c_s^2 (c_a d_bc + c_b d_ac
+// + c_c d_ab).  A symmetric third-order tensor is held by its seven
+// components that can matter on these lattices, in the order
+//   0 xxy, 1 xxz, 2 xyy, 3 yyz, 4 xzz, 5 yzz, 6 xyz
+// (xxx-type components vanish: c^3 = c).  The basis polynomials a lattice
+// carries, orthogonal in the weighted lattice sum sum_i w_i P_k P_l:
+//   D3Q27: the seven components themselves;
+//   D3Q19: xyz vanishes and the pairs (xxy, yzz), (xzz, xyy), (yyz, xxz)
+//          alias, so their sums and differences.
+// A tensor A enters the populations as w_i sum_k P_k(c_i) <A, P_k> / |P_k|^2
+// with the lattice norms |P_k|^2 = sum_i w_i P_k(c_i)^2.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int t3_axis(int comp, int r) {
+  constexpr int T[7][3] = {{0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {1, 1, 2}, {0, 2, 2}, {1, 2, 2}, {0, 1, 2}};
+  return T[comp][r];
+}
+template <int Q>
+__host__ __device__ constexpr double h3(int i, int comp) {
+  const int a = t3_axis(comp, 0), b = t3_axis(comp, 1), c = t3_axis(comp, 2);
+  const double ca = Lat<Q>::c(i, a), cb = Lat<Q>::c(i, b), cc = Lat<Q>::c(i, c);
+  return ca * cb * cc - (ca * (b == c) + cb * (a == c) + cc * (a == b)) / 3.0;
+}
+template <int Q>
+struct H3Basis {
+  static constexpr int n = Q == 27 ? 7 : 6;
+  // first and second component of basis polynomial k, and the sign of the
+  // second (0: a single component)
+  __host__ __device__ static constexpr int c0(int k) {
+    constexpr int A[6] = {0, 0, 4, 4, 3, 3};
+    return Q == 27 ? k : A[k];
+  }
+  __host__ __device__ static constexpr int c1(int k) {
+    constexpr int B[6] = {5, 5, 2, 2, 1, 1};
+    return Q == 27 ? 0 : B[k];
+  }
+  __host__ __device__ static constexpr double sgn(int k) { return Q == 27 ? 0.0 : (k % 2 == 0 ? 1.0 : -1.0); }
+  __host__ __device__ static constexpr double P(int k, int i) {
+    return h3<Q>(i, c0(k)) + (sgn(k) != 0.0 ? sgn(k) * h3<Q>(i, c1(k)) : 0.0);
+  }
+};
+template <int Q>
+struct H3Norms {
+  double v[7];
+};
+template <int Q>
+__host__ __device__ constexpr H3Norms<Q> h3_norms() {
+  H3Norms<Q> r{};
+  for (int k = 0; k < H3Basis<Q>::n; ++k) {
+    double s = 0.0;
+    for (int i = 0; i < Q; ++i) s += Lat<Q>::w(i) * H3Basis<Q>::P(k, i) * H3Basis<Q>::P(k, i);
+    r.v[k] = s;
+  }
+  return r;
+}
+__host__ __device__ constexpr bool near_eq(double a, double b) { return a - b < 1e-15 && b - a < 1e-15; }
+// D3Q27: 2 c_s^6 for the xxy type, c_s^6 for xyz; D3Q19: 2 c_s^6 for the sums,
+// 6 c_s^6 for the differences (the continuous norm of each sum and difference
+// would be 4 c_s^6).
+static_assert(near_eq(h3_norms<27>().v[0], 2.0 / 27.0) && near_eq(h3_norms<27>().v[6], 1.0 / 27.0), "D3Q27 norms");
+static_assert(near_eq(h3_norms<19>().v[0], 2.0 / 27.0) && near_eq(h3_norms<19>().v[1], 6.0 / 27.0), "D3Q19 norms");
+
 // s += c * v for a lattice component c in {-1, 0, 1} known at compile time
 // after unrolling (no multiplication, no 0*v).
 template <typename R>

@@ -45,6 +45,7 @@ class Case:
     u_ref: float = 0.0
     z0: float = 1.0
     lid: int = 0
+    collision: int = 0  # 0 BGK, 1 recursive regularized (third order)
     mask: np.ndarray | None = None
     wall_dist: np.ndarray | None = None
     porosity: np.ndarray | None = None

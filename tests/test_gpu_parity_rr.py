@@ -1,0 +1,129 @@
+"""Parity of the recursive regularized collision (LBM_RR3) of the HIP path
+with the FP64 oracle's, through the C ABI.  Same bars as the BGK parity
+tests: FP64 storage within 1e-12 of the oracle (density and velocity
+relative to the oracle field's max-norm, rho - 1 within 1e-10 of its own);
+FP32 within 1e-5 after 100 steps; FP16 reported with a loose bound.  The
+cases cover every place the model enters: the bulk kernel with and without
+porosity and forcing, the wall-model reconstruction, the initial state, the
+fringe and the lid."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2506_21804_amd import inputs as I
+from gpu_helpers import announce, moment_errors, oracle_for, rel_maxnorm
+
+pytestmark = pytest.mark.gpu
+
+
+def rr(case):
+    return dataclasses.replace(case, collision=1)
+
+
+def _run_both(lbm, case, steps, storage, wall_dist="case"):
+    announce(f"RR {case.name} q={case.q} storage={storage} steps={steps}")
+    lat = lbm.Lattice(case, storage=storage, wall_dist=wall_dist)
+    lat.step(steps)
+    rho, u = lat.moments()
+    orc = oracle_for(case, steps)
+    orho, ou = orc.moments()
+    return lat, orc, rho.cpu().numpy().astype(np.float64), u.cpu().numpy().astype(np.float64), orho, ou
+
+
+def _check(msg, errs, tol):
+    e_rho, e_u, e_drho = errs
+    announce(f"{msg}: rho {e_rho:.3e} u {e_u:.3e} drho {e_drho:.3e}")
+    assert e_rho <= tol and e_u <= tol, msg
+    if tol <= 1e-12:
+        assert e_drho <= 1e-10, msg
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_rr_tgv_fp64(gpu, q):
+    case = rr(I.taylor_green(32, u0=0.05, q=q, tau0=0.6, cs_smag=0.1))
+    lat, orc, rho, u, orho, ou = _run_both(gpu, case, 100, "f64")
+    _check(f"rr tgv q={q} f64", moment_errors(rho, u, orho, ou), 1e-12)
+    e_f = rel_maxnorm(lat.populations().cpu().numpy(), orc.populations())
+    assert e_f <= 1e-13, e_f
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_rr_tgv_fp32_fp16(gpu, q):
+    case = rr(I.taylor_green(32, u0=0.05, q=q, tau0=0.6, cs_smag=0.1))
+    _, _, rho, u, orho, ou = _run_both(gpu, case, 100, "f32")
+    e_rho, e_u = rel_maxnorm(rho, orho), rel_maxnorm(u, ou)
+    announce(f"rr tgv q={q} f32: rho {e_rho:.3e} u {e_u:.3e}")
+    assert e_rho <= 1e-5 and e_u <= 1e-5
+    _, _, rho, u, _, _ = _run_both(gpu, case, 100, "f16")
+    e_rho, e_u = rel_maxnorm(rho, orho), rel_maxnorm(u, ou)
+    announce(f"rr tgv q={q} f16: rho {e_rho:.3e} u {e_u:.3e}")
+    assert e_rho <= 1e-3 and e_u <= 5e-2
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_rr_ragged_forced_random_state(gpu, storage, tol):
+    """A generic non-equilibrium state with a body force on a 263x7x9 periodic
+    box (two 128-wide tiles plus a tail), population by population after odd
+    and even step counts: the force enters through the first-order Hermite
+    coefficient -F/2 as well as the Guo source."""
+    q = 27
+    shape = (263, 7, 9)
+    N = int(np.prod(shape))
+    c, w, _ = O.velocity_set(q)
+    f0 = I.random_state(w, N, seed_offset=12, amp=0.05)
+    force = (2e-5, -1e-5, 5e-6)
+    case = I.Case(name="ragged", q=q, shape=shape, periodic=(1, 1, 1), tau0=0.58, cs_smag=0.12, force=force,
+                  collision=1)
+    lat = gpu.Lattice(case, storage=storage)
+    lat.set_populations(torch.as_tensor(f0))
+    orc = O.Oracle(O.make_params(q, shape, tau0=0.58, cs_smag=0.12, force=force, collision=1))
+    orc.set_populations(f0)
+    for n in (1, 4):
+        lat.step(n)
+        orc.step(n)
+        f = lat.populations().cpu().numpy().astype(np.float64)
+        err = rel_maxnorm(f - w[:, None], orc.populations() - w[:, None])
+        announce(f"rr ragged {storage} after {lat.steps}: {err:.3e}")
+        assert err <= (1e-12 if storage == "f64" else 1e-5), (storage, lat.steps, err)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_rr_channel_wall_model_fp64(gpu, q):
+    case = rr(I.channel(70, 10, 9, q=q, utau=0.01, nu=1e-3, tau0=0.503, cs_smag=0.1, amp=0.01, wall_model=1))
+    lat, orc, rho, u, orho, ou = _run_both(gpu, case, 51, "f64")
+    _check(f"rr channel q={q} f64", moment_errors(rho, u, orho, ou), 1e-12)
+    g, o = lat.wall_records(), orc.wall_info()
+    np.testing.assert_allclose(g["utau"], o["utau"], rtol=1e-11)
+
+
+@pytest.mark.parametrize("storage,tol,steps", [("f64", 1e-12, 41), ("f32", 1e-5, 100)])
+def test_rr_urban_crop(gpu, storage, tol, steps):
+    case = rr(I.urban(nx=160, ny=72, nz=48, q=27, tau0=0.5003, fringe_len=24, x_lo=16, x_hi=110,
+                      h_mean=14.0, h_max=36, fp_lo=6, fp_hi=16))
+    _, _, rho, u, orho, ou = _run_both(gpu, case, steps, storage)
+    _check(f"rr urban {storage}", moment_errors(rho, u, orho, ou), tol)
+
+
+def test_rr_porosity_fp64(gpu):
+    case = rr(I.porous_channel(shape=(40, 24, 12)))
+    _, _, rho, u, orho, ou = _run_both(gpu, case, 30, "f64")
+    _check("rr porous f64", moment_errors(rho, u, orho, ou), 1e-12)
+
+
+def test_rr_cavity_fp64(gpu):
+    case = rr(I.cavity((140, 20, 18), q=19))
+    _, _, rho, u, orho, ou = _run_both(gpu, case, 80, "f64")
+    _check("rr cavity f64", moment_errors(rho, u, orho, ou), 1e-12)
+
+
+def test_rr_adjoint_refused(gpu):
+    case = rr(I.porous_channel(shape=(16, 12, 8)))
+    lat = gpu.Lattice(case, storage="f64")
+    lam, grad = lat.new_adjoint(), lat.new_gradient()
+    gpu.lbm_adjoint_seed(lat.ctx, case.extra["planes"], lam)
+    with pytest.raises(gpu.LbmError) as e:
+        gpu.lbm_adjoint_step(lat.ctx, lam, grad)
+    assert e.value.code == gpu.EINVAL and "BGK" in str(e.value)
