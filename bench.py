@@ -267,8 +267,15 @@ def bench_precision(args, torch, lbm):
         cnt = mask3.sum(dim=(1, 2)).clamp(min=1)
         return (ux * mask3).sum(dim=(1, 2)) / cnt
 
+    def urban_rr():
+        # the urban canopy is not stable with BGK over 2000 steps; the
+        # recursive regularized collision is
+        c = I.urban(768, 768, 256, q=27, with_wall_dist=False)
+        c.collision = 1
+        return c
+
     for wname, make in (("channel384x192x192", lambda: I.channel(384, 192, 192, q=27)),
-                        ("urban768x768x256", lambda: I.urban(768, 768, 256, q=27, with_wall_dist=False))):
+                        ("urban768x768x256_rr3", urban_rr)):
         case = make()
         nx, ny, nz = case.shape
         mask3 = (torch.ones((nz, ny, nx), dtype=torch.float64, device="cuda") if case.mask is None else
@@ -308,7 +315,8 @@ def bench_precision(args, torch, lbm):
            "value": ch.get("u"), "unit": "max-norm relative error of u (FP16, channel, 100 steps)",
            "n_gpus": 1, "steps": horizons[-1], "warmup": 0, "ms_per_step": None, "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32 compute", "data": "synthetic",
-           "config": {"workload": "channel384x192x192 and urban768x768x256, D3Q27"}, "errors": rows}
+           "config": {"workload": "channel384x192x192 (BGK) and urban768x768x256 (recursive regularized), D3Q27"},
+           "errors": rows}
     print(json.dumps(out), flush=True)
 
 
