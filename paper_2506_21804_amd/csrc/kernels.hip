@@ -29,24 +29,30 @@
 
 namespace lbmk {
 
-// Tile of one block: two rows of 128 cells, each row two wavefronts wide.
-// On odd steps the x-shifted accesses of a wavefront straddle cache lines;
-// with the neighbouring wavefront of the same row in the same block, the
-// partial lines are completed while still in L2 (measured: 1-2 % faster K2
-// than 64 x 4 tiles on the channel and the urban canopy; 256 x 1 loses on
-// widths that are not multiples of 256).
-constexpr int TX = 128;  // tile width in x (power of two)
-constexpr int TY = 2;    // tile height in y
-constexpr int BLOCK = TX * TY;
+// Tile of one block (256 threads): rows of 128 cells, two wavefronts wide,
+// two rows per block; or rows of 64 cells, four rows per block, when that
+// leaves fewer lanes outside the domain (0 < nx mod 128 <= 64).  On odd steps
+// the x-shifted accesses of a wavefront straddle cache lines; with the
+// neighbouring wavefront of the same row in the same block, the partial lines
+// are completed while still in L2.  Measured on K2: 128-wide tiles 1-2 %
+// faster than 64-wide on the channel (nx 384) and the urban canopy (768);
+// 64-wide 2 % faster on the 575^3 cavity, where 128-wide tiles leave 65 of
+// 640 lanes per row idle; 256 x 1 loses on widths that are not multiples of
+// 256.
+constexpr int BLOCK = 256;
 
 struct Tiles {
   unsigned nblocks;
   int gx, gy;
+  int lx;  // log2 of the tile width (6 or 7)
 };
 static Tiles tiles_of(const KArgs &k) {
   Tiles t;
-  t.gx = (k.nx + TX - 1) / TX;
-  t.gy = (k.ny + TY - 1) / TY;
+  const int r = k.nx % 128;
+  t.lx = (r > 0 && r <= 64) ? 6 : 7;
+  const int tw = 1 << t.lx, th = BLOCK >> t.lx;
+  t.gx = (k.nx + tw - 1) / tw;
+  t.gy = (k.ny + th - 1) / th;
   t.nblocks = (unsigned)t.gx * (unsigned)t.gy * (unsigned)k.nz;
   return t;
 }
@@ -58,8 +64,8 @@ __device__ __forceinline__ bool tile_xyz(const KArgs &k, Tiles t, unsigned block
   const unsigned r = L / (unsigned)t.gx;
   const int ty = (int)(r % (unsigned)t.gy);
   z = (int)(r / (unsigned)t.gy);
-  x = tx * TX + (int)(threadIdx.x & (TX - 1));
-  y = ty * TY + (int)(threadIdx.x / TX);
+  x = (tx << t.lx) + (int)(threadIdx.x & ((1u << t.lx) - 1u));
+  y = ty * (BLOCK >> t.lx) + (int)(threadIdx.x >> t.lx);
   return x < k.nx && y < k.ny;
 }
 

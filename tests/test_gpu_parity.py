@@ -7,7 +7,7 @@ sum of full populations); FP32
 deviation storage within 1e-5 (density relative to its max-norm, velocity
 relative to its max-norm) after 100 steps; FP16 deviation storage reported
 (bounded loosely, its error is a measured quantity, not a target).
-Sizes span several 128x2 tiles and ragged tails in x and y.
+Sizes span several tiles and ragged tails in x and y.
 """
 import numpy as np
 import pytest
@@ -61,9 +61,9 @@ def test_tgv_fp32_fp16(gpu, q):
 
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_ragged_random_state(gpu, storage, tol):
-    """A generic non-equilibrium state on a 263x7x9 periodic box (two full
-    128-wide tiles plus a tail of 7 in x, a half tile in y), odd and even step
-    counts, checked population by population."""
+    """A generic non-equilibrium state on a 263x7x9 periodic box (several
+    tiles plus a ragged tail in x and y), odd and even step counts, checked
+    population by population."""
     q = 27
     shape = (263, 7, 9)
     N = int(np.prod(shape))

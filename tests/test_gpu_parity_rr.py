@@ -66,7 +66,7 @@ def test_rr_tgv_fp32_fp16(gpu, q):
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_rr_ragged_forced_random_state(gpu, storage, tol):
     """A generic non-equilibrium state with a body force on a 263x7x9 periodic
-    box (two 128-wide tiles plus a tail), population by population after odd
+    box (several tiles plus a ragged tail), population by population after odd
     and even step counts: the force enters through the first-order Hermite
     coefficient -F/2 as well as the Guo source."""
     q = 27
