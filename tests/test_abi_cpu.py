@@ -38,7 +38,7 @@ def test_workspace_bytes_and_validation():
     p16 = lbm.make_params(27, (32, 32, 32), storage=lbm.F16DEV, tau0=0.6)
     assert lbm.lbm_workspace_bytes(p16) >= 27 * 32 ** 3 * 2
     for bad in (dict(tau0=0.5), dict(tau0=float("nan")), dict(cs_smag=-1.0), dict(storage=7),
-                dict(fringe_len=99)):
+                dict(fringe_len=99), dict(collision=2), dict(collision=-1)):
         kw = dict(tau0=0.6)
         kw.update(bad)
         with pytest.raises(lbm.LbmError):
@@ -47,6 +47,11 @@ def test_workspace_bytes_and_validation():
         lbm.lbm_workspace_bytes(lbm.make_params(23, (32, 32, 32), tau0=0.6))
     with pytest.raises(lbm.LbmError):
         lbm.lbm_workspace_bytes(lbm.make_params(19, (2048, 1024, 1024), tau0=0.6))
+    # one population array at most 4 GiB: 1024^3 FP32 fits exactly, FP64 does not
+    assert lbm.lbm_workspace_bytes(lbm.make_params(27, (1024, 1024, 1024), storage=lbm.F32DEV, tau0=0.6)) > 0
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_workspace_bytes(lbm.make_params(27, (1024, 1024, 1024), storage=lbm.F64, tau0=0.6))
+    assert lbm.lbm_workspace_bytes(lbm.make_params(19, (16, 16, 16), tau0=0.6, collision="rr3")) > 0
 
 
 def test_wall_cells_counted_in_workspace():
