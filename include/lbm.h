@@ -59,7 +59,7 @@ enum { LBM_F64 = 0, LBM_F32DEV = 1, LBM_F16DEV = 2 };
  *    to 3 (Eqs. (8), (9)), the third by the recursion u_a Pi_bc + u_b Pi_ac
  *    + u_c Pi_ab; third-order terms projected on the Hermite components the
  *    lattice carries.  Wall cells and the initial state then use the
- *    third-order equilibrium as well.  The adjoint supports LBM_BGK only. */
+ *    third-order equilibrium as well.  The adjoint supports both models. */
 enum { LBM_BGK = 0, LBM_RR3 = 1 };
 
 typedef struct {

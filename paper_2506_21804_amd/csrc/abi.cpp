@@ -473,7 +473,6 @@ int lbm_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lambda) {
 int lbm_adjoint_step(lbm_ctx *ctx, void *lambda, void *grad_phi) {
   if (!ctx || !lambda || !grad_phi) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
   if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
-  if (ctx->ka.rr) return set_err(ctx, LBM_EINVAL, "the adjoint differentiates the BGK collision only");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   return dev_adjoint_step(ctx, lambda, grad_phi);
@@ -499,7 +498,6 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
   if (T < 1 || nsnap < 1 || !snapshots || !lambda || !grad_phi || !planes)
     return set_err(ctx, LBM_EINVAL, "gradient needs T >= 1, nsnap >= 1 and non-null buffers");
   if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
-  if (ctx->ka.rr) return set_err(ctx, LBM_EINVAL, "the adjoint differentiates the BGK collision only");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   const size_t sb = lbm_state_bytes(ctx);

@@ -1,6 +1,7 @@
 // Discrete adjoint (reverse mode) of the forward step of kernels.hip, for
 // gradients of a terminal objective with respect to the per-cell porosity of
-// the homogenized velocity (Sec. 2.2, Eq. (12)).
+// the homogenized velocity (Sec. 2.2, Eq. (12)), for both bulk collision
+// models (BGK and the recursive regularized one).
 //
 // An adjoint field has the state's in-memory AA layout.  One reverse step
 // at parity n is the transpose of the forward step: for each cell, the
@@ -207,6 +208,228 @@ __device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi
   return phib;
 }
 
+// Vector-Jacobian product of the recursive regularized collision (the
+// RR = true branch of collide_bulk) in precision R.  Forward:
+//   out_i = w_i (drho + rho (3 c.v + 9/2 (c.v)^2 - 3/2 v.v)) + w_i T3(rho v v v)_i
+//         + c1 [ -3/2 w_i c.F + 9/2 w_i (c.Pi.c - c_s^2 tr Pi) + w_i T3(A1(u, Pi))_i ]
+//         + c2 w_i (3 (c.F - u.F) + 9 (c.u)(c.F)),
+// with u = (j + F/2)/rho, Pi = M2 - drho c_s^2 I - rho u u, v = phi u,
+// c1 = 1 - 1/tau, c2 = 1 - 1/(2 tau), tau from |Pi| and rho, and T3 the
+// projection on the lattice's third-order Hermite basis (linear in its
+// tensor argument: sum_i mu_i w_i T3(A)_i = sum_k <A, P_k> M_k / |P_k|^2 with
+// M_k = sum_i mu_i w_i P_k(c_i)).  The outputs depend on g only through its
+// moments.
+template <int Q, typename R, bool POROUS, typename OUT>
+__device__ __forceinline__ R collide_bulk_rr_vjp(const R g[Q], const R mu[Q], R phi, const KArgs &k, OUT out) {
+  // ---- forward recomputation
+  R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+  R mxx = R(0), myy = R(0), mzz = R(0), mxy = R(0), mxz = R(0), myz = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+    drho += g[i];
+    acc(jx, cx, g[i]);
+    acc(jy, cy, g[i]);
+    acc(jz, cz, g[i]);
+    acc(mxx, cx * cx, g[i]);
+    acc(myy, cy * cy, g[i]);
+    acc(mzz, cz * cz, g[i]);
+    acc(mxy, cx * cy, g[i]);
+    acc(mxz, cx * cz, g[i]);
+    acc(myz, cy * cz, g[i]);
+  }
+  const R rho = R(1) + drho;
+  const R ir = R(1) / rho;
+  const R Fx = R(k.F[0]), Fy = R(k.F[1]), Fz = R(k.F[2]);
+  const R mx = jx + R(0.5) * Fx, my = jy + R(0.5) * Fy, mz = jz + R(0.5) * Fz;
+  const R ux = mx * ir, uy = my * ir, uz = mz * ir;
+  const R cs2 = R(1.0 / 3.0);
+  const R pxx = mxx - drho * cs2 - rho * ux * ux;
+  const R pyy = myy - drho * cs2 - rho * uy * uy;
+  const R pzz = mzz - drho * cs2 - rho * uz * uz;
+  const R pxy = mxy - rho * ux * uy;
+  const R pxz = mxz - rho * ux * uz;
+  const R pyz = myz - rho * uy * uz;
+  const R pn = sqrt(pxx * pxx + pyy * pyy + pzz * pzz + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz));
+  const R tau0 = R(k.tau0), smag = R(k.smag);
+  const R sA = sqrt(tau0 * tau0 + smag * pn * ir);
+  const R tau = R(0.5) * (tau0 + sA);
+  const R om = R(1) / tau;
+  const R c1 = R(1) - om, c2 = R(1) - R(0.5) * om;
+  const R vx = POROUS ? phi * ux : ux, vy = POROUS ? phi * uy : uy, vz = POROUS ? phi * uz : uz;
+  const R vv = vx * vx + vy * vy + vz * vz;
+  const R uF = ux * Fx + uy * Fy + uz * Fz;
+  const R tr3 = (pxx + pyy + pzz) * cs2;
+  R A0[7], A1[7], K0[7], K1[7];
+  cube_tensor(rho, vx, vy, vz, A0);
+  A1[0] = R(2) * ux * pxy + uy * pxx;
+  A1[1] = R(2) * ux * pxz + uz * pxx;
+  A1[2] = R(2) * uy * pxy + ux * pyy;
+  A1[3] = R(2) * uy * pyz + uz * pyy;
+  A1[4] = R(2) * uz * pxz + ux * pzz;
+  A1[5] = R(2) * uz * pyz + uy * pzz;
+  A1[6] = ux * pyz + uy * pxz + uz * pxy;
+  third_coefs<Q, R>(A1, K1);
+
+  // ---- reverse through the outputs
+  R c1b = R(0), c2b = R(0);
+  R s0 = R(0), s1 = R(0);                      // sum mu w, sum mu w (3cv + 9/2 cv^2 - 3/2 vv)
+  R evx = R(0), evy = R(0), evz = R(0);        // sum mu w (3 + 9 c.v) c
+  R gux = R(0), guy = R(0), guz = R(0);        // sum mu w (9 c.F) c   (Guo, times c2 later)
+  R gF = R(0);                                 // sum mu w
+  R pbxx = R(0), pbyy = R(0), pbzz = R(0), pbxy = R(0), pbxz = R(0), pbyz = R(0), pbtr = R(0);
+  R M[7];
+#pragma unroll
+  for (int m = 0; m < 7; ++m) M[m] = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+    const R w = R(Lat<Q>::w(i));
+    const R mw = mu[i] * w;
+    const R cu = dot3(cx, cy, cz, ux, uy, uz);
+    const R cv = dot3(cx, cy, cz, vx, vy, vz);
+    const R cF = dot3(cx, cy, cz, Fx, Fy, Fz);
+    R cPc = R(0);
+    acc(cPc, cx * cx, pxx);
+    acc(cPc, cy * cy, pyy);
+    acc(cPc, cz * cz, pzz);
+    acc(cPc, cx * cy, R(2) * pxy);
+    acc(cPc, cx * cz, R(2) * pxz);
+    acc(cPc, cy * cz, R(2) * pyz);
+    const R t1 = third_term<Q, R>(i, K1);
+    c1b += mw * (R(-1.5) * cF + R(4.5) * (cPc - tr3) + t1);
+    c2b += mw * (R(3) * (cF - uF) + R(9) * cu * cF);
+    s0 += mw;
+    s1 += mw * (R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv);
+    const R te = mw * (R(3) + R(9) * cv);
+    acc(evx, cx, te);
+    acc(evy, cy, te);
+    acc(evz, cz, te);
+    const R tg = mw * R(9) * cF;
+    acc(gux, cx, tg);
+    acc(guy, cy, tg);
+    acc(guz, cz, tg);
+    gF += mw;
+    // 9/2 w (c.Pi.c - c_s^2 tr Pi): d/dp_aa = 9/2 w c_a^2, d/dp_ab = 9 w c_a c_b, tr part separately
+    acc(pbxx, cx * cx, mw);
+    acc(pbyy, cy * cy, mw);
+    acc(pbzz, cz * cz, mw);
+    acc(pbxy, cx * cy, mw);
+    acc(pbxz, cx * cz, mw);
+    acc(pbyz, cy * cz, mw);
+    pbtr += mw;
+#pragma unroll
+    for (int kk = 0; kk < H3Basis<Q>::n; ++kk) {
+      const double pk = H3Basis<Q>::P(kk, i);
+      if (pk != 0.0) M[kk] += mw * R(pk);
+    }
+  }
+  // adjoints of the tensor components through the projection: Ab = sum_k M_k / |P_k|^2 d<A,P_k>/dA
+  R Ab[7];
+  {
+    constexpr H3Norms<Q> nrm = h3_norms<Q>();
+#pragma unroll
+    for (int m = 0; m < 7; ++m) Ab[m] = R(0);
+#pragma unroll
+    for (int kk = 0; kk < H3Basis<Q>::n; ++kk) {
+      const R mk = M[kk] * R(1.0 / nrm.v[kk]);
+      Ab[H3Basis<Q>::c0(kk)] += mk;
+      if (H3Basis<Q>::sgn(kk) > 0.0) Ab[H3Basis<Q>::c1(kk)] += mk;
+      if (H3Basis<Q>::sgn(kk) < 0.0) Ab[H3Basis<Q>::c1(kk)] -= mk;
+    }
+  }
+  // equilibrium: drho, rho and v
+  R drhob = s0;
+  R rhob = s1;
+  R vxb = rho * (evx - R(3) * vx * s0), vyb = rho * (evy - R(3) * vy * s0), vzb = rho * (evz - R(3) * vz * s0);
+  // third-order equilibrium A0 = rho v v v:
+  // xxy, xxz, xyy, yyz, xzz, yzz, xyz
+  rhob += Ab[0] * vx * vx * vy + Ab[1] * vx * vx * vz + Ab[2] * vx * vy * vy + Ab[3] * vy * vy * vz +
+          Ab[4] * vx * vz * vz + Ab[5] * vy * vz * vz + Ab[6] * vx * vy * vz;
+  vxb += rho * (Ab[0] * R(2) * vx * vy + Ab[1] * R(2) * vx * vz + Ab[2] * vy * vy + Ab[4] * vz * vz + Ab[6] * vy * vz);
+  vyb += rho * (Ab[0] * vx * vx + Ab[2] * R(2) * vx * vy + Ab[3] * R(2) * vy * vz + Ab[5] * vz * vz + Ab[6] * vx * vz);
+  vzb += rho * (Ab[1] * vx * vx + Ab[3] * vy * vy + Ab[4] * R(2) * vx * vz + Ab[5] * R(2) * vy * vz + Ab[6] * vx * vy);
+  // regularized f^(1), times c1: Pi directly, and Pi and u through A1
+  R pxxb = c1 * R(4.5) * (pbxx - cs2 * pbtr), pyyb = c1 * R(4.5) * (pbyy - cs2 * pbtr),
+    pzzb = c1 * R(4.5) * (pbzz - cs2 * pbtr);
+  R pxyb = c1 * R(9) * pbxy, pxzb = c1 * R(9) * pbxz, pyzb = c1 * R(9) * pbyz;
+  R uxb = R(0), uyb = R(0), uzb = R(0);
+  {
+    R B[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) B[m] = c1 * Ab[m];
+    // A1: xxy = 2 ux pxy + uy pxx; xxz = 2 ux pxz + uz pxx; xyy = 2 uy pxy + ux pyy;
+    //     yyz = 2 uy pyz + uz pyy; xzz = 2 uz pxz + ux pzz; yzz = 2 uz pyz + uy pzz;
+    //     xyz = ux pyz + uy pxz + uz pxy
+    uxb += B[0] * R(2) * pxy + B[1] * R(2) * pxz + B[2] * pyy + B[4] * pzz + B[6] * pyz;
+    uyb += B[0] * pxx + B[2] * R(2) * pxy + B[3] * R(2) * pyz + B[5] * pzz + B[6] * pxz;
+    uzb += B[1] * pxx + B[3] * pyy + B[4] * R(2) * pxz + B[5] * R(2) * pyz + B[6] * pxy;
+    pxxb += B[0] * uy + B[1] * uz;
+    pyyb += B[2] * ux + B[3] * uz;
+    pzzb += B[4] * ux + B[5] * uy;
+    pxyb += B[0] * R(2) * ux + B[2] * R(2) * uy + B[6] * uz;
+    pxzb += B[1] * R(2) * ux + B[4] * R(2) * uz + B[6] * uy;
+    pyzb += B[3] * R(2) * uy + B[5] * R(2) * uz + B[6] * ux;
+  }
+  // Guo term, times c2: d/du = w (-3 F + 9 (c.F) c)
+  uxb += c2 * (gux - R(3) * Fx * gF);
+  uyb += c2 * (guy - R(3) * Fy * gF);
+  uzb += c2 * (guz - R(3) * Fz * gF);
+  // homogenized velocity
+  R phib = R(0);
+  if (POROUS) {
+    uxb += phi * vxb;
+    uyb += phi * vyb;
+    uzb += phi * vzb;
+    phib = vxb * ux + vyb * uy + vzb * uz;
+  } else {
+    uxb += vxb;
+    uyb += vyb;
+    uzb += vzb;
+  }
+  // relaxation rate: om = 1/tau, tau = (tau0 + sqrt(A))/2, A = tau0^2 + smag pn / rho
+  const R omb = -c1b - R(0.5) * c2b;
+  const R taub = -omb * om * om;
+  const R Abar = R(0.5) * taub / (R(2) * sA);
+  const R pnb = Abar * smag * ir;
+  R irb = Abar * smag * pn;
+  const R q = pn > R(0) ? pnb / pn : R(0);
+  pxxb += q * pxx;
+  pyyb += q * pyy;
+  pzzb += q * pzz;
+  pxyb += R(2) * q * pxy;
+  pxzb += R(2) * q * pxz;
+  pyzb += R(2) * q * pyz;
+  // Pi = M2 - drho c_s^2 I - rho u u
+  drhob -= cs2 * (pxxb + pyyb + pzzb);
+  rhob -= ux * ux * pxxb + uy * uy * pyyb + uz * uz * pzzb + ux * uy * pxyb + ux * uz * pxzb + uy * uz * pyzb;
+  uxb -= rho * (R(2) * ux * pxxb + uy * pxyb + uz * pxzb);
+  uyb -= rho * (R(2) * uy * pyyb + ux * pxyb + uz * pyzb);
+  uzb -= rho * (R(2) * uz * pzzb + ux * pxzb + uy * pyzb);
+  // u = m / rho
+  const R mxb = uxb * ir, myb = uyb * ir, mzb = uzb * ir;
+  irb += uxb * mx + uyb * my + uzb * mz;
+  rhob -= irb * ir * ir;
+  drhob += rhob;
+  // moments -> populations
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+    R s = drhob;
+    acc(s, cx, mxb);
+    acc(s, cy, myb);
+    acc(s, cz, mzb);
+    acc(s, cx * cx, pxxb);
+    acc(s, cy * cy, pyyb);
+    acc(s, cz * cz, pzzb);
+    acc(s, cx * cy, pxyb);
+    acc(s, cx * cz, pxzb);
+    acc(s, cy * cz, pyzb);
+    out(i, s);
+  }
+  return phib;
+}
+
 // Cell that wrote the adjoint that cell n reads for direction i (see above).
 template <int Q, bool SOLID>
 __device__ __forceinline__ int writer_of(const Nb &n, unsigned sm, int i) {
@@ -214,7 +437,7 @@ __device__ __forceinline__ int writer_of(const Nb &n, unsigned sm, int i) {
   return n.cell + nb_off<Q>(n, i, +1);
 }
 
-template <int Q, typename S, bool ODD, bool POROUS, bool SOLID>
+template <int Q, typename S, bool ODD, bool POROUS, bool SOLID, bool RR>
 __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                     typename Store<S>::R *__restrict__ dev,
                                                     const double *__restrict__ m_prev, double *__restrict__ m_next,
@@ -254,8 +477,10 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
 #pragma unroll
   for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
   const R ph = POROUS ? phi[n.cell] : R(1);
-  const R phib = collide_bulk_vjp<Q, R, POROUS>(g, dmu, ph, k,
-                                                [&](int i, R v) { dev[read_slot<Q, ODD>(n, sm, i, N)] = v; });
+  auto store = [&](int i, R v) { dev[read_slot<Q, ODD>(n, sm, i, N)] = v; };
+  R phib;
+  if constexpr (RR) phib = collide_bulk_rr_vjp<Q, R, POROUS>(g, dmu, ph, k, store);
+  else phib = collide_bulk_vjp<Q, R, POROUS>(g, dmu, ph, k, store);
   m_next[n.cell] = m;
   if (POROUS) grad[n.cell] += (double)phib;
 }
@@ -390,12 +615,17 @@ int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv) {
     double *grad = (double *)gradv;
     const R *phi = (const R *)ctx->phi;
     // reads the common modes of the later state (the other parity), writes this parity's
-    if (ctx->porous)
-      k_adjoint<Q, S, ODD, true, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(
-          (const S *)ctx->pop, ctx->flags, dev, a.m_other, a.m_cur, phi, grad, ctx->ka, t);
-    else
-      k_adjoint<Q, S, ODD, false, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(
-          (const S *)ctx->pop, ctx->flags, dev, a.m_other, a.m_cur, phi, grad, ctx->ka, t);
+    auto go = [&](auto kern) {
+      kern<<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, dev, a.m_other, a.m_cur, phi,
+                                                  grad, ctx->ka, t);
+    };
+    if (ctx->porous) {
+      if (ctx->ka.rr) go(k_adjoint<Q, S, ODD, true, SOLID, true>);
+      else go(k_adjoint<Q, S, ODD, true, SOLID, false>);
+    } else {
+      if (ctx->ka.rr) go(k_adjoint<Q, S, ODD, false, SOLID, true>);
+      else go(k_adjoint<Q, S, ODD, false, SOLID, false>);
+    }
     return check(ctx, "k_adjoint");
   });
 }

@@ -110,43 +110,6 @@ __device__ __forceinline__ void lid_equilibrium(R g[Q], const KArgs &k) {
   }
 }
 
-// Third-order Hermite coefficients K_k = <A, P_k> / |P_k|^2 of a tensor given
-// by its components A[0..6] (xxy, xxz, xyy, yyz, xzz, yzz, xyz).
-template <int Q, typename R>
-__device__ __forceinline__ void third_coefs(const R A[7], R K[7]) {
-  constexpr H3Norms<Q> nrm = h3_norms<Q>();
-#pragma unroll
-  for (int k = 0; k < H3Basis<Q>::n; ++k) {
-    R m = A[H3Basis<Q>::c0(k)];
-    if (H3Basis<Q>::sgn(k) > 0.0) m += A[H3Basis<Q>::c1(k)];
-    if (H3Basis<Q>::sgn(k) < 0.0) m -= A[H3Basis<Q>::c1(k)];
-    K[k] = m * R(1.0 / nrm.v[k]);
-  }
-}
-// sum_k P_k(c_i) K_k (the caller multiplies by w_i).
-template <int Q, typename R>
-__device__ __forceinline__ R third_term(int i, const R K[7]) {
-  R v = R(0);
-#pragma unroll
-  for (int k = 0; k < H3Basis<Q>::n; ++k) {
-    const double p = H3Basis<Q>::P(k, i);
-    if (p != 0.0) v += R(p) * K[k];
-  }
-  return v;
-}
-// Components of rho v v v.
-template <typename R>
-__device__ __forceinline__ void cube_tensor(R rho, R vx, R vy, R vz, R A[7]) {
-  const R rx = rho * vx, ry = rho * vy;
-  A[0] = rx * vx * vy;
-  A[1] = rx * vx * vz;
-  A[2] = rx * vy * vy;
-  A[3] = ry * vy * vz;
-  A[4] = rx * vz * vz;
-  A[5] = ry * vz * vz;
-  A[6] = rx * vy * vz;
-}
-
 // Bulk collision on deviations g (sigma = 1): BGK with tau_eff from the
 // non-equilibrium stress, homogenized velocity u_hat = phi u, Guo forcing.
 // Opposite directions i and i+H share everything but a sign: with

@@ -23,12 +23,16 @@ from gpu_helpers import announce, oracle_for
 pytestmark = pytest.mark.gpu
 
 
-def _case(shape=(20, 12, 8)):
-    return I.porous_channel(shape=shape)
+def _case(shape=(20, 12, 8), collision=0):
+    c = I.porous_channel(shape=shape)
+    c.collision = collision
+    return c
 
 
-def test_transpose_one_step(gpu):
-    case = _case()
+@pytest.mark.parametrize("collision", [0, 1])
+def test_transpose_one_step(gpu, collision):
+    """collision 0: BGK; 1: recursive regularized (its own vector-Jacobian product)."""
+    case = _case(collision=collision)
     q, N = case.q, case.ncells
     c, w, _ = O.velocity_set(q)
     f_n = I.random_state(w, N, seed_offset=21, amp=0.05)
@@ -37,7 +41,7 @@ def test_transpose_one_step(gpu):
     dphi = rng.standard_normal(N)
     wv = rng.standard_normal((q, N))
     for parity in (0, 1):
-        announce(f"transpose test parity {parity}")
+        announce(f"transpose test collision {collision} parity {parity}")
         # oracle: tangent of one step from f_n in direction (v, dphi)
         orc = oracle_for(case, tangent=True)
         orc.set_populations(f_n, v)
@@ -66,8 +70,9 @@ def test_transpose_one_step(gpu):
         assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
 
 
-def test_gradient_matches_oracle_tangent(gpu):
-    case = _case((16, 12, 8))
+@pytest.mark.parametrize("collision", [0, 1])
+def test_gradient_matches_oracle_tangent(gpu, collision):
+    case = _case((16, 12, 8), collision=collision)
     planes = (2, 13)
     T = 20
     lat = gpu.Lattice(case, storage="f64")

@@ -117,13 +117,3 @@ def test_rr_cavity_fp64(gpu):
     case = rr(I.cavity((140, 20, 18), q=19))
     _, _, rho, u, orho, ou = _run_both(gpu, case, 80, "f64")
     _check("rr cavity f64", moment_errors(rho, u, orho, ou), 1e-12)
-
-
-def test_rr_adjoint_refused(gpu):
-    case = rr(I.porous_channel(shape=(16, 12, 8)))
-    lat = gpu.Lattice(case, storage="f64")
-    lam, grad = lat.new_adjoint(), lat.new_gradient()
-    gpu.lbm_adjoint_seed(lat.ctx, case.extra["planes"], lam)
-    with pytest.raises(gpu.LbmError) as e:
-        gpu.lbm_adjoint_step(lat.ctx, lam, grad)
-    assert e.value.code == gpu.EINVAL and "BGK" in str(e.value)
