@@ -44,6 +44,7 @@ class Params(C.Structure):
         ("u_ref", C.c_double), ("z0", C.c_double),
         ("lid", C.c_int),
         ("collision", C.c_int),
+        ("fd_weight", C.c_double),
     ]
 
 
@@ -105,7 +106,7 @@ def _ptr(a):
 
 def make_params(q, shape, periodic=(1, 1, 1), tau0=0.6, cs_smag=0.0, force=(0.0, 0.0, 0.0),
                 wall_model=0, kappa=0.41, E=9.0, fringe_len=0, u_ref=0.0, z0=1.0, lid=0,
-                collision=0) -> Params:
+                collision=0, fd_weight=0.0) -> Params:
     p = Params()
     p.q = q
     p.nx, p.ny, p.nz = shape
@@ -115,6 +116,7 @@ def make_params(q, shape, periodic=(1, 1, 1), tau0=0.6, cs_smag=0.0, force=(0.0,
     p.wall_model, p.kappa, p.E = wall_model, kappa, E
     p.fringe_len, p.u_ref, p.z0, p.lid = fringe_len, u_ref, z0, lid
     p.collision = collision
+    p.fd_weight = fd_weight
     return p
 
 

@@ -38,6 +38,14 @@
  *     makes -F/2), 2 (Pi^neq) and 3 (by the recursion u_a Pi_bc + u_b Pi_ac
  *     + u_c Pi_ab), each third-order term projected on the Hermite
  *     components the lattice carries (see hermite3 below);
+ *   - hybrid collision (Eq. (7)) with weight fd_weight = 1 - sigma of the
+ *     finite-difference strain: S^FD from central differences of the
+ *     pre-collision velocity field of the same step (one-sided next to a
+ *     non-fluid neighbour, zero with none), f^(1,FD) = -(w rho tau / c_s^2)
+ *     H^(2) : S^FD; the hybrid blends the second-order part, the third-order
+ *     part keeps the factor sigma and the first-order part (-F/2) is kept
+ *     whole; wall cells (sigma = 0 there) use the full S^FD with its
+ *     t-n component replaced by the wall law's G/2;
  *   - f^(1) = f - f^eq(rho, u); f* = f^eq(rho, u_hat) + (1 - 1/tau)(f - f^eq(rho,u));
  *   - porosity phi in [0,1], 1 = fluid: u_hat = phi*u + (1-phi)*u_B, u_B = 0
  *     in the bulk (the weights of Eq. (12) read with d := 1 - phi);
@@ -77,6 +85,7 @@ typedef struct {
   double u_ref, z0;
   int lid;
   int collision; /* 0: BGK (second-order equilibrium); 1: recursive regularized, third order */
+  double fd_weight; /* 1 - sigma of Eq. (7): weight of the finite-difference strain (collision 1 only) */
 } orc_params;
 }
 
@@ -388,6 +397,8 @@ struct Sim : SimBase {
   std::vector<long> wcell, wref;
   std::vector<double> wnorm, wyb, wyr;
   std::vector<long> wall_index; /* cell -> wall record, -1 if none */
+  /* pre-collision velocity field [3][N] of the current step (hybrid collision only) */
+  std::vector<T> uf;
   /* wall-model records of the current step (FP64) */
   std::vector<double> wt, wutan, wG, wtau, wutau;
 
@@ -440,6 +451,10 @@ struct Sim : SimBase {
     }
     if (p.collision != 0 && p.collision != 1) {
       err = "collision must be 0 (BGK) or 1 (recursive regularized)";
+      return ORC_EINVAL;
+    }
+    if (!(p.fd_weight >= 0.0 && p.fd_weight <= 1.0) || (p.fd_weight > 0.0 && p.collision != 1)) {
+      err = "fd_weight must be in [0, 1], and above 0 only with the recursive regularized collision";
       return ORC_EINVAL;
     }
     vs = make_velocity_set(p.q);
@@ -588,6 +603,38 @@ struct Sim : SimBase {
     return status;
   }
 
+  /* Velocity field of the current state (Guo velocity, fluid cells). */
+  void velocity_field() {
+    uf.assign((size_t)3 * N, T(0.0));
+    for (long c = 0; c < N; ++c) {
+      if (!fluid[c]) continue;
+      T r, j[3];
+      local_moments(c, r, j);
+      for (int a = 0; a < 3; ++a) uf[(size_t)a * N + c] = (j[a] + 0.5 * p.force[a]) / r;
+    }
+  }
+  /* Strain rate S_ab = (d_a u_b + d_b u_a)/2 at cell c by central differences
+   * of the velocity field; one-sided where one neighbour along the axis is not
+   * fluid, zero where neither is. */
+  void strain_fd(long c, T S[3][3]) const {
+    T D[3][3];
+    for (int a = 0; a < 3; ++a) {
+      int e[3] = {0, 0, 0};
+      e[a] = 1;
+      long xp = neighbor(c, e[0], e[1], e[2]), xm = neighbor(c, -e[0], -e[1], -e[2]);
+      bool fp = is_fluid(xp), fm = is_fluid(xm);
+      for (int b = 0; b < 3; ++b) {
+        T uc = uf[(size_t)b * N + c];
+        if (fp && fm) D[a][b] = 0.5 * (uf[(size_t)b * N + xp] - uf[(size_t)b * N + xm]);
+        else if (fp) D[a][b] = uf[(size_t)b * N + xp] - uc;
+        else if (fm) D[a][b] = uc - uf[(size_t)b * N + xm];
+        else D[a][b] = T(0.0);
+      }
+    }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) S[a][b] = 0.5 * (D[a][b] + D[b][a]);
+  }
+
   /* Bulk cell (sigma = 1): homogenized Smagorinsky collision with Guo
    * forcing; BGK (collision 0) keeps all of f - f^eq, the recursive
    * regularized model (collision 1) keeps its Hermite reconstruction. */
@@ -633,11 +680,25 @@ struct Sim : SimBase {
           for (int g = 0; g < 3; ++g) A[a][b][g] = u[a] * Pi[b][g] + u[b] * Pi[a][g] + u[g] * Pi[a][b];
       T t3[27];
       third_order_term(vs, h3, A, t3);
-      T trPi = Pi[0][0] + Pi[1][1] + Pi[2][2];
+      /* hybrid (Eq. (7)): the second-order part blends Pi with the stress of
+       * the finite-difference strain, -2 rho c_s^2 tau S^FD (f^(1,FD) of
+       * Eq. (10)); the third-order part keeps the factor sigma */
+      const double sig = 1.0 - p.fd_weight;
+      T Ph[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Ph[a][b] = Pi[a][b];
+      if (p.fd_weight > 0.0) {
+        T S[3][3];
+        strain_fd(c, S);
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) Ph[a][b] = sig * Pi[a][b] - p.fd_weight * (2.0 / 3.0) * rho * tau * S[a][b];
+        for (int i = 0; i < vs.q; ++i) t3[i] = sig * t3[i];
+      }
+      T trPi = Ph[0][0] + Ph[1][1] + Ph[2][2];
       for (int i = 0; i < vs.q; ++i) {
         T cPc(0.0);
         for (int a = 0; a < 3; ++a)
-          for (int b = 0; b < 3; ++b) cPc += double(vs.c[i][a] * vs.c[i][b]) * Pi[a][b];
+          for (int b = 0; b < 3; ++b) cPc += double(vs.c[i][a] * vs.c[i][b]) * Ph[a][b];
         T ca1 = double(vs.c[i][0]) * a1[0] + double(vs.c[i][1]) * a1[1] + double(vs.c[i][2]) * a1[2];
         /* w_i H^(1)_i . a^(1) / c_s^2 = 3 w_i xi.a1;
          * w_i H^(2)_i : Pi / (2 c_s^4) = 9/2 w_i (xi.Pi.xi - c_s^2 tr Pi) */
@@ -671,16 +732,36 @@ struct Sim : SimBase {
     double tau = wtau[k], G = wG[k];
     T feq[27];
     eqm(rho, uw, feq);
+    /* with the hybrid collision, the full finite-difference strain with its
+     * t-n component replaced by the wall law's G/2 */
+    T S[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) S[a][b] = T(0.0);
+    if (p.fd_weight > 0.0) {
+      strain_fd(c, S);
+      T tSn(0.0);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) tSn += t[a] * S[a][b] * n[b];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) S[a][b] = S[a][b] + (0.5 * G - tSn) * (t[a] * n[b] + n[a] * t[b]);
+    } else {
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) S[a][b] = 0.5 * G * (t[a] * n[b] + n[a] * t[b]);
+    }
+    T trS = S[0][0] + S[1][1] + S[2][2];
     for (int i = 0; i < vs.q; ++i) {
-      double ct = vs.c[i][0] * t[0] + vs.c[i][1] * t[1] + vs.c[i][2] * t[2];
-      double cn = vs.c[i][0] * n[0] + vs.c[i][1] * n[1] + vs.c[i][2] * n[2];
-      T ffd = -3.0 * vs.w[i] * rho * tau * G * ct * cn;
+      T cSc(0.0);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) cSc += double(vs.c[i][a] * vs.c[i][b]) * S[a][b];
+      /* f^(1,FD)_i = -(w_i rho tau / c_s^2) H^(2)_i : S */
+      T ffd = -3.0 * vs.w[i] * rho * tau * (cSc - trS / 3.0);
       fo[i] = feq[i] + (1.0 - 1.0 / tau) * ffd + (1.0 - 0.5 / tau) * guo_term(vs, i, uw, p.force);
     }
     return std::isfinite(val(rho)) && val(rho) > 0.0;
   }
 
   int step_once() {
+    if (p.fd_weight > 0.0) velocity_field();
     if (p.wall_model && !wcell.empty()) {
       int rc = wall_prepass();
       if (rc != ORC_OK) return rc;
@@ -944,6 +1025,7 @@ void orc_collide_bulk2(int q, int collision, double tau0, double cs, const doubl
   s.p = orc_params{};
   s.p.q = q;
   s.p.collision = collision;
+  s.p.fd_weight = 0.0;
   s.p.tau0 = tau0;
   s.p.cs_smag = cs;
   for (int a = 0; a < 3; ++a) s.p.force[a] = force[a];

@@ -13,6 +13,7 @@ import pytest
 import oracle as O
 import test_oracle_pins as pins
 import test_oracle_pins_rr as pins_rr
+import test_oracle_pins_hybrid as pins_hy
 
 SRC = os.path.join(os.path.dirname(O.__file__), "lbm_oracle.cpp")
 
@@ -43,6 +44,13 @@ MUTATIONS = [
      "fo[i] = feqh[i] + (1.0 - 1.0 / tau) * (fi[i] - feq[i]) +"),
     ("third-order equilibrium term dropped", "for (int i = 0; i < vs.q; ++i) feq[i] += t[i];",
      "for (int i = 0; i < vs.q; ++i) feq[i] += 0.0 * t[i];"),
+    ("finite-difference stress sign", "Ph[a][b] = sig * Pi[a][b] - p.fd_weight * (2.0 / 3.0)",
+     "Ph[a][b] = sig * Pi[a][b] + p.fd_weight * (2.0 / 3.0)"),
+    ("one-sided difference reversed", "else if (fp) D[a][b] = uf[(size_t)b * N + xp] - uc;",
+     "else if (fp) D[a][b] = uc - uf[(size_t)b * N + xp];"),
+    ("wall t-n component", "(0.5 * G - tSn)", "(G - tSn)"),
+    ("hybrid third-order factor dropped", "for (int i = 0; i < vs.q; ++i) t3[i] = sig * t3[i];",
+     "for (int i = 0; i < vs.q; ++i) t3[i] = t3[i];"),
 ]
 
 PIN_TESTS = [
@@ -62,6 +70,9 @@ PIN_TESTS = [
     (pins_rr.test_equilibrium3_moments, [(19,), (27,)]),
     (pins_rr.test_rr_keeps_bgk_low_moments_and_sets_third, [(19,), (27,)]),
     (pins_rr.test_rr_removes_ghost_modes, [(19,)]),
+    (pins_hy.test_hybrid_fd_stress_quadratic_shear, [(19,)]),
+    (pins_hy.test_hybrid_blend_and_third_moments, [(27,)]),
+    (pins_hy.test_hybrid_wall_cell_tensor, [(1.0,)]),
 ]
 
 
