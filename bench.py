@@ -64,7 +64,7 @@ def make_case(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(name, budget_s=12.0, collision=0):
+def cpu_baseline(name, budget_s=12.0, collision=0, fd_weight=0.0):
     """The FP64 oracle on a bounded crop of the workload (same x-y plane,
     fewer z planes), timed around its step loop on the host cores."""
     import oracle as O
@@ -85,12 +85,15 @@ def cpu_baseline(name, budget_s=12.0, collision=0):
         case = I.porous_channel(shape=(128, 128, 16))
         sample = "porous channel crop 128x128x16 D3Q19 FP64"
     case.collision = collision
+    case.fd_weight = fd_weight
     if collision:
         sample += ", recursive regularized collision"
+    if fd_weight > 0:
+        sample += f", hybrid with finite-difference weight {fd_weight}"
     p = O.make_params(case.q, case.shape, periodic=case.periodic, tau0=case.tau0, cs_smag=case.cs_smag,
                       force=case.force, wall_model=case.wall_model, kappa=case.kappa, E=case.E,
                       fringe_len=case.fringe_len, u_ref=case.u_ref, z0=case.z0, lid=case.lid,
-                      collision=case.collision)
+                      collision=case.collision, fd_weight=case.fd_weight)
     s = O.Oracle(p, mask=case.mask, wall_dist=case.wall_dist, porosity=case.porosity, rho0=case.rho0, u0=case.u0)
     t0 = time.perf_counter()
     s.step(1)
@@ -134,6 +137,8 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "rr3"],
                     help="bulk collision model: BGK or recursive regularized (third order)")
+    ap.add_argument("--fd-weight", type=float, default=0.0,
+                    help="with --collision rr3: weight 1 - sigma of the finite-difference strain (hybrid)")
     ap.add_argument("--profile-steps", type=int, default=2000,
                     help="precision workload: second horizon, with mean-profile errors")
     args = ap.parse_args()
@@ -154,6 +159,9 @@ def main():
     if args.collision == "rr3":
         case.collision = 1
         wname += "_rr3"
+        if args.fd_weight > 0:
+            case.fd_weight = args.fd_weight
+            wname += f"_hybrid{args.fd_weight:g}"
     print(f"[bench] workload {wname} storage {storage} cells {case.ncells}", file=sys.stderr, flush=True)
     if args.workload == "adjoint":
         return bench_adjoint(args, torch, lbm, case, storage, wname)
@@ -222,7 +230,8 @@ def main():
                   "f64": "f64"}[storage],
         "data": "synthetic",
         "config": {"workload": wname, "cells": N, "fluid_cells": nfluid, "wall_cells": nwall, "lattice": f"D3Q{q}",
-                   "storage": storage, "collision": args.collision},
+                   "storage": storage, "collision": args.collision,
+                   "fd_weight": args.fd_weight if args.collision == "rr3" else 0.0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": "k_bulk", "avg_launch_ms": round(k2_ms, 5), "alg_bytes_per_launch": k2_bytes},
@@ -238,7 +247,8 @@ def main():
         out["copy_ceiling_gbs"] = round(copy_ceiling(torch), 1)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, collision=1 if args.collision == "rr3" else 0)
+        out["cpu_baseline"] = cpu_baseline(args.workload, collision=1 if args.collision == "rr3" else 0,
+                                           fd_weight=args.fd_weight if args.collision == "rr3" else 0.0)
     out.pop("mass_drift_rel")
     print(json.dumps(out), flush=True)
 

@@ -76,6 +76,12 @@ typedef struct {
   double u_ref, z0;   /* log-law inflow u_ref ln(1 + z_c/z0)/ln(1 + z_top/z0) */
   int lid;            /* 1: the top plane z = nz-1 holds the inflow equilibrium */
   int collision;      /* LBM_BGK or LBM_RR3 */
+  double fd_weight;   /* 1 - sigma of Eq. (7), in [0, 1], above 0 only with LBM_RR3:
+                       * weight of the finite-difference strain (Eq. (10)) taken
+                       * from central differences of the step's velocity field;
+                       * wall cells then use the full finite-difference strain
+                       * with its wall-normal shear replaced by the wall law's.
+                       * 0 = purely local. */
   void *stream;       /* hipStream_t for all device work (NULL = null stream) */
 } lbm_params;
 

@@ -45,7 +45,7 @@
  *     H^(2) : S^FD; the hybrid blends the second-order part, the third-order
  *     part keeps the factor sigma and the first-order part (-F/2) is kept
  *     whole; wall cells (sigma = 0 there) use the full S^FD with its
- *     t-n component replaced by the wall law's G/2;
+ *     wall-normal shear replaced by the wall law's, G/2 along t;
  *   - f^(1) = f - f^eq(rho, u); f* = f^eq(rho, u_hat) + (1 - 1/tau)(f - f^eq(rho,u));
  *   - porosity phi in [0,1], 1 = fluid: u_hat = phi*u + (1-phi)*u_B, u_B = 0
  *     in the bulk (the weights of Eq. (12) read with d := 1 - phi);
@@ -732,18 +732,25 @@ struct Sim : SimBase {
     double tau = wtau[k], G = wG[k];
     T feq[27];
     eqm(rho, uw, feq);
-    /* with the hybrid collision, the full finite-difference strain with its
-     * t-n component replaced by the wall law's G/2 */
+    /* with the hybrid collision, the full finite-difference strain whose
+     * wall-normal shear (the tangential part s of S n, in every tangential
+     * direction) is replaced by the wall law's, G/2 along t:
+     * S' = S - (s n^T + n s^T) + (G/2)(t n^T + n t^T), s = S n - (n.S.n) n */
     T S[3][3];
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) S[a][b] = T(0.0);
     if (p.fd_weight > 0.0) {
       strain_fd(c, S);
-      T tSn(0.0);
+      T Sn[3], nSn(0.0);
+      for (int a = 0; a < 3; ++a) {
+        Sn[a] = S[a][0] * n[0] + S[a][1] * n[1] + S[a][2] * n[2];
+        nSn += n[a] * Sn[a];
+      }
+      T sv[3];
+      for (int a = 0; a < 3; ++a) sv[a] = Sn[a] - nSn * n[a];
       for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) tSn += t[a] * S[a][b] * n[b];
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) S[a][b] = S[a][b] + (0.5 * G - tSn) * (t[a] * n[b] + n[a] * t[b]);
+        for (int b = 0; b < 3; ++b)
+          S[a][b] = S[a][b] - (sv[a] * n[b] + n[a] * sv[b]) + 0.5 * G * (t[a] * n[b] + n[a] * t[b]);
     } else {
       for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) S[a][b] = 0.5 * G * (t[a] * n[b] + n[a] * t[b]);

@@ -48,6 +48,7 @@ class Params(C.Structure):
         ("u_ref", C.c_double), ("z0", C.c_double),
         ("lid", C.c_int),
         ("collision", C.c_int),
+        ("fd_weight", C.c_double),
         ("stream", C.c_void_p),
     ]
 
@@ -163,7 +164,7 @@ def _check(ctx, rc):
 
 def make_params(q, shape, periodic=(1, 1, 1), storage=F64, tau0=0.6, cs_smag=0.0, force=(0.0, 0.0, 0.0),
                 wall_model=0, kappa=0.41, E=9.0, fringe_len=0, u_ref=0.0, z0=1.0, lid=0, collision=0,
-                stream=None) -> Params:
+                fd_weight=0.0, stream=None) -> Params:
     p = Params()
     p.lattice = q
     p.nx, p.ny, p.nz = shape
@@ -174,6 +175,7 @@ def make_params(q, shape, periodic=(1, 1, 1), storage=F64, tau0=0.6, cs_smag=0.0
     p.wall_model, p.kappa, p.E = wall_model, kappa, E
     p.fringe_len, p.u_ref, p.z0, p.lid = fringe_len, u_ref, z0, lid
     p.collision = COLLISION_NAMES.get(collision, collision) if isinstance(collision, str) else collision
+    p.fd_weight = fd_weight
     p.stream = stream
     return p
 
@@ -371,7 +373,8 @@ class Lattice:
         self.p = make_params(case.q, case.shape, periodic=case.periodic, storage=self.storage, tau0=case.tau0,
                              cs_smag=case.cs_smag, force=case.force, wall_model=case.wall_model, kappa=case.kappa,
                              E=case.E, fringe_len=case.fringe_len, u_ref=case.u_ref, z0=case.z0, lid=case.lid,
-                             collision=getattr(case, "collision", 0), stream=stream.cuda_stream)
+                             collision=getattr(case, "collision", 0), fd_weight=getattr(case, "fd_weight", 0.0),
+                             stream=stream.cuda_stream)
         porous = case.porosity is not None
         nbytes = lbm_workspace_bytes(self.p, case.mask, porous)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")

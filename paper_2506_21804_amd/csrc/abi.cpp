@@ -89,11 +89,15 @@ bool params_ok(const lbm_params *p, std::string &msg) {
     msg = "collision must be LBM_BGK or LBM_RR3";
     return false;
   }
+  if (!(p->fd_weight >= 0.0 && p->fd_weight <= 1.0) || (p->fd_weight > 0.0 && p->collision != LBM_RR3)) {
+    msg = "fd_weight must be in [0, 1], and above 0 only with LBM_RR3";
+    return false;
+  }
   return true;
 }
 
 struct Layout {
-  size_t pop, flags, phi, tables, wcell, wref, wrefwall, wlist, wrec, partial, result, errflag, total;
+  size_t pop, flags, phi, tables, vel, wcell, wref, wrefwall, wlist, wrec, partial, result, errflag, total;
 };
 
 Layout layout_of(const lbm_params &p, long long nwall, bool porous) {
@@ -109,6 +113,8 @@ Layout layout_of(const lbm_params &p, long long nwall, bool porous) {
   off += porous ? align_up(N * rb) : 0;
   L.tables = off;
   off += align_up(((size_t)p.nz + p.nx) * rb);
+  L.vel = off;
+  off += p.fd_weight > 0.0 ? align_up(3 * N * rb) : 0;
   L.wcell = off;
   off += align_up((size_t)nwall * sizeof(int));
   L.wref = off;
@@ -248,6 +254,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   ctx->flags = (uint8_t *)(base + L.flags);
   ctx->phi = ctx->porous ? base + L.phi : nullptr;
   ctx->tables = base + L.tables;
+  ctx->vel = p->fd_weight > 0.0 ? base + L.vel : nullptr;
   ctx->nwall = (int)nwall;
   ctx->wcell = (int *)(base + L.wcell);
   ctx->wref = (int *)(base + L.wref);
@@ -276,6 +283,8 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   k.fringe_start = p->fringe_len > 0 ? p->nx - p->fringe_len : p->nx;
   k.u_lid = p->u_ref;  // ln(1 + z_top/z0) / ln(1 + z_top/z0) = 1 at the lid plane
   k.rr = p->collision == LBM_RR3 ? 1 : 0;
+  k.fdw = p->fd_weight;
+  k.vel = p->fd_weight > 0.0 ? ctx->vel : nullptr;
   // inflow profile u_in(z) and fringe weights lambda(x)
   std::vector<double> tab((size_t)p->nz + p->nx, 0.0);
   if (p->fringe_len > 0 || p->lid) {
@@ -473,6 +482,8 @@ int lbm_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lambda) {
 int lbm_adjoint_step(lbm_ctx *ctx, void *lambda, void *grad_phi) {
   if (!ctx || !lambda || !grad_phi) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
   if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
+  if (ctx->ka.fdw > 0.0)
+    return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the finite-difference strain");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   return dev_adjoint_step(ctx, lambda, grad_phi);
@@ -498,6 +509,8 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
   if (T < 1 || nsnap < 1 || !snapshots || !lambda || !grad_phi || !planes)
     return set_err(ctx, LBM_EINVAL, "gradient needs T >= 1, nsnap >= 1 and non-null buffers");
   if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
+  if (ctx->ka.fdw > 0.0)
+    return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the finite-difference strain");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   const size_t sb = lbm_state_bytes(ctx);

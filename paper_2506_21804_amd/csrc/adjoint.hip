@@ -260,8 +260,7 @@ __device__ __forceinline__ R collide_bulk_rr_vjp(const R g[Q], const R mu[Q], R 
   const R vv = vx * vx + vy * vy + vz * vz;
   const R uF = ux * Fx + uy * Fy + uz * Fz;
   const R tr3 = (pxx + pyy + pzz) * cs2;
-  R A0[7], A1[7], K0[7], K1[7];
-  cube_tensor(rho, vx, vy, vz, A0);
+  R A1[7], K1[7];
   A1[0] = R(2) * ux * pxy + uy * pxx;
   A1[1] = R(2) * ux * pxz + uz * pxx;
   A1[2] = R(2) * uy * pxy + ux * pyy;

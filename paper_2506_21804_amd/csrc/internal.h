@@ -47,6 +47,8 @@ struct KArgs {
   int fringe_start;  // first fringe plane in x (nx when there is no fringe)
   double u_lid;      // lid velocity (x component)
   int rr;            // 1: recursive regularized collision (third order), 0: BGK
+  double fdw;        // weight of the finite-difference strain (1 - sigma), 0 = local only
+  const void *vel;   // [3][N] velocity field of the current step, compute type (fdw > 0)
   const void *uin;   // [nz] fringe inflow profile, compute type
   const void *lam;   // [nx] fringe blend weight, compute type (0 before the fringe)
 };
@@ -98,6 +100,7 @@ struct lbm_ctx {
   uint8_t *flags = nullptr;   // [N]
   void *phi = nullptr;        // [N] compute type, porous only
   void *tables = nullptr;     // [nz] inflow + [nx] fringe weights, compute type
+  void *vel = nullptr;        // [3][N] velocity field, compute type (hybrid collision only)
   int nwall = 0;
   int *wcell = nullptr;       // [nwall]
   int *wref = nullptr;        // [nwall]

@@ -110,6 +110,37 @@ __device__ __forceinline__ void lid_equilibrium(R g[Q], const KArgs &k) {
   }
 }
 
+// Strain rate S = (D + D^T)/2 of the step's velocity field at cell n, with
+// D_ab = d_a u_b by central differences; one-sided where one neighbour along
+// the axis is solid or outside a non-periodic axis, zero where both are
+// (hybrid collision, Sec. 2.2, Eq. (10)).  S[0..5] = xx, yy, zz, xy, xz, yz.
+template <typename R>
+__device__ __forceinline__ void fd_strain(const Nb &n, const uint8_t *__restrict__ flags, const KArgs &k, R S[6]) {
+  const R *v = static_cast<const R *>(k.vel);
+  const size_t N = (size_t)k.N;
+  R D[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int cp = n.cell + n.d[a][1], cm = n.cell + n.d[a][0];
+    const bool fp = !((n.out >> (2 * a + 1)) & 1u) && (flags[cp] & FL_FLUID);
+    const bool fm = !((n.out >> (2 * a)) & 1u) && (flags[cm] & FL_FLUID);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const R uc = v[(size_t)b * N + n.cell];
+      if (fp && fm) D[a][b] = R(0.5) * (v[(size_t)b * N + cp] - v[(size_t)b * N + cm]);
+      else if (fp) D[a][b] = v[(size_t)b * N + cp] - uc;
+      else if (fm) D[a][b] = uc - v[(size_t)b * N + cm];
+      else D[a][b] = R(0);
+    }
+  }
+  S[0] = D[0][0];
+  S[1] = D[1][1];
+  S[2] = D[2][2];
+  S[3] = R(0.5) * (D[0][1] + D[1][0]);
+  S[4] = R(0.5) * (D[0][2] + D[2][0]);
+  S[5] = R(0.5) * (D[1][2] + D[2][1]);
+}
+
 // Bulk collision on deviations g (sigma = 1): BGK with tau_eff from the
 // non-equilibrium stress, homogenized velocity u_hat = phi u, Guo forcing.
 // Opposite directions i and i+H share everything but a sign: with
@@ -124,8 +155,13 @@ __device__ __forceinline__ void lid_equilibrium(R g[Q], const KArgs &k) {
 // sum c (f - f^eq) = j - rho u = -F/2 (Guo velocity); order 2, Pi^neq; order 3,
 // the recursion u_a Pi_bc + u_b Pi_ac + u_c Pi_ab.  The third-order terms are
 // odd in c and join Qo; the outputs no longer carry c1 g_i.
-template <int Q, typename R, bool POROUS, bool RR>
-__device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
+//
+// HYB = true (with RR): the hybrid of Eq. (7) with weight k.fdw = 1 - sigma
+// of the finite-difference strain Sfd: the second-order part uses
+// sigma Pi^neq - (1 - sigma) 2 rho c_s^2 tau S^FD, the third-order part keeps
+// the factor sigma, the first-order part (-F/2) is kept whole.
+template <int Q, typename R, bool POROUS, bool RR, bool HYB = false>
+__device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k, const R *Sfd = nullptr) {
   constexpr int H = Lat<Q>::H;
   // moments from pair sums s = g_i + g_ibar (even moments) and differences d = g_i - g_ibar (odd)
   R drho = g[0], jx = R(0), jy = R(0), jz = R(0);
@@ -168,9 +204,22 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
   const R vv = vx * vx + vy * vy + vz * vz;
   const R uF = ux * Fx + uy * Fy + uz * Fz;
   if constexpr (RR) {
-    // third-order coefficients of f^eq(rho, v) + c1 f^(1): A = rho v v v + c1 A1
+    // third-order coefficients of f^eq(rho, v) + c1 f^(1): A = rho v v v + c1 sigma A1
     R A[7], A1[7], K[7];
     cube_tensor(rho, vx, vy, vz, A);
+    R sig = R(1);
+    R hxx = pxx, hyy = pyy, hzz = pzz, hxy = pxy, hxz = pxz, hyz = pyz;  // second-order coefficient
+    if constexpr (HYB) {
+      const R fw = R(k.fdw);
+      sig = R(1) - fw;
+      const R fs = fw * R(2.0 / 3.0) * rho * tau;  // (1 - sigma) 2 rho c_s^2 tau
+      hxx = sig * pxx - fs * Sfd[0];
+      hyy = sig * pyy - fs * Sfd[1];
+      hzz = sig * pzz - fs * Sfd[2];
+      hxy = sig * pxy - fs * Sfd[3];
+      hxz = sig * pxz - fs * Sfd[4];
+      hyz = sig * pyz - fs * Sfd[5];
+    }
     A1[0] = R(2) * ux * pxy + uy * pxx;
     A1[1] = R(2) * ux * pxz + uz * pxx;
     A1[2] = R(2) * uy * pxy + ux * pyy;
@@ -178,10 +227,11 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
     A1[4] = R(2) * uz * pxz + ux * pzz;
     A1[5] = R(2) * uz * pyz + uy * pzz;
     A1[6] = ux * pyz + uy * pxz + uz * pxy;
+    const R c1s = c1 * sig;
 #pragma unroll
-    for (int m = 0; m < 7; ++m) A[m] += c1 * A1[m];
+    for (int m = 0; m < 7; ++m) A[m] += c1s * A1[m];
     third_coefs<Q, R>(A, K);
-    const R tr3 = (pxx + pyy + pzz) * cs2;
+    const R tr3 = (hxx + hyy + hzz) * cs2;
     // rest: f^eq - w = w0 (drho - 3/2 rho v.v); f^(1)_0 = -9/2 w0 c_s^2 tr Pi; Guo -3 w0 u.F
     {
       const R w = R(Lat<Q>::w(0));
@@ -194,13 +244,13 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
       const R cu = dot3(cx, cy, cz, ux, uy, uz);
       const R cv = POROUS ? dot3(cx, cy, cz, vx, vy, vz) : cu;
       const R cF = dot3(cx, cy, cz, Fx, Fy, Fz);
-      R cPc = R(0);  // c . Pi . c
-      acc(cPc, cx * cx, pxx);
-      acc(cPc, cy * cy, pyy);
-      acc(cPc, cz * cz, pzz);
-      acc(cPc, cx * cy, R(2) * pxy);
-      acc(cPc, cx * cz, R(2) * pxz);
-      acc(cPc, cy * cz, R(2) * pyz);
+      R cPc = R(0);  // c . Pi . c (of the second-order coefficient)
+      acc(cPc, cx * cx, hxx);
+      acc(cPc, cy * cy, hyy);
+      acc(cPc, cz * cz, hzz);
+      acc(cPc, cx * cy, R(2) * hxy);
+      acc(cPc, cx * cz, R(2) * hxz);
+      acc(cPc, cy * cz, R(2) * hyz);
       const R P = w * (drho + rho * (R(4.5) * cv * cv - R(1.5) * vv) + c1 * R(4.5) * (cPc - tr3) +
                        c2 * (R(9) * cu * cF - R(3) * uF));
       // odd part: 3 w rho c.v + w sum_k P_k K_k + c1 (3 w c.a1, a1 = -F/2) + c2 3 w c.F
@@ -248,10 +298,10 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k) {
 // Gather, collide, scatter of one cell.  With LINKS = false the cell has no
 // solid link and every slot is the plain AA one (32-bit offsets from a
 // per-direction base); with LINKS = true slots follow the bounce-back map.
-template <int Q, typename S, bool ODD, bool POROUS, bool LINKS, bool RR>
+template <int Q, typename S, bool ODD, bool POROUS, bool LINKS, bool RR, bool HYB>
 __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename Store<S>::R *__restrict__ phi,
-                                          const KArgs &k, const Nb &n, unsigned sm, uint8_t fl, int x, int z,
-                                          int *__restrict__ errflag) {
+                                          const uint8_t *__restrict__ flags, const KArgs &k, const Nb &n,
+                                          unsigned sm, uint8_t fl, int x, int z, int *__restrict__ errflag) {
   using R = typename Store<S>::R;
   const size_t N = (size_t)k.N;
   R g[Q];
@@ -269,7 +319,9 @@ __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename St
       }
     }
     const R ph = POROUS ? phi[n.cell] : R(1);
-    if (!collide_bulk<Q, R, POROUS, RR>(g, ph, k)) atomicOr(errflag, 1);
+    R Sfd[6];
+    if constexpr (HYB) fd_strain<R>(n, flags, k, Sfd);
+    if (!collide_bulk<Q, R, POROUS, RR, HYB>(g, ph, k, Sfd)) atomicOr(errflag, 1);
   }
   fringe_blend<Q, R>(g, x, z, k);
 #pragma unroll
@@ -284,7 +336,7 @@ __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename St
   }
 }
 
-template <int Q, typename S, bool ODD, bool POROUS, bool SOLID, bool RR>
+template <int Q, typename S, bool ODD, bool POROUS, bool SOLID, bool RR, bool HYB>
 __global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                 const typename Store<S>::R *__restrict__ phi, KArgs k,
                                                 Tiles t, int *__restrict__ errflag) {
@@ -296,8 +348,8 @@ __global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8
   unsigned sm = 0;
   if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
   // cells without solid links (all but a thin layer) take the plain-address path
-  if (SOLID && ODD && sm != 0u) bulk_cell<Q, S, ODD, POROUS, true, RR>(pop, phi, k, n, sm, fl, x, z, errflag);
-  else bulk_cell<Q, S, ODD, POROUS, false, RR>(pop, phi, k, n, sm, fl, x, z, errflag);
+  if (SOLID && ODD && sm != 0u) bulk_cell<Q, S, ODD, POROUS, true, RR, HYB>(pop, phi, flags, k, n, sm, fl, x, z, errflag);
+  else bulk_cell<Q, S, ODD, POROUS, false, RR, HYB>(pop, phi, flags, k, n, sm, fl, x, z, errflag);
 }
 
 // ---------------------------------------------------------------------------
@@ -508,6 +560,29 @@ __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t
   const R om = R(1) / tau;
   const R c1 = R(1) - om, c2 = R(1) - R(0.5) * om;
   const R fd = R(-3) * rho * tau * G;  // f^(1,FD)_i = fd * w_i (c.t)(c.n)
+  // hybrid collision (sigma = 0 in the wall region): the full finite-difference
+  // strain whose wall-normal shear s = S n - (n.S.n) n (every tangential
+  // direction) is replaced by the wall law's, G/2 along t:
+  // S' = S + (e n^T + n e^T), e = (G/2) t - s; then
+  // f^(1,FD)_i = -3 w_i rho tau (c.S'.c - c_s^2 tr S')
+  R Sw[6] = {};
+  const bool full = k.fdw > 0.0;
+  if (full) {
+    fd_strain<R>(n, flags, k, Sw);
+    const R snx = Sw[0] * nx + Sw[3] * ny + Sw[4] * nz;
+    const R sny = Sw[3] * nx + Sw[1] * ny + Sw[5] * nz;
+    const R snz = Sw[4] * nx + Sw[5] * ny + Sw[2] * nz;
+    const R nSn = nx * snx + ny * sny + nz * snz;
+    const R hg = R(0.5) * G;
+    const R ex = hg * tx - (snx - nSn * nx), ey = hg * ty - (sny - nSn * ny), ez = hg * tz - (snz - nSn * nz);
+    Sw[0] += R(2) * ex * nx;
+    Sw[1] += R(2) * ey * ny;
+    Sw[2] += R(2) * ez * nz;
+    Sw[3] += ex * ny + nx * ey;
+    Sw[4] += ex * nz + nx * ez;
+    Sw[5] += ey * nz + ny * ez;
+  }
+  const R trw = (Sw[0] + Sw[1] + Sw[2]) * R(1.0 / 3.0);
   // recursive regularized model: third-order equilibrium at the modeled velocity
   R K[7] = {};
   if (k.rr) {
@@ -524,7 +599,19 @@ __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t
     const R cn = dot3(cx, cy, cz, nx, ny, nz);
     const R cF = dot3(cx, cy, cz, Fx, Fy, Fz);
     const R ge = geq_dev(w, drho, rho, cv, vv);
-    const R ffd = fd * w * ct * cn;
+    R ffd;
+    if (full) {
+      R cSc = R(0);
+      acc(cSc, cx * cx, Sw[0]);
+      acc(cSc, cy * cy, Sw[1]);
+      acc(cSc, cz * cz, Sw[2]);
+      acc(cSc, cx * cy, R(2) * Sw[3]);
+      acc(cSc, cx * cz, R(2) * Sw[4]);
+      acc(cSc, cy * cz, R(2) * Sw[5]);
+      ffd = R(-3) * w * rho * tau * (cSc - trw);
+    } else {
+      ffd = fd * w * ct * cn;
+    }
     const R guo = w * (R(3) * (cF - vF) + R(9) * cv * cF);
     g[i] = ge + c1 * ffd + c2 * guo;
     if (k.rr) g[i] += w * third_term<Q, R>(i, K);
@@ -812,8 +899,9 @@ static void launch_bulk(lbm_ctx *ctx, Tiles t) {
     kern<<<t.nblocks, BLOCK, lds_cap, ctx->stream>>>(pop, ctx->flags, phi, ctx->ka, t, ctx->errflag);
   };
   auto by_model = [&]<bool POROUS, bool SOLID>() {
-    if (ctx->ka.rr) go(k_bulk<Q, S, ODD, POROUS, SOLID, true>);
-    else go(k_bulk<Q, S, ODD, POROUS, SOLID, false>);
+    if (ctx->ka.rr && ctx->ka.fdw > 0.0) go(k_bulk<Q, S, ODD, POROUS, SOLID, true, true>);
+    else if (ctx->ka.rr) go(k_bulk<Q, S, ODD, POROUS, SOLID, true, false>);
+    else go(k_bulk<Q, S, ODD, POROUS, SOLID, false, false>);
   };
   if (ctx->porous) {
     if (ctx->has_solid) by_model.template operator()<true, true>();
@@ -831,6 +919,22 @@ int dev_step(lbm_ctx *ctx) {
     const int nw = ctx->nwall;
     const int wb = (nw + 255) / 256;
     const int nb = ctx->nwall_refwall;
+    // hybrid collision: the step's velocity field first (read by K2 and K3 at neighbours)
+    if (ctx->ka.fdw > 0.0) {
+      using R = typename Store<S>::R;
+      R *vel = (R *)ctx->vel;
+      auto go = [&]<bool ODD, bool SOLID>() {
+        k_moments<Q, S, ODD, SOLID><<<t.nblocks, BLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, nullptr,
+                                                                        vel, ctx->ka, t);
+      };
+      if (odd) {
+        if (ctx->has_solid) go.template operator()<true, true>();
+        else go.template operator()<true, false>();
+      } else {
+        if (ctx->has_solid) go.template operator()<false, true>();
+        else go.template operator()<false, false>();
+      }
+    }
     // wall records whose reference cell is itself a wall cell, before any wall cell is written
     if (nb > 0) {
       prof_begin(ctx, 0);

@@ -46,6 +46,7 @@ class Case:
     z0: float = 1.0
     lid: int = 0
     collision: int = 0  # 0 BGK, 1 recursive regularized (third order)
+    fd_weight: float = 0.0  # 1 - sigma: weight of the finite-difference strain (collision 1 only)
     mask: np.ndarray | None = None
     wall_dist: np.ndarray | None = None
     porosity: np.ndarray | None = None

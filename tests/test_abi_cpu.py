@@ -38,7 +38,8 @@ def test_workspace_bytes_and_validation():
     p16 = lbm.make_params(27, (32, 32, 32), storage=lbm.F16DEV, tau0=0.6)
     assert lbm.lbm_workspace_bytes(p16) >= 27 * 32 ** 3 * 2
     for bad in (dict(tau0=0.5), dict(tau0=float("nan")), dict(cs_smag=-1.0), dict(storage=7),
-                dict(fringe_len=99), dict(collision=2), dict(collision=-1)):
+                dict(fringe_len=99), dict(collision=2), dict(collision=-1), dict(fd_weight=0.5),
+                dict(collision=1, fd_weight=1.5), dict(collision=1, fd_weight=-0.1)):
         kw = dict(tau0=0.6)
         kw.update(bad)
         with pytest.raises(lbm.LbmError):

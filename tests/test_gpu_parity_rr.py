@@ -117,3 +117,52 @@ def test_rr_cavity_fp64(gpu):
     case = rr(I.cavity((140, 20, 18), q=19))
     _, _, rho, u, orho, ou = _run_both(gpu, case, 80, "f64")
     _check("rr cavity f64", moment_errors(rho, u, orho, ou), 1e-12)
+
+
+def hyb(case, fdw):
+    c = dataclasses.replace(case, collision=1)
+    c.fd_weight = fdw
+    return c
+
+
+@pytest.mark.parametrize("q,fdw", [(19, 0.3), (27, 1.0)])
+def test_hybrid_tgv_fp64(gpu, q, fdw):
+    """Hybrid collision (finite-difference strain weight fdw) on a periodic box."""
+    case = hyb(I.taylor_green(32, u0=0.05, q=q, tau0=0.6, cs_smag=0.1), fdw)
+    lat, orc, rho, u, orho, ou = _run_both(gpu, case, 60, "f64")
+    _check(f"hybrid tgv q={q} w={fdw} f64", moment_errors(rho, u, orho, ou), 1e-12)
+
+
+@pytest.mark.parametrize("q,fdw", [(19, 0.5), (27, 0.2)])
+def test_hybrid_channel_wall_model_fp64(gpu, q, fdw):
+    """Walls outside z with the wall model: bulk cells blend the finite-difference
+    strain, wall cells use it in full with the law's t-n component, and the
+    one-sided differences next to the walls."""
+    case = hyb(I.channel(70, 10, 9, q=q, utau=0.01, nu=1e-3, tau0=0.503, cs_smag=0.1, amp=0.01,
+                         wall_model=1), fdw)
+    _, _, rho, u, orho, ou = _run_both(gpu, case, 51, "f64")
+    _check(f"hybrid channel q={q} w={fdw} f64", moment_errors(rho, u, orho, ou), 1e-12)
+
+
+@pytest.mark.parametrize("storage,tol,steps", [("f64", 1e-12, 41), ("f32", 1e-5, 100)])
+def test_hybrid_urban_crop(gpu, storage, tol, steps):
+    case = hyb(I.urban(nx=160, ny=72, nz=48, q=27, tau0=0.5003, fringe_len=24, x_lo=16, x_hi=110,
+                       h_mean=14.0, h_max=36, fp_lo=6, fp_hi=16), 0.25)
+    _, _, rho, u, orho, ou = _run_both(gpu, case, steps, storage)
+    _check(f"hybrid urban {storage}", moment_errors(rho, u, orho, ou), tol)
+
+
+def test_hybrid_porous_cavity_fp64(gpu):
+    for case in (hyb(I.porous_channel(shape=(40, 24, 12)), 0.4), hyb(I.cavity((140, 20, 18), q=19), 0.6)):
+        _, _, rho, u, orho, ou = _run_both(gpu, case, 30, "f64")
+        _check(f"hybrid {case.name} f64", moment_errors(rho, u, orho, ou), 1e-12)
+
+
+def test_hybrid_adjoint_refused(gpu):
+    case = hyb(I.porous_channel(shape=(16, 12, 8)), 0.5)
+    lat = gpu.Lattice(case, storage="f64")
+    lam, grad = lat.new_adjoint(), lat.new_gradient()
+    gpu.lbm_adjoint_seed(lat.ctx, case.extra["planes"], lam)
+    with pytest.raises(gpu.LbmError) as e:
+        gpu.lbm_adjoint_step(lat.ctx, lam, grad)
+    assert e.value.code == gpu.EINVAL and "finite-difference" in str(e.value)

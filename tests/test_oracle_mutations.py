@@ -48,7 +48,11 @@ MUTATIONS = [
      "Ph[a][b] = sig * Pi[a][b] + p.fd_weight * (2.0 / 3.0)"),
     ("one-sided difference reversed", "else if (fp) D[a][b] = uf[(size_t)b * N + xp] - uc;",
      "else if (fp) D[a][b] = uc - uf[(size_t)b * N + xp];"),
-    ("wall t-n component", "(0.5 * G - tSn)", "(G - tSn)"),
+    ("wall-normal shear of the FD strain kept",
+     "S[a][b] = S[a][b] - (sv[a] * n[b] + n[a] * sv[b]) + 0.5 * G * (t[a] * n[b] + n[a] * t[b]);",
+     "S[a][b] = S[a][b] + 0.5 * G * (t[a] * n[b] + n[a] * t[b]);"),
+    ("wall-law shear in the hybrid wall strain", "+ 0.5 * G * (t[a] * n[b] + n[a] * t[b]);\n    } else {",
+     "+ 0.25 * G * (t[a] * n[b] + n[a] * t[b]);\n    } else {"),
     ("hybrid third-order factor dropped", "for (int i = 0; i < vs.q; ++i) t3[i] = sig * t3[i];",
      "for (int i = 0; i < vs.q; ++i) t3[i] = t3[i];"),
 ]
@@ -72,7 +76,8 @@ PIN_TESTS = [
     (pins_rr.test_rr_removes_ghost_modes, [(19,)]),
     (pins_hy.test_hybrid_fd_stress_quadratic_shear, [(19,)]),
     (pins_hy.test_hybrid_blend_and_third_moments, [(27,)]),
-    (pins_hy.test_hybrid_wall_cell_tensor, [(1.0,)]),
+    (pins_hy.test_hybrid_wall_shear_replaced, [(1.0,)]),
+    (pins_hy.test_hybrid_wall_keeps_normal_strain, [()]),
 ]
 
 

@@ -9,9 +9,10 @@ post-collision second moment follows from the collision's definition:
   sum_i c_a c_b f*_i - rho c_s^2 d_ab - rho u_a u_b
       = (1 - 1/tau) [sigma Pi^neq - (1 - sigma) 2 rho c_s^2 tau S^FD]_ab
 
-in the bulk (no force), and in a wall cell the full S^FD with its t-n
-component replaced by the wall law's G/2.  The third moments keep the factor
-sigma on the recursive part."""
+in the bulk (no force).  The third moments keep the factor
+sigma on the recursive part.  In a wall cell the wall law replaces the
+wall-normal shear of S^FD (in every tangential direction) by its own,
+(G/2)(t n^T + n t^T), and the rest of S^FD is kept."""
 import numpy as np
 import pytest
 
@@ -70,7 +71,9 @@ def test_hybrid_fd_stress_quadratic_shear(q):
 def test_hybrid_blend_and_third_moments(q):
     """sigma = 0.7 on a periodic box with u_y = a sin(2 pi x / nx) plus a
     perturbation without mass or momentum: the second moments blend Pi^neq
-    and the FD stress, the third keep sigma on the recursive part."""
+    and the FD stress, the third keep sigma on the recursive part.  In a wall cell the wall law replaces the
+wall-normal shear of S^FD (in every tangential direction) by its own,
+(G/2)(t n^T + n t^T), and the rest of S^FD is kept."""
     nx, ny, nz = 8, 3, 3
     shape = (nx, ny, nz)
     N = nx * ny * nz
@@ -112,52 +115,67 @@ def test_hybrid_blend_and_third_moments(q):
             assert abs(m - e) <= 1e-15, (cell, terms, m, e)
 
 
-@pytest.mark.parametrize("fdw", [0.0, 1.0])
-def test_hybrid_wall_cell_tensor(fdw):
-    """Wall cells on the ground of a channel carrying u_x = a + b z_c,
-    u_y = d z_c (z_c = z + 1/2): with the hybrid collision the strain is the
-    one-sided S^FD (S_xz = b/2, S_yz = d/2) with its t-n component replaced by
-    G/2; without it, only (G/2)(t n^T + n t^T)."""
+def _wall_run(fdw, u, shape, tau0=0.55):
     q = 19
+    c, w, _ = O.velocity_set(q)
+    f = _eq_state(q, shape, u)
+    nx, ny, nz = shape
+    zc = np.arange(nx * ny * nz) // (nx * ny) + 0.5
+    zdist = np.minimum(zc, nz - zc)
+    p = O.make_params(q, shape, periodic=(1, 1, 0), tau0=tau0, cs_smag=0.1, wall_model=1, collision=1,
+                      fd_weight=fdw)
+    s = O.Oracle(p, wall_dist=zdist)
+    s.set_populations(f)
+    s.step(1)
+    info = s.wall_info()
+    ground = np.flatnonzero(info["cells"] < nx * ny)
+    assert len(ground) == nx * ny
+    return _second(c, s.post_collision()), info, ground
+
+
+@pytest.mark.parametrize("fdw", [0.0, 1.0])
+def test_hybrid_wall_shear_replaced(fdw):
+    """Ground cells of a channel carrying u_x = a + b z_c, u_y = d z_c
+    (z_c = z + 1/2): the finite-difference strain has only the wall-normal
+    shear S_xz = b/2, S_yz = d/2, which the wall law replaces by
+    (G/2)(t n^T + n t^T), with or without the hybrid collision."""
     nx, ny, nz = 4, 4, 6
-    shape = (nx, ny, nz)
     N = nx * ny * nz
     zc = np.arange(N) // (nx * ny) + 0.5
     a, b, d = 0.02, 0.004, 0.002
     u = np.zeros((3, N))
     u[0] = a + b * zc
     u[1] = d * zc
-    c, w, _ = O.velocity_set(q)
-    f = _eq_state(q, shape, u)
-    zdist = np.minimum(zc, nz - zc)
-    p = O.make_params(q, shape, periodic=(1, 1, 0), tau0=0.55, cs_smag=0.1, wall_model=1, collision=1,
-                      fd_weight=fdw)
-    s = O.Oracle(p, wall_dist=zdist)
-    s.set_populations(f)
-    s.step(1)
-    fs = s.post_collision()
-    info = s.wall_info()
-    M2 = _second(c, fs)
+    M2, info, ground = _wall_run(fdw, u, (nx, ny, nz))
     ur = np.array([a + 1.5 * b, 1.5 * d, 0.0])  # reference cell of a ground cell: one step up
     t = ur / np.linalg.norm(ur)
-    n = np.array([0.0, 0.0, 1.0])
-    ground = np.flatnonzero(info["cells"] < nx * ny)
-    assert len(ground) == nx * ny
     for k in ground:
         G, tau = info["G"][k], info["tau"][k]
-        S = np.zeros((3, 3))
-        if fdw > 0:
-            S[0, 2] = S[2, 0] = 0.5 * b
-            S[1, 2] = S[2, 1] = 0.5 * d
-            tSn = t @ S @ n
-            S = S + (0.5 * G - tSn) * (np.outer(t, n) + np.outer(n, t))
-        else:
-            S = 0.5 * G * (np.outer(t, n) + np.outer(n, t))
         cell = info["cells"][k]
-        expect = (1 - 1 / tau) * (-2.0 * CS2 * tau * S)
-        # the modeled velocity has no z component, so the xz and yz moments are the stress alone
-        assert abs(M2[cell, 0, 2] - expect[0, 2]) <= 1e-15 * max(1.0, abs(expect[0, 2]) * 1e3), (k, fdw)
-        assert abs(M2[cell, 1, 2] - expect[1, 2]) <= 1e-15 * max(1.0, abs(expect[1, 2]) * 1e3), (k, fdw)
+        # the modeled velocity has no z component, so these moments are the stress alone
+        for (i, j), tn in (((0, 2), t[0]), ((1, 2), t[1])):
+            expect = (1 - 1 / tau) * (-2.0 * CS2 * tau * 0.5 * G * tn)
+            assert abs(M2[cell, i, j] - expect) <= 1e-18 + 1e-12 * abs(expect), (k, fdw, i, j)
+
+
+def test_hybrid_wall_keeps_normal_strain():
+    """With the hybrid collision the wall cell keeps the rest of the
+    finite-difference strain: u_z = h z_c gives the one-sided S_zz = h at the
+    ground, and the zz moment is rho (c_s^2 + u_z^2) + (1 - 1/tau)(-2 rho c_s^2 tau h)
+    (the modeled velocity keeps the local normal component u_z = h/2)."""
+    nx, ny, nz = 4, 4, 6
+    N = nx * ny * nz
+    zc = np.arange(N) // (nx * ny) + 0.5
+    h = 3e-4
+    u = np.zeros((3, N))
+    u[0] = 0.02 + 0.004 * zc
+    u[2] = h * zc
+    M2, info, ground = _wall_run(1.0, u, (nx, ny, nz))
+    for k in ground:
+        tau = info["tau"][k]
+        cell = info["cells"][k]
+        expect = CS2 + (0.5 * h) ** 2 + (1 - 1 / tau) * (-2.0 * CS2 * tau * h)
+        assert abs(M2[cell, 2, 2] - expect) <= 1e-15, (k, M2[cell, 2, 2], expect)
 
 
 def test_fd_weight_checked():
