@@ -202,17 +202,25 @@ def main():
     k2_ms = kms[1] / max(kcount[1], 1)
     q = lat.q
     sb = storage_bytes(storage)
+    fdw = args.fd_weight if args.collision == "rr3" else 0.0
     # algorithmic bytes of one bulk launch: every cell's flag byte, q loads and
-    # q stores for each fluid cell it updates (all fluid cells but the wall cells)
-    k2_bytes = N * 1 + (nfluid - nwall) * 2 * q * sb
+    # q stores for each fluid cell it updates (all fluid cells but the wall
+    # cells); the hybrid collision also reads the velocity field once (three
+    # compute-type values per fluid cell), which a pre-pass over the q loads
+    # of every fluid cell wrote
+    rb = 8 if storage == "f64" else 4
+    k2_bytes = N * 1 + (nfluid - nwall) * 2 * q * sb + (nfluid * 3 * rb if fdw > 0 else 0)
     achieved = k2_bytes / (k2_ms * 1e-3) / 1e9
-    step_bytes = nfluid * (2 * q * sb + 1)
+    step_bytes = nfluid * (2 * q * sb + 1) + (nfluid * (q * sb + 6 * rb) if fdw > 0 else 0)
+    # counter-measured bytes apply only to the kernel they were taken on: the
+    # same sources, workload, collision and finite-difference weight
     traffic = None
     tf = os.path.join(ROOT, "profiles", f"k_bulk_{args.workload}_traffic.json")
     if os.path.exists(tf):
         with open(tf) as fh:
             t = json.load(fh)
-        if t.get("kernel_hash") == kernel_source_hash():
+        if (t.get("kernel_hash") == kernel_source_hash() and t.get("collision") == args.collision
+                and t.get("fd_weight") == fdw):
             traffic = t.get("bytes_per_launch")
     diag = lat.diagnostics()
     out = {
@@ -231,7 +239,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "cells": N, "fluid_cells": nfluid, "wall_cells": nwall, "lattice": f"D3Q{q}",
                    "storage": storage, "collision": args.collision,
-                   "fd_weight": args.fd_weight if args.collision == "rr3" else 0.0},
+                   "fd_weight": fdw},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": "k_bulk", "avg_launch_ms": round(k2_ms, 5), "alg_bytes_per_launch": k2_bytes},
