@@ -45,6 +45,8 @@ class Params(C.Structure):
         ("lid", C.c_int),
         ("collision", C.c_int),
         ("fd_weight", C.c_double),
+        ("open_x", C.c_int),
+        ("rho_out", C.c_double),
     ]
 
 
@@ -106,7 +108,7 @@ def _ptr(a):
 
 def make_params(q, shape, periodic=(1, 1, 1), tau0=0.6, cs_smag=0.0, force=(0.0, 0.0, 0.0),
                 wall_model=0, kappa=0.41, E=9.0, fringe_len=0, u_ref=0.0, z0=1.0, lid=0,
-                collision=0, fd_weight=0.0) -> Params:
+                collision=0, fd_weight=0.0, open_x=0, rho_out=1.0) -> Params:
     p = Params()
     p.q = q
     p.nx, p.ny, p.nz = shape
@@ -117,6 +119,7 @@ def make_params(q, shape, periodic=(1, 1, 1), tau0=0.6, cs_smag=0.0, force=(0.0,
     p.fringe_len, p.u_ref, p.z0, p.lid = fringe_len, u_ref, z0, lid
     p.collision = collision
     p.fd_weight = fd_weight
+    p.open_x, p.rho_out = open_x, rho_out
     return p
 
 

@@ -59,7 +59,22 @@
  *   - wall cells: fluid cells with at least one solid link; normal from the
  *     sum of the solid links; reference cell one lattice step along the
  *     direction best aligned with the normal; stress-consistent strain
- *     G = 2 u_tau^2 / (nu + sqrt(nu^2 + 4 C_S^2 u_tau^2)).
+ *     G = 2 u_tau^2 / (nu + sqrt(nu^2 + 4 C_S^2 u_tau^2));
+ *   - open x faces (open_x = 1; Sec. 2.2.2 imposes the inflow with a
+ *     regularized local velocity condition, Sec. 3.2 closes the outlet with a
+ *     fixed local pressure condition): the fluid cells of the planes x = 0
+ *     (inlet) and x = nx - 1 (outlet) that are not lid cells replace their
+ *     pre-collision populations before the collision.  The populations that
+ *     enter through the face are unknown.  Inlet: u = (u_in(z), 0, 0)
+ *     prescribed, rho from the known populations and u.n; outlet: rho =
+ *     rho_out prescribed, the normal velocity from the known populations, the
+ *     tangential velocity zero.  The non-equilibrium of an unknown population
+ *     is that of its opposite (known) one, Pi^neq is summed over all of them,
+ *     and the cell's populations become f^eq(rho, u) + w H^(2) : Pi^neq /
+ *     (2 c_s^4); the ordinary bulk collision follows.  These cells are never
+ *     wall-modeled, links through an open face are otherwise handled like
+ *     solid links, the outlet plane is left out of the fringe, and the body
+ *     force must be zero.
  */
 #include <cmath>
 #include <cstdint>
@@ -86,6 +101,8 @@ typedef struct {
   int lid;
   int collision; /* 0: BGK (second-order equilibrium); 1: recursive regularized, third order */
   double fd_weight; /* 1 - sigma of Eq. (7): weight of the finite-difference strain (collision 1 only) */
+  int open_x;       /* 1: velocity inlet at x = 0 and pressure outlet at x = nx - 1 (non-periodic x) */
+  double rho_out;   /* density imposed at the outlet (open_x only) */
 } orc_params;
 }
 
@@ -364,7 +381,7 @@ int solve_uplus(double yplus, double start, double kappa, double E, double* uplu
   return ORC_ENEWTON;
 }
 
-enum Kind : uint8_t { K_SOLID = 0, K_BULK = 1, K_WALL = 2, K_LID = 3 };
+enum Kind : uint8_t { K_SOLID = 0, K_BULK = 1, K_WALL = 2, K_LID = 3, K_INLET = 4, K_OUTLET = 5 };
 
 /* ------------------------------------------------------------------------ */
 /* The simulation state.                                                     */
@@ -457,6 +474,18 @@ struct Sim : SimBase {
       err = "fd_weight must be in [0, 1], and above 0 only with the recursive regularized collision";
       return ORC_EINVAL;
     }
+    if (p.open_x != 0 && p.open_x != 1) {
+      err = "open_x must be 0 or 1";
+      return ORC_EINVAL;
+    }
+    if (p.open_x &&
+        (p.periodic[0] || p.nx < 3 || p.fringe_len > p.nx - 2 || p.fd_weight > 0.0 || p.force[0] != 0.0 ||
+         p.force[1] != 0.0 || p.force[2] != 0.0 || !(p.rho_out > 0.0) || !std::isfinite(p.rho_out) ||
+         !(p.z0 > 0.0) || !std::isfinite(p.u_ref))) {
+      err = "open x faces need a non-periodic x axis, nx >= 3, fringe_len <= nx - 2, no hybrid, no force, "
+            "rho_out > 0 and the inflow profile (z0 > 0, finite u_ref)";
+      return ORC_EINVAL;
+    }
     vs = make_velocity_set(p.q);
     h3 = make_h3_basis(vs);
     N = (long)p.nx * p.ny * p.nz;
@@ -473,6 +502,8 @@ struct Sim : SimBase {
       int x, y, z;
       coords(c, x, y, z);
       kind[c] = (p.lid && z == p.nz - 1) ? K_LID : K_BULK;
+      if (p.open_x && kind[c] == K_BULK && x == 0) kind[c] = K_INLET;
+      if (p.open_x && kind[c] == K_BULK && x == p.nx - 1) kind[c] = K_OUTLET;
     }
     wall_index.assign(N, -1);
     if (p.wall_model) {
@@ -640,9 +671,13 @@ struct Sim : SimBase {
    * regularized model (collision 1) keeps its Hermite reconstruction. */
   bool collide_bulk(long c, T* fo) const {
     T fi[27];
+    for (int i = 0; i < vs.q; ++i) fi[i] = f[(size_t)i * N + c];
+    return collide_populations(c, fi, fo);
+  }
+  /* The same collision of the given pre-collision populations of cell c. */
+  bool collide_populations(long c, const T* fi, T* fo) const {
     T rho(0.0), j[3] = {T(0.0), T(0.0), T(0.0)};
     for (int i = 0; i < vs.q; ++i) {
-      fi[i] = f[(size_t)i * N + c];
       rho += fi[i];
       for (int a = 0; a < 3; ++a) j[a] += double(vs.c[i][a]) * fi[i];
     }
@@ -711,6 +746,64 @@ struct Sim : SimBase {
                 (1.0 - 0.5 / tau) * guo_term(vs, i, u, p.force);
     }
     return std::isfinite(val(rho)) && val(rho) > 0.0;
+  }
+
+  /* Open-face cell (inlet or outlet): its pre-collision populations rebuilt
+   * by the regularized local condition (reading in the header).  n is the
+   * outward normal, -x at the inlet and +x at the outlet; the populations
+   * with xi.n < 0 enter through the face and are unknown. */
+  void open_reconstruct(long c, T* fr) const {
+    int x, y, z;
+    coords(c, x, y, z);
+    const bool inlet = kind[c] == K_INLET;
+    const int nx_out = inlet ? -1 : 1; /* x component of the outward normal */
+    T fi[27];
+    for (int i = 0; i < vs.q; ++i) fi[i] = f[(size_t)i * N + c];
+    /* mass and normal momentum of the known populations: sum over xi.n = 0
+     * and over the populations leaving through the face (xi.n > 0) */
+    T s_par(0.0), s_out(0.0);
+    for (int i = 0; i < vs.q; ++i) {
+      const int cn = vs.c[i][0] * nx_out;
+      if (cn == 0) s_par += fi[i];
+      else if (cn > 0) s_out += fi[i];
+    }
+    /* rho = s_par + s_out + s_in and rho u.n = s_out - s_in give
+     * rho (1 + u.n) = s_par + 2 s_out */
+    T rho, u[3];
+    if (inlet) {
+      u[0] = T(u_in(z + 0.5));
+      u[1] = u[2] = T(0.0);
+      const T un = double(nx_out) * u[0];
+      rho = (s_par + 2.0 * s_out) / (1.0 + un);
+    } else {
+      rho = T(p.rho_out);
+      const T un = (s_par + 2.0 * s_out) / rho - 1.0;
+      u[0] = double(nx_out) * un;
+      u[1] = u[2] = T(0.0);
+    }
+    T feq[27];
+    eqm(rho, u, feq);
+    /* non-equilibrium: known populations as they are, an unknown one takes
+     * that of its opposite direction */
+    T fneq[27];
+    for (int i = 0; i < vs.q; ++i) {
+      const bool unknown = vs.c[i][0] * nx_out < 0;
+      fneq[i] = unknown ? fi[vs.opp[i]] - feq[vs.opp[i]] : fi[i] - feq[i];
+    }
+    T Pi[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        Pi[a][b] = T(0.0);
+        for (int i = 0; i < vs.q; ++i) Pi[a][b] += double(vs.c[i][a] * vs.c[i][b]) * fneq[i];
+      }
+    const T trPi = Pi[0][0] + Pi[1][1] + Pi[2][2];
+    for (int i = 0; i < vs.q; ++i) {
+      T cPc(0.0);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) cPc += double(vs.c[i][a] * vs.c[i][b]) * Pi[a][b];
+      /* w_i H^(2)_i : Pi / (2 c_s^4) = 9/2 w_i (xi.Pi.xi - c_s^2 tr Pi) */
+      fr[i] = feq[i] + 4.5 * vs.w[i] * (cPc - trPi / 3.0);
+    }
   }
 
   /* Wall cell (sigma = 0): equilibrium at the modeled velocity plus the
@@ -787,10 +880,14 @@ struct Sim : SimBase {
             eqm(T(1.0), v, fo);
           } else if (kind[c] == K_WALL) {
             if (!collide_wall(c, wall_index[c], fo)) bad = 1;
+          } else if (kind[c] == K_INLET || kind[c] == K_OUTLET) {
+            T fr[27];
+            open_reconstruct(c, fr);
+            if (!collide_populations(c, fr, fo)) bad = 1;
           } else {
             if (!collide_bulk(c, fo)) bad = 1;
           }
-          if (p.fringe_len > 0 && x >= fstart) {
+          if (p.fringe_len > 0 && x >= fstart && kind[c] != K_OUTLET) {
             double s = double(x - fstart + 1) / p.fringe_len;
             double lam = s * s * (3.0 - 2.0 * s);
             T v[3] = {T(u_in(z + 0.5)), T(0.0), T(0.0)};
