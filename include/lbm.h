@@ -82,6 +82,22 @@ typedef struct {
                        * wall cells then use the full finite-difference strain
                        * with its wall-normal shear replaced by the wall law's.
                        * 0 = purely local. */
+  int open_x;         /* 1: open x faces (Sec. 2.2.2, Sec. 3.2): regularized local
+                       * velocity inlet on the plane x = 0 imposing (u_in(z), 0, 0),
+                       * the log-law profile above; fixed local pressure outlet on
+                       * x = nx-1 imposing rho_out with zero tangential velocity.
+                       * Each such fluid cell that is not a lid cell rebuilds its
+                       * pre-collision populations, then collides as a bulk cell:
+                       * inlet cells as f^eq(rho, u) plus the regularized
+                       * non-equilibrium (the unknown populations, those entering
+                       * through the face, take the non-equilibrium of their
+                       * opposites); outlet cells as f^eq(rho_out, u) with the
+                       * normal velocity from the known populations.  Needs a
+                       * non-periodic x axis, nx >= 3, fringe_len <= nx - 2 (the
+                       * outlet plane is left out of the fringe), no force, no
+                       * hybrid (fd_weight 0), z0 > 0; these cells are never
+                       * wall-modeled.  0 = off. */
+  double rho_out;     /* outlet density, > 0 (open_x only) */
   void *stream;       /* hipStream_t for all device work (NULL = null stream) */
 } lbm_params;
 
@@ -188,7 +204,8 @@ int lbm_adjoint_from_natural(lbm_ctx *ctx, const void *natural, void *lambda);
  * checkpoint to T-1.  *J receives the objective at step T and *nforward the
  * forward steps taken (lbm_revolve_cost(T, nsnap) + 1 + that re-advance; T
  * exactly when nsnap > T).  On return the context holds the state of step 0
- * again.  Synchronises.  Not available with the wall model. */
+ * again.  Synchronises.  Not available with the wall model, the hybrid
+ * collision or open x faces. */
 int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
                  void *grad_phi, double *J, long long *nforward);
 

@@ -66,12 +66,15 @@
  *     (inlet) and x = nx - 1 (outlet) that are not lid cells replace their
  *     pre-collision populations before the collision.  The populations that
  *     enter through the face are unknown.  Inlet: u = (u_in(z), 0, 0)
- *     prescribed, rho from the known populations and u.n; outlet: rho =
- *     rho_out prescribed, the normal velocity from the known populations, the
- *     tangential velocity zero.  The non-equilibrium of an unknown population
- *     is that of its opposite (known) one, Pi^neq is summed over all of them,
- *     and the cell's populations become f^eq(rho, u) + w H^(2) : Pi^neq /
- *     (2 c_s^4); the ordinary bulk collision follows.  These cells are never
+ *     prescribed, rho from the known populations and u.n, and (regularized)
+ *     the non-equilibrium of an unknown population is that of its opposite
+ *     (known) one, Pi^neq is summed over all of them, and the cell's
+ *     populations become f^eq(rho, u) + w H^(2) : Pi^neq / (2 c_s^4).
+ *     Outlet: rho = rho_out prescribed, the normal velocity from the known
+ *     populations, the tangential velocity zero, and the populations become
+ *     f^eq(rho_out, u) (no non-equilibrium: rebuilt from the arriving
+ *     populations it makes the outlet unstable as tau approaches 1/2).  The
+ *     ordinary bulk collision follows.  These cells are never
  *     wall-modeled, links through an open face are otherwise handled like
  *     solid links, the outlet plane is left out of the fringe, and the body
  *     force must be zero.
@@ -783,8 +786,15 @@ struct Sim : SimBase {
     }
     T feq[27];
     eqm(rho, u, feq);
-    /* non-equilibrium: known populations as they are, an unknown one takes
-     * that of its opposite direction */
+    if (!inlet) {
+      /* the outlet holds the equilibrium at (rho_out, u): a non-equilibrium
+       * rebuilt there from the arriving populations feeds the over-relaxed
+       * (tau near 1/2) non-equilibrium back through the face and grows */
+      for (int i = 0; i < vs.q; ++i) fr[i] = feq[i];
+      return;
+    }
+    /* inlet non-equilibrium: known populations as they are, an unknown one
+     * takes that of its opposite direction */
     T fneq[27];
     for (int i = 0; i < vs.q; ++i) {
       const bool unknown = vs.c[i][0] * nx_out < 0;

@@ -49,6 +49,8 @@ class Params(C.Structure):
         ("lid", C.c_int),
         ("collision", C.c_int),
         ("fd_weight", C.c_double),
+        ("open_x", C.c_int),
+        ("rho_out", C.c_double),
         ("stream", C.c_void_p),
     ]
 
@@ -164,7 +166,7 @@ def _check(ctx, rc):
 
 def make_params(q, shape, periodic=(1, 1, 1), storage=F64, tau0=0.6, cs_smag=0.0, force=(0.0, 0.0, 0.0),
                 wall_model=0, kappa=0.41, E=9.0, fringe_len=0, u_ref=0.0, z0=1.0, lid=0, collision=0,
-                fd_weight=0.0, stream=None) -> Params:
+                fd_weight=0.0, open_x=0, rho_out=1.0, stream=None) -> Params:
     p = Params()
     p.lattice = q
     p.nx, p.ny, p.nz = shape
@@ -176,6 +178,7 @@ def make_params(q, shape, periodic=(1, 1, 1), storage=F64, tau0=0.6, cs_smag=0.0
     p.fringe_len, p.u_ref, p.z0, p.lid = fringe_len, u_ref, z0, lid
     p.collision = COLLISION_NAMES.get(collision, collision) if isinstance(collision, str) else collision
     p.fd_weight = fd_weight
+    p.open_x, p.rho_out = int(open_x), rho_out
     p.stream = stream
     return p
 
@@ -374,6 +377,7 @@ class Lattice:
                              cs_smag=case.cs_smag, force=case.force, wall_model=case.wall_model, kappa=case.kappa,
                              E=case.E, fringe_len=case.fringe_len, u_ref=case.u_ref, z0=case.z0, lid=case.lid,
                              collision=getattr(case, "collision", 0), fd_weight=getattr(case, "fd_weight", 0.0),
+                             open_x=getattr(case, "open_x", 0), rho_out=getattr(case, "rho_out", 1.0),
                              stream=stream.cuda_stream)
         porous = case.porosity is not None
         nbytes = lbm_workspace_bytes(self.p, case.mask, porous)

@@ -93,6 +93,17 @@ bool params_ok(const lbm_params *p, std::string &msg) {
     msg = "fd_weight must be in [0, 1], and above 0 only with LBM_RR3";
     return false;
   }
+  if (p->open_x != 0 && p->open_x != 1) {
+    msg = "open_x must be 0 or 1";
+    return false;
+  }
+  if (p->open_x && (p->periodic[0] || p->nx < 3 || p->fringe_len > p->nx - 2 || p->fd_weight > 0.0 ||
+                    p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0 || !(p->rho_out > 0.0) ||
+                    !std::isfinite(p->rho_out) || !(p->z0 > 0.0) || !std::isfinite(p->u_ref))) {
+    msg = "open x faces need a non-periodic x axis, nx >= 3, fringe_len <= nx - 2, no hybrid, no force, "
+          "rho_out > 0 and the inflow profile (z0 > 0, finite u_ref)";
+    return false;
+  }
   return true;
 }
 
@@ -249,6 +260,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   ctx->porous = porosity != nullptr;
   ctx->has_solid = g.has_solid;
   ctx->has_lid = g.has_lid;
+  ctx->has_open = g.has_open;
   char *base = (char *)workspace;
   ctx->pop = base + L.pop;
   ctx->flags = (uint8_t *)(base + L.flags);
@@ -285,9 +297,11 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   k.rr = p->collision == LBM_RR3 ? 1 : 0;
   k.fdw = p->fd_weight;
   k.vel = p->fd_weight > 0.0 ? ctx->vel : nullptr;
+  k.open_x = p->open_x;
+  k.rho_out = p->open_x ? p->rho_out : 1.0;
   // inflow profile u_in(z) and fringe weights lambda(x)
   std::vector<double> tab((size_t)p->nz + p->nx, 0.0);
-  if (p->fringe_len > 0 || p->lid) {
+  if (p->fringe_len > 0 || p->lid || p->open_x) {
     const double ztop = p->nz - 0.5;
     for (int z = 0; z < p->nz; ++z)
       tab[z] = p->u_ref * std::log(1.0 + (z + 0.5) / p->z0) / std::log(1.0 + ztop / p->z0);
@@ -484,6 +498,7 @@ int lbm_adjoint_step(lbm_ctx *ctx, void *lambda, void *grad_phi) {
   if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
   if (ctx->ka.fdw > 0.0)
     return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the finite-difference strain");
+  if (ctx->has_open) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the open x faces");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   return dev_adjoint_step(ctx, lambda, grad_phi);
@@ -511,6 +526,7 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
   if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
   if (ctx->ka.fdw > 0.0)
     return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the finite-difference strain");
+  if (ctx->has_open) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the open x faces");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   const size_t sb = lbm_state_bytes(ctx);

@@ -111,7 +111,7 @@ int build(const lbm_params &p, const uint8_t *mask, Geometry &g, std::string &ms
   const int nz = p.nz;
   std::vector<std::vector<int>> wc(nz), wr(nz);
   std::vector<std::vector<double>> wn(nz);
-  std::vector<char> any_solid(nz, 0), any_lid(nz, 0);
+  std::vector<char> any_solid(nz, 0), any_lid(nz, 0), any_open(nz, 0);
   parallel_slabs(nz, [&](int z0, int z1) {
     for (int z = z0; z < z1; ++z)
       for (int y = 0; y < p.ny; ++y)
@@ -130,7 +130,13 @@ int build(const lbm_params &p, const uint8_t *mask, Geometry &g, std::string &ms
             fl |= FL_LID;
             any_lid[z] = 1;
           }
-          if (p.wall_model && near && !lid && (s[0] || s[1] || s[2])) {
+          // open x faces: inlet / outlet cells (a lid cell stays a lid cell)
+          const bool open = p.open_x && !lid && (x == 0 || x == p.nx - 1);
+          if (open) {
+            fl |= x == 0 ? FL_INLET : FL_OUTLET;
+            any_open[z] = 1;
+          }
+          if (p.wall_model && near && !lid && !open && (s[0] || s[1] || s[2])) {
             fl |= FL_WALL;
             const int k = best_direction<Q>(s);
             long long r = b.nb(x, y, z, Lat<Q>::c(k, 0), Lat<Q>::c(k, 1), Lat<Q>::c(k, 2));
@@ -155,12 +161,14 @@ int build(const lbm_params &p, const uint8_t *mask, Geometry &g, std::string &ms
   g.wnorm.reserve(3 * (size_t)total);
   g.has_solid = false;
   g.has_lid = false;
+  g.has_open = false;
   for (int z = 0; z < nz; ++z) {
     g.wcell.insert(g.wcell.end(), wc[z].begin(), wc[z].end());
     g.wref.insert(g.wref.end(), wr[z].begin(), wr[z].end());
     g.wnorm.insert(g.wnorm.end(), wn[z].begin(), wn[z].end());
     g.has_solid = g.has_solid || any_solid[z];
     g.has_lid = g.has_lid || any_lid[z];
+    g.has_open = g.has_open || any_open[z];
   }
   (void)msg;
   return LBM_OK;

@@ -19,7 +19,9 @@ enum : uint8_t {
   FL_FLUID = 1,  // carries populations
   FL_NEAR = 2,   // at least one link to a solid cell or outside a non-periodic axis
   FL_WALL = 4,   // wall-modeled cell (reconstruction collision, wall kernel)
-  FL_LID = 8     // top-lid cell (inflow equilibrium)
+  FL_LID = 8,    // top-lid cell (inflow equilibrium)
+  FL_INLET = 16, // open-face velocity inlet cell (plane x = 0), open-face kernel
+  FL_OUTLET = 32 // open-face pressure outlet cell (plane x = nx - 1), open-face kernel
 };
 
 // Number of doubles per wall record (structure of arrays, nwall entries each).
@@ -48,6 +50,8 @@ struct KArgs {
   double u_lid;      // lid velocity (x component)
   int rr;            // 1: recursive regularized collision (third order), 0: BGK
   double fdw;        // weight of the finite-difference strain (1 - sigma), 0 = local only
+  int open_x;        // 1: inlet / outlet on the x faces
+  double rho_out;    // outlet density
   const void *vel;   // [3][N] velocity field of the current step, compute type (fdw > 0)
   const void *uin;   // [nz] fringe inflow profile, compute type
   const void *lam;   // [nx] fringe blend weight, compute type (0 before the fringe)
@@ -95,6 +99,7 @@ struct lbm_ctx {
   bool porous = false;
   bool has_solid = false;  // some cell has a solid link (bounce-back needed)
   bool has_lid = false;
+  bool has_open = false;   // some cell is an inlet or outlet cell
   // device regions carved from the caller's workspace
   void *pop = nullptr;        // [q][N] stored deviations
   uint8_t *flags = nullptr;   // [N]
@@ -127,6 +132,7 @@ struct Geometry {
   std::vector<double> wnorm;   // [3 * nwall]
   bool has_solid = false;
   bool has_lid = false;
+  bool has_open = false;
 };
 // Builds flags and the wall list; returns LBM_OK or an error code with msg.
 int build_geometry(const lbm_params &p, const uint8_t *mask, Geometry &g, std::string &msg);

@@ -344,12 +344,138 @@ __global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8
   if (!tile_xyz(k, t, blockIdx.x, x, y, z)) return;
   const Nb n = make_nb(x, y, z, k);
   const uint8_t fl = flags[n.cell];
-  if (!(fl & FL_FLUID) || (fl & FL_WALL)) return;
+  // wall cells and open-face cells have kernels of their own
+  if (!(fl & FL_FLUID) || (fl & (FL_WALL | FL_INLET | FL_OUTLET))) return;
   unsigned sm = 0;
   if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
   // cells without solid links (all but a thin layer) take the plain-address path
   if (SOLID && ODD && sm != 0u) bulk_cell<Q, S, ODD, POROUS, true, RR, HYB>(pop, phi, flags, k, n, sm, fl, x, z, errflag);
   else bulk_cell<Q, S, ODD, POROUS, false, RR, HYB>(pop, phi, flags, k, n, sm, fl, x, z, errflag);
+}
+
+// ---------------------------------------------------------------------------
+// Open x faces (Sec. 2.2.2: regularized local velocity inlet; Sec. 3.2: fixed
+// local pressure outlet).  The pre-collision deviations g of an inlet
+// (x = 0) or outlet (x = nx - 1) cell are rebuilt in place:
+//  - with n the outward normal (-x at the inlet, +x at the outlet), the
+//    populations with c.n < 0 enter through the face and are unknown;
+//  - rho (1 + u.n) = s_0 + 2 s_+, where s_0 sums the populations with c.n = 0
+//    and s_+ those with c.n > 0 (in deviations: 1 + G_0 + 2 G_+, since their
+//    weights sum to 2/3 and 1/6);
+//  - inlet: u = (u_in(z), 0, 0), rho from that relation; outlet: rho =
+//    rho_out, u.n from it, no tangential velocity;
+//  - inlet (regularized): the non-equilibrium h = g - g^eq of an unknown
+//    population is that of its opposite, Pi = sum c c h, and
+//    g = g^eq + 9/2 w (c.Pi.c - tr Pi/3);
+//  - outlet: g = g^eq.  A non-equilibrium rebuilt there from the arriving
+//    populations feeds the over-relaxed (tau near 1/2) non-equilibrium back
+//    through the face: perturbations then grow without bound at small
+//    viscosity, while the equilibrium outlet keeps them at their size.
+// The velocity is along x, so the third-order equilibrium terms vanish on
+// D3Q19 and D3Q27 (no xxx component) and one equilibrium serves both models.
+// ---------------------------------------------------------------------------
+template <int Q, typename R>
+__device__ __forceinline__ void open_rebuild(R g[Q], bool outlet, int z, const KArgs &k) {
+  constexpr int H = (Q - 1) / 2;
+  const int nxo = outlet ? 1 : -1;  // x component of the outward normal
+  R gpar = g[0], gout = R(0);
+#pragma unroll
+  for (int i = 1; i <= H; ++i) {
+    const int cx = Lat<Q>::c(i, 0);
+    if (cx == 0) {
+      gpar += g[i] + g[i + H];
+    } else {
+      gout += cx * nxo > 0 ? g[i] : g[i + H];  // the member of the pair that leaves through the face
+    }
+  }
+  const R m = gpar + R(2) * gout;  // s_0 + 2 s_+ - 1
+  R drho, rho, ux;
+  if (outlet) {
+    drho = R(k.rho_out - 1.0);
+    rho = R(1) + drho;
+    ux = (m - drho) / rho;  // u.n with n = +x
+  } else {
+    ux = static_cast<const R *>(k.uin)[z];
+    const R un = -ux;
+    drho = (m - un) / (R(1) + un);
+    rho = R(1) + drho;
+  }
+  const R uu = ux * ux;
+  R geq[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R cu = R(Lat<Q>::c(i, 0)) * ux;
+    geq[i] = R(Lat<Q>::w(i)) * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+  }
+  if (outlet) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = geq[i];
+    return;
+  }
+  R pxx = R(0), pyy = R(0), pzz = R(0), pxy = R(0), pxz = R(0), pyz = R(0);
+#pragma unroll
+  for (int i = 1; i <= H; ++i) {
+    const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+    R hs;  // h_i + h_ibar
+    if (cx == 0) {
+      hs = (g[i] - geq[i]) + (g[i + H] - geq[i + H]);
+    } else {
+      const int kn = cx * nxo > 0 ? i : i + H;  // the known member of the pair
+      hs = R(2) * (g[kn] - geq[kn]);
+    }
+    acc(pxx, cx * cx, hs);
+    acc(pyy, cy * cy, hs);
+    acc(pzz, cz * cz, hs);
+    acc(pxy, cx * cy, hs);
+    acc(pxz, cx * cz, hs);
+    acc(pyz, cy * cz, hs);
+  }
+  const R tr3 = (pxx + pyy + pzz) * R(1.0 / 3.0);
+  g[0] = geq[0] - R(4.5) * R(Lat<Q>::w(0)) * tr3;
+#pragma unroll
+  for (int i = 1; i <= H; ++i) {
+    const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+    R cPc = R(0);
+    acc(cPc, cx * cx, pxx);
+    acc(cPc, cy * cy, pyy);
+    acc(cPc, cz * cz, pzz);
+    acc(cPc, cx * cy, R(2) * pxy);
+    acc(cPc, cx * cz, R(2) * pxz);
+    acc(cPc, cy * cz, R(2) * pyz);
+    const R r = R(4.5) * R(Lat<Q>::w(i)) * (cPc - tr3);
+    g[i] = geq[i] + r;
+    g[i + H] = geq[i + H] + r;
+  }
+}
+
+// One thread per cell of the two open planes: threads [0, ny nz) take the
+// inlet plane, the next ny nz the outlet plane.  Gather through the AA map
+// (links through the face read as bounce-back, like any outside link),
+// rebuild, bulk collision, scatter.  No fringe: the inlet lies before it and
+// the outlet plane is left out of it.
+template <int Q, typename S, bool ODD, bool POROUS, bool RR>
+__global__ __launch_bounds__(256) void k_open(S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                              const typename Store<S>::R *__restrict__ phi, KArgs k,
+                                              int *__restrict__ errflag) {
+  using R = typename Store<S>::R;
+  const int face = k.ny * k.nz;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * face) return;
+  const bool outlet = t >= face;
+  const int r = outlet ? t - face : t;
+  const int y = r % k.ny, z = r / k.ny;
+  const Nb n = make_nb(outlet ? k.nx - 1 : 0, y, z, k);
+  if (!(flags[n.cell] & (outlet ? FL_OUTLET : FL_INLET))) return;
+  const unsigned sm = ODD ? solid_mask<Q>(n, flags) : 0u;
+  const size_t N = (size_t)k.N;
+  R g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+  open_rebuild<Q, R>(g, outlet, z, k);
+  const R ph = POROUS ? phi[n.cell] : R(1);
+  if (!collide_bulk<Q, R, POROUS, RR>(g, ph, k)) atomicOr(errflag, 1);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) Store<S>::st(pop + write_slot<Q, ODD>(n, sm, i, N), g[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -912,6 +1038,22 @@ static void launch_bulk(lbm_ctx *ctx, Tiles t) {
   }
 }
 
+template <int Q, typename S, bool ODD>
+static void launch_open(lbm_ctx *ctx) {
+  using R = typename Store<S>::R;
+  const int nb = (2 * ctx->ka.ny * ctx->ka.nz + 255) / 256;
+  S *pop = (S *)ctx->pop;
+  const R *phi = (const R *)ctx->phi;
+  auto go = [&](auto kern) { kern<<<nb, 256, 0, ctx->stream>>>(pop, ctx->flags, phi, ctx->ka, ctx->errflag); };
+  if (ctx->porous) {
+    if (ctx->ka.rr) go(k_open<Q, S, ODD, true, true>);
+    else go(k_open<Q, S, ODD, true, false>);
+  } else {
+    if (ctx->ka.rr) go(k_open<Q, S, ODD, false, true>);
+    else go(k_open<Q, S, ODD, false, false>);
+  }
+}
+
 int dev_step(lbm_ctx *ctx) {
   const Tiles t = tiles_of(ctx->ka);
   const bool odd = (ctx->steps & 1) != 0;
@@ -959,6 +1101,11 @@ int dev_step(lbm_ctx *ctx) {
         k_wall<Q, S, false><<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wref,
                                                          ctx->wrefwall, ctx->wrec, nw, ctx->ka, ctx->errflag);
       prof_end(ctx, 2);
+    }
+    // open x faces (they may be reference cells of wall records, so after K1/K3)
+    if (ctx->has_open) {
+      if (odd) launch_open<Q, S, true>(ctx);
+      else launch_open<Q, S, false>(ctx);
     }
     prof_begin(ctx, 1);
     if (odd) launch_bulk<Q, S, true>(ctx, t);

@@ -47,6 +47,8 @@ class Case:
     lid: int = 0
     collision: int = 0  # 0 BGK, 1 recursive regularized (third order)
     fd_weight: float = 0.0  # 1 - sigma: weight of the finite-difference strain (collision 1 only)
+    open_x: int = 0  # 1: velocity inlet at x = 0, pressure outlet at x = nx - 1 (x not periodic)
+    rho_out: float = 1.0  # outlet density (open_x only)
     mask: np.ndarray | None = None
     wall_dist: np.ndarray | None = None
     porosity: np.ndarray | None = None
@@ -201,10 +203,12 @@ def urban(nx: int = 768, ny: int = 768, nz: int = 256, q: int = 27, seed_offset:
           u_ref: float = 0.08, tau0: float = 0.5003, cs_smag: float = 0.2, fringe_len: int = 64,
           with_wall_dist: bool = True, x_lo: int = 64, x_hi: int | None = None,
           h_mean: float = 40.0, h_max: int = 192, fp_lo: int = 8, fp_hi: int = 40,
-          host_fields: bool = True) -> Case:
+          host_fields: bool = True, open_x: bool = False) -> Case:
     """Synthetic urban canopy: random buildings on a wall-modeled ground,
     periodic x with a fringe over the last ``fringe_len`` planes, periodic y,
-    lid layer on top; initial velocity u_ref ln(1 + z_c/z0)/ln(1 + z_top/z0)
+    lid layer on top (with ``open_x``: a velocity inlet at x = 0 and a
+    pressure outlet at x = nx - 1 instead of the periodic x axis, the fringe
+    kept before the outlet; the wall distance still treats x as unbounded); initial velocity u_ref ln(1 + z_c/z0)/ln(1 + z_top/z0)
     in x (z_c = z + 1/2, z_top = nz - 1/2, z0 = 1) in fluid cells.
 
     C_S defaults to 0.2: with the BGK collision, nu = 1e-4 and wall-modeled
@@ -223,9 +227,10 @@ def urban(nx: int = 768, ny: int = 768, nz: int = 256, q: int = 27, seed_offset:
         u = np.zeros((3, N))
         u[0] = np.repeat(log_profile(nz, u_ref, z0), nx * ny) * mask
     wd = voxel_wall_distance(mask, (nx, ny, nz), (1, 1, 0)) if with_wall_dist else None
-    return Case(name=f"urban{nx}x{ny}x{nz}", q=q, shape=(nx, ny, nz), periodic=(1, 1, 0), tau0=tau0,
-                cs_smag=cs_smag, wall_model=1, fringe_len=fringe_len, u_ref=u_ref, z0=z0, lid=1,
-                mask=mask, wall_dist=wd, rho0=None, u0=u)
+    return Case(name=f"urban{nx}x{ny}x{nz}" + ("_open" if open_x else ""), q=q, shape=(nx, ny, nz),
+                periodic=(0, 1, 0) if open_x else (1, 1, 0), tau0=tau0, cs_smag=cs_smag, wall_model=1,
+                fringe_len=fringe_len, u_ref=u_ref, z0=z0, lid=1, open_x=int(open_x), mask=mask, wall_dist=wd,
+                rho0=None, u0=u)
 
 
 def log_profile(nz: int, u_ref: float, z0: float = 1.0) -> np.ndarray:

@@ -64,6 +64,32 @@ def test_wall_cells_counted_in_workspace():
     assert diff >= nwall * (2 * 4 + 12 * 8)
 
 
+def test_open_x_validation_and_wall_cells():
+    """Open x faces: the same constraints as the oracle's, and the cells of
+    the two planes are never wall-modeled (the wall list shrinks by exactly
+    the ground cells on those planes, counted through the workspace size)."""
+    ok = dict(periodic=(0, 1, 0), tau0=0.6, u_ref=0.05, z0=1.0, open_x=1, rho_out=1.0)
+    assert lbm.lbm_workspace_bytes(lbm.make_params(19, (16, 8, 10), **ok)) > 0
+    for bad in (dict(periodic=(1, 1, 0)), dict(force=(1e-6, 0.0, 0.0)), dict(collision=1, fd_weight=0.3),
+                dict(fringe_len=15), dict(rho_out=0.0), dict(rho_out=float("inf")), dict(open_x=2),
+                dict(z0=0.0)):
+        kw = dict(ok)
+        kw.update(bad)
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_workspace_bytes(lbm.make_params(19, (16, 8, 10), **kw))
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_workspace_bytes(lbm.make_params(19, (2, 8, 10), **ok))
+    # walls outside z and (closed) outside x: with the wall model every boundary
+    # cell of the closed box is a wall cell, N - 14*8*8 = 384 of them; with open
+    # x faces only the z walls between the faces remain, 2*14*8 = 224
+    shape = (16, 8, 10)
+    common = dict(periodic=(0, 1, 0), storage=lbm.F32DEV, tau0=0.6, u_ref=0.05, z0=1.0, wall_model=1)
+    n_open = lbm.lbm_workspace_bytes(lbm.make_params(27, shape, open_x=1, **common))
+    n_closed = lbm.lbm_workspace_bytes(lbm.make_params(27, shape, open_x=0, **common))
+    per_wall = 2 * 4 + 12 * 8  # cell and reference indices, FP64 record
+    assert 160 * per_wall <= n_closed - n_open <= 160 * (per_wall + 8) + 4096
+
+
 def _beta(s, t):
     return math.comb(s + t, s)
 

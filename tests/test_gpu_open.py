@@ -1,0 +1,117 @@
+"""Parity of the open x faces (regularized velocity inlet, fixed-pressure
+outlet; Sec. 2.2.2, Sec. 3.2) of the HIP path with the FP64 oracle, through
+the C ABI.  Same bars as the other parity tests: FP64 storage within 1e-12
+of the oracle (density and velocity relative to the oracle field's max-norm,
+rho - 1 within 1e-10 of its own); FP32 within 1e-5 after 100 steps.  The
+cases cover the open-face kernel at both parities, with and without
+porosity, with both collision models, next to wall-modeled ground and
+buildings (whose reference cells may lie on the inlet plane), the fringe
+before the outlet and the lid above both faces."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2506_21804_amd import inputs as I
+from gpu_helpers import announce, moment_errors, oracle_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_both(lbm, case, steps, storage):
+    announce(f"open {case.name} q={case.q} storage={storage} collision={case.collision} steps={steps}")
+    lat = lbm.Lattice(case, storage=storage, wall_dist="case" if case.wall_dist is not None else None)
+    lat.step(steps)
+    rho, u = lat.moments()
+    orc = oracle_for(case, steps, wall_dist=case.wall_dist)
+    orho, ou = orc.moments()
+    return lat, rho.cpu().numpy().astype(np.float64), u.cpu().numpy().astype(np.float64), orho, ou
+
+
+def _check(msg, errs, tol):
+    e_rho, e_u, e_drho = errs
+    announce(f"{msg}: rho {e_rho:.3e} u {e_u:.3e} drho {e_drho:.3e}")
+    assert e_rho <= tol and e_u <= tol, msg
+    if tol <= 1e-12:
+        assert e_drho <= 1e-10, msg
+
+
+def _stream(q, shape, U, collision=0):
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    u0 = np.zeros((3, N))
+    u0[0] = U
+    return I.Case(name=f"stream{nx}x{ny}x{nz}", q=q, shape=shape, periodic=(0, 1, 1), tau0=0.6, cs_smag=0.1,
+                  u_ref=U, z0=1.0, collision=collision, open_x=1, rho_out=1.0, u0=u0)
+
+
+@pytest.mark.parametrize("q,collision", [(19, 0), (27, 1)])
+def test_open_uniform_stream(gpu, q, collision):
+    """nz = 1: the inflow profile is the constant u_ref, and the stream between
+    the faces stays uniform; the smallest box (nx = 3) has one interior plane."""
+    for shape in ((12, 3, 1), (3, 5, 1)):
+        case = _stream(q, shape, 0.04, collision)
+        lat, rho, u, orho, ou = _run_both(gpu, case, 41, "f64")
+        _check(f"stream {shape} q={q} f64", moment_errors(rho, u, orho, ou), 1e-12)
+        x = np.arange(case.ncells) % shape[0]
+        inner = (x > 0) & (x < shape[0] - 1)
+        np.testing.assert_allclose(rho[inner], 1.0, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(u[0, inner], 0.04, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("storage,tol,steps", [("f64", 1e-12, 301), ("f32", 1e-5, 100)])
+def test_open_laminar_channel(gpu, storage, tol, steps):
+    """Log-law inlet, pressure outlet, bounce-back walls outside z (no wall
+    model): the developing laminar channel of the oracle's Poiseuille pin."""
+    nx, ny, nz = 40, 1, 8
+    case = I.Case(name="openchannel", q=19, shape=(nx, ny, nz), periodic=(0, 1, 0), tau0=0.8, cs_smag=0.0,
+                  u_ref=0.02, z0=1.0, open_x=1, rho_out=1.0)
+    _, rho, u, orho, ou = _run_both(gpu, case, steps, storage)
+    _check(f"open channel {storage}", moment_errors(rho, u, orho, ou), tol)
+
+
+def _urban_open(q=27, collision=0):
+    case = I.urban(nx=160, ny=72, nz=48, q=q, tau0=0.5003, fringe_len=24, x_lo=16, x_hi=110, h_mean=14.0,
+                   h_max=36, fp_lo=6, fp_hi=16, open_x=True)
+    return dataclasses.replace(case, collision=collision)
+
+
+@pytest.mark.parametrize("collision,storage,tol,steps", [(0, "f64", 1e-12, 41), (1, "f64", 1e-12, 40),
+                                                         (0, "f32", 1e-5, 100), (1, "f32", 1e-5, 100)])
+def test_open_urban_crop(gpu, collision, storage, tol, steps):
+    """Buildings on a wall-modeled ground, fringe before the outlet, lid on
+    top, inlet and outlet planes; the ground's wall cells next to the inlet
+    take reference cells on the inlet plane."""
+    case = _urban_open(collision=collision)
+    _, rho, u, orho, ou = _run_both(gpu, case, steps, storage)
+    _check(f"open urban collision={collision} {storage}", moment_errors(rho, u, orho, ou), tol)
+
+
+def test_open_urban_fp16(gpu):
+    """FP16 deviation storage: reported against the oracle with a loose bound."""
+    case = _urban_open()
+    _, rho, u, orho, ou = _run_both(gpu, case, 100, "f16")
+    e_rho, e_u, _ = moment_errors(rho, u, orho, ou)
+    announce(f"open urban f16: rho {e_rho:.3e} u {e_u:.3e}")
+    assert e_rho < 5e-3 and e_u < 5e-2
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_open_ragged_porous(gpu, q):
+    """A ragged box (x and y not multiples of the tiles) with a porosity field,
+    walls outside z and a uniform start: the porous open-face kernel."""
+    case = I.porous_channel(shape=(131, 5, 7), q=q)
+    case = dataclasses.replace(case, name="porous_open", periodic=(0, 1, 0), force=(0.0, 0.0, 0.0), open_x=1,
+                               rho_out=1.002, u_ref=0.05, z0=1.0)
+    _, rho, u, orho, ou = _run_both(gpu, case, 33, "f64")
+    _check(f"open porous q={q} f64", moment_errors(rho, u, orho, ou), 1e-12)
+
+
+def test_open_adjoint_refused(gpu):
+    case = _stream(19, (12, 3, 4), 0.04)
+    lat = gpu.Lattice(case, storage="f64")
+    lam, grad = lat.new_adjoint(), lat.new_gradient()
+    gpu.lbm_adjoint_seed(lat.ctx, (2, 9), lam)
+    with pytest.raises(gpu.LbmError) as e:
+        gpu.lbm_adjoint_step(lat.ctx, lam, grad)
+    assert e.value.code == gpu.EINVAL and "open x faces" in str(e.value)

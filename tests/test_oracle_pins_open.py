@@ -2,10 +2,15 @@
 (Sec. 2.2.2, last sentence) and the fixed local pressure outlet (Sec. 3.2).
 
 - Exactness: on a state that is exactly regularized, f = f^eq(rho, u) +
-  w H^(2) : Pi / (2 c_s^4), with the prescribed velocity (inlet) or density
-  (outlet), the condition recovers the whole state from its known
-  populations, whatever the unknown ones hold. The cell must then collide
-  exactly like an interior cell that holds the complete state.
+  w H^(2) : Pi / (2 c_s^4), the inlet (velocity prescribed) recovers the
+  whole state from its known populations, whatever the unknown ones hold,
+  and must collide exactly like an interior cell that holds the complete
+  state. The outlet (density prescribed) recovers the normal velocity exactly
+  and holds f^eq(rho_out, u).
+- Stability: a slightly perturbed uniform stream at tau0 - 1/2 = 3e-4
+  (nearly inviscid, no Smagorinsky) keeps its perturbation at its size. A
+  regularized outlet fails this: it grows the perturbation by orders of
+  magnitude and diverges within 400 steps.
 - Invariance: a uniform stream f^eq(1, U x) between an inlet imposing U and
   an outlet imposing rho = 1 stays exactly uniform.
 - The outlet plane is left out of the fringe; the planes before it are
@@ -51,6 +56,7 @@ def test_open_faces_exact_on_regularized_states(q, collision):
     c, w, opp = O.velocity_set(q)
     rng = np.random.default_rng(2506 + q + collision)
     f = np.empty((q, N))
+    u_out = np.empty((ny, nz))
     eq = (lambda rho, u: _eq2(c, w, rho, u)) if collision == 0 else (lambda rho, u: O.equilibrium3(q, rho, u))
     for z in range(nz):
         for y in range(ny):
@@ -60,11 +66,11 @@ def test_open_faces_exact_on_regularized_states(q, collision):
             st = eq(rng.uniform(0.98, 1.02), u) + _reg_neq(c, w, _rand_sym(rng, 2e-3))
             f[:, base + 0] = st
             f[:, base + 1] = st
-            # outlet column x = nx - 1 and its copy at x = nx - 2
+            # outlet column x = nx - 1 (its velocity kept for the check)
             u = np.array([rng.uniform(-0.03, 0.06), 0.0, 0.0])
-            st = eq(rho_out, u) + _reg_neq(c, w, _rand_sym(rng, 2e-3))
-            f[:, base + nx - 1] = st
-            f[:, base + nx - 2] = st
+            u_out[y, z] = u[0]
+            f[:, base + nx - 1] = eq(rho_out, u) + _reg_neq(c, w, _rand_sym(rng, 2e-3))
+            f[:, base + nx - 2] = eq(1.0, np.array([0.01, 0.0, 0.02])) + _reg_neq(c, w, _rand_sym(rng, 2e-3))
             # the middle column: any state
             f[:, base + 2] = eq(1.0, np.array([0.02, 0.01, -0.01])) + _reg_neq(c, w, _rand_sym(rng, 2e-3))
             # the populations entering through each face are overwritten with noise
@@ -83,7 +89,9 @@ def test_open_faces_exact_on_regularized_states(q, collision):
         for y in range(ny):
             base = nx * (y + ny * z)
             np.testing.assert_allclose(fs[:, base + 0], fs[:, base + 1], rtol=0, atol=2e-15)
-            np.testing.assert_allclose(fs[:, base + nx - 1], fs[:, base + nx - 2], rtol=0, atol=2e-15)
+            # the outlet's equilibrium has no third-order part for a velocity along x
+            expect = _eq2(c, w, rho_out, np.array([u_out[y, z], 0.0, 0.0]))
+            np.testing.assert_allclose(fs[:, base + nx - 1], expect, rtol=0, atol=2e-15)
 
 
 @pytest.mark.parametrize("q", [19, 27])
@@ -108,6 +116,25 @@ def test_open_uniform_stream_is_invariant(q, collision):
     np.testing.assert_allclose(rho[inner], 1.0, rtol=0, atol=1e-14)
     np.testing.assert_allclose(u[0, inner], U, rtol=0, atol=1e-14)
     np.testing.assert_allclose(u[1:, inner], 0.0, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_open_low_viscosity_stream_stable(q):
+    nx, ny, nz, U = 16, 8, 1, 0.05
+    N = nx * ny * nz
+    u0 = np.zeros((3, N))
+    u0[0] = U
+    u0 += 1e-6 * np.random.default_rng(7).standard_normal((3, N))
+    p = O.make_params(q, (nx, ny, nz), periodic=(0, 1, 1), tau0=0.5003, cs_smag=0.0, u_ref=U, z0=1.0,
+                      open_x=1, rho_out=1.0)
+    s = O.Oracle(p, u0=u0)
+    x = np.arange(N) % nx
+    inner = (x > 0) & (x < nx - 1)
+    for _ in range(8):
+        s.step(50)
+        rho, u = s.moments()
+        dev = max(np.abs(u[0, inner] - U).max(), np.abs(u[1:, inner]).max(), np.abs(rho[inner] - 1.0).max())
+        assert dev < 2e-5, dev
 
 
 def test_open_poiseuille():
@@ -150,9 +177,11 @@ def test_open_poiseuille():
     rho_mid = np.array([rho[(x == i) & (z == 4)][0] for i in range(20, 36)])
     drho = np.polyfit(np.arange(20, 36), rho_mid, 1)[0]
     assert abs(CS2 * drho / (nu * 2.0 * coef[2] * rho_mid.mean()) - 1.0) < 0.01
-    # the density extrapolates to the imposed outlet value at the face
+    # the density extrapolates to the imposed outlet value at the face, within
+    # half a cell's pressure drop (the equilibrium outlet drops the shear
+    # stress of the last plane, a first-order error there)
     rho_face = np.polyval(np.polyfit(np.arange(20, 36), rho_mid, 1), nx - 1)
-    assert abs(rho_face - 1.0) < 1e-4
+    assert abs(rho_face - 1.0) < 0.5 * abs(drho)
 
 
 def test_open_outlet_outside_the_fringe():
