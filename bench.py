@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -51,6 +53,9 @@ def make_case(name):
     if name in ("urban", "urban16"):
         return I.urban(768, 768, 256, q=27, with_wall_dist=False), ("f16" if name.endswith("16") else "f32"), \
             "urban768x768x256_d3q27_smag_wallmodel_fringe_lid"
+    if name in ("urban_open", "urban_open16"):
+        return I.urban(768, 768, 256, q=27, with_wall_dist=False, open_x=True), \
+            ("f16" if name.endswith("16") else "f32"), "urban768x768x256_d3q27_smag_wallmodel_inlet_outlet_fringe_lid"
     if name in ("big", "big16"):
         case = I.urban(1024, 1024, 1024, q=27, with_wall_dist=False, x_lo=64, x_hi=896, host_fields=False)
         case.u0 = I.urban_u0_device(case)
@@ -64,6 +69,18 @@ def make_case(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def open_face_cells(case):
+    """Fluid cells of the inlet and outlet planes that are not lid cells (the
+    open-face kernel updates them, the bulk kernel skips them)."""
+    if not case.open_x:
+        return 0
+    nx, ny, nz = case.shape
+    m = np.ones((nz, ny, nx), bool) if case.mask is None else np.asarray(case.mask).reshape(nz, ny, nx) != 0
+    if case.lid:
+        m = m[:-1]
+    return int(m[:, :, 0].sum() + m[:, :, -1].sum())
+
+
 def cpu_baseline(name, budget_s=12.0, collision=0, fd_weight=0.0):
     """The FP64 oracle on a bounded crop of the workload (same x-y plane,
     fewer z planes), timed around its step loop on the host cores."""
@@ -73,8 +90,10 @@ def cpu_baseline(name, budget_s=12.0, collision=0, fd_weight=0.0):
         case = I.channel(384, 192, 24, q=27)
         sample = "channel crop 384x192x24 (walls at z), D3Q27 FP64"
     elif name.startswith("urban") or name.startswith("big"):
-        case = I.urban(192, 192, 64, q=27, fringe_len=32, x_lo=16, x_hi=144, h_mean=20.0, h_max=48)
-        sample = "urban crop 192x192x64 (buildings, fringe, lid), D3Q27 FP64"
+        open_x = name.startswith("urban_open")
+        case = I.urban(192, 192, 64, q=27, fringe_len=32, x_lo=16, x_hi=144, h_mean=20.0, h_max=48, open_x=open_x)
+        sample = "urban crop 192x192x64 (buildings, fringe, lid{}), D3Q27 FP64".format(
+            ", inlet and outlet" if open_x else "")
     elif name == "tgv":
         case = I.taylor_green(32, q=19)
         sample = "tgv 32^3 D3Q19 FP64 (full)"
@@ -93,7 +112,7 @@ def cpu_baseline(name, budget_s=12.0, collision=0, fd_weight=0.0):
     p = O.make_params(case.q, case.shape, periodic=case.periodic, tau0=case.tau0, cs_smag=case.cs_smag,
                       force=case.force, wall_model=case.wall_model, kappa=case.kappa, E=case.E,
                       fringe_len=case.fringe_len, u_ref=case.u_ref, z0=case.z0, lid=case.lid,
-                      collision=case.collision, fd_weight=case.fd_weight)
+                      collision=case.collision, fd_weight=case.fd_weight, open_x=case.open_x, rho_out=case.rho_out)
     s = O.Oracle(p, mask=case.mask, wall_dist=case.wall_dist, porosity=case.porosity, rho0=case.rho0, u0=case.u0)
     t0 = time.perf_counter()
     s.step(1)
@@ -170,6 +189,7 @@ def main():
     N = case.ncells
     nfluid = case.nfluid()
     nwall = lbm.lbm_wall_count(lat.ctx)
+    n_open = open_face_cells(case)
     del case
     torch.cuda.empty_cache()
     stream = lat.stream
@@ -205,11 +225,11 @@ def main():
     fdw = args.fd_weight if args.collision == "rr3" else 0.0
     # algorithmic bytes of one bulk launch: every cell's flag byte, q loads and
     # q stores for each fluid cell it updates (all fluid cells but the wall
-    # cells); the hybrid collision also reads the velocity field once (three
+    # cells and the open-face cells); the hybrid collision also reads the velocity field once (three
     # compute-type values per fluid cell), which a pre-pass over the q loads
     # of every fluid cell wrote
     rb = 8 if storage == "f64" else 4
-    k2_bytes = N * 1 + (nfluid - nwall) * 2 * q * sb + (nfluid * 3 * rb if fdw > 0 else 0)
+    k2_bytes = N * 1 + (nfluid - nwall - n_open) * 2 * q * sb + (nfluid * 3 * rb if fdw > 0 else 0)
     achieved = k2_bytes / (k2_ms * 1e-3) / 1e9
     step_bytes = nfluid * (2 * q * sb + 1) + (nfluid * (q * sb + 6 * rb) if fdw > 0 else 0)
     # counter-measured bytes apply only to the kernel they were taken on: the

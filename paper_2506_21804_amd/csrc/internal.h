@@ -20,8 +20,8 @@ enum : uint8_t {
   FL_NEAR = 2,   // at least one link to a solid cell or outside a non-periodic axis
   FL_WALL = 4,   // wall-modeled cell (reconstruction collision, wall kernel)
   FL_LID = 8,    // top-lid cell (inflow equilibrium)
-  FL_INLET = 16, // open-face velocity inlet cell (plane x = 0), open-face kernel
-  FL_OUTLET = 32 // open-face pressure outlet cell (plane x = nx - 1), open-face kernel
+  FL_INLET = 16, // velocity inlet cell (plane x = 0, open x faces)
+  FL_OUTLET = 32 // pressure outlet cell (plane x = nx - 1, open x faces)
 };
 
 // Number of doubles per wall record (structure of arrays, nwall entries each).

@@ -293,67 +293,6 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k, cons
 }
 
 // ---------------------------------------------------------------------------
-// K2: fused gather / collide / scatter over all non-wall fluid cells.
-// ---------------------------------------------------------------------------
-// Gather, collide, scatter of one cell.  With LINKS = false the cell has no
-// solid link and every slot is the plain AA one (32-bit offsets from a
-// per-direction base); with LINKS = true slots follow the bounce-back map.
-template <int Q, typename S, bool ODD, bool POROUS, bool LINKS, bool RR, bool HYB>
-__device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename Store<S>::R *__restrict__ phi,
-                                          const uint8_t *__restrict__ flags, const KArgs &k, const Nb &n,
-                                          unsigned sm, uint8_t fl, int x, int z, int *__restrict__ errflag) {
-  using R = typename Store<S>::R;
-  const size_t N = (size_t)k.N;
-  R g[Q];
-  if (fl & FL_LID) {
-    lid_equilibrium<Q, R>(g, k);
-  } else {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      if (LINKS) {
-        g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
-      } else {
-        int dir;
-        const int idx = plain_read<Q, ODD>(n, i, dir);
-        g[i] = Store<S>::ld(slot_at(pop, dir, N, idx));
-      }
-    }
-    const R ph = POROUS ? phi[n.cell] : R(1);
-    R Sfd[6];
-    if constexpr (HYB) fd_strain<R>(n, flags, k, Sfd);
-    if (!collide_bulk<Q, R, POROUS, RR, HYB>(g, ph, k, Sfd)) atomicOr(errflag, 1);
-  }
-  fringe_blend<Q, R>(g, x, z, k);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    if (LINKS) {
-      Store<S>::st(pop + write_slot<Q, ODD>(n, sm, i, N), g[i]);
-    } else {
-      int dir;
-      const int idx = plain_write<Q, ODD>(n, i, dir);
-      Store<S>::st(slot_at(pop, dir, N, idx), g[i]);
-    }
-  }
-}
-
-template <int Q, typename S, bool ODD, bool POROUS, bool SOLID, bool RR, bool HYB>
-__global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8_t *__restrict__ flags,
-                                                const typename Store<S>::R *__restrict__ phi, KArgs k,
-                                                Tiles t, int *__restrict__ errflag) {
-  int x, y, z;
-  if (!tile_xyz(k, t, blockIdx.x, x, y, z)) return;
-  const Nb n = make_nb(x, y, z, k);
-  const uint8_t fl = flags[n.cell];
-  // wall cells and open-face cells have kernels of their own
-  if (!(fl & FL_FLUID) || (fl & (FL_WALL | FL_INLET | FL_OUTLET))) return;
-  unsigned sm = 0;
-  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
-  // cells without solid links (all but a thin layer) take the plain-address path
-  if (SOLID && ODD && sm != 0u) bulk_cell<Q, S, ODD, POROUS, true, RR, HYB>(pop, phi, flags, k, n, sm, fl, x, z, errflag);
-  else bulk_cell<Q, S, ODD, POROUS, false, RR, HYB>(pop, phi, flags, k, n, sm, fl, x, z, errflag);
-}
-
-// ---------------------------------------------------------------------------
 // Open x faces (Sec. 2.2.2: regularized local velocity inlet; Sec. 3.2: fixed
 // local pressure outlet).  The pre-collision deviations g of an inlet
 // (x = 0) or outlet (x = nx - 1) cell are rebuilt in place:
@@ -448,34 +387,72 @@ __device__ __forceinline__ void open_rebuild(R g[Q], bool outlet, int z, const K
   }
 }
 
-// One thread per cell of the two open planes: threads [0, ny nz) take the
-// inlet plane, the next ny nz the outlet plane.  Gather through the AA map
-// (links through the face read as bounce-back, like any outside link),
-// rebuild, bulk collision, scatter.  No fringe: the inlet lies before it and
-// the outlet plane is left out of it.
-template <int Q, typename S, bool ODD, bool POROUS, bool RR>
-__global__ __launch_bounds__(256) void k_open(S *__restrict__ pop, const uint8_t *__restrict__ flags,
-                                              const typename Store<S>::R *__restrict__ phi, KArgs k,
-                                              int *__restrict__ errflag) {
+// ---------------------------------------------------------------------------
+// K2: fused gather / collide / scatter over all non-wall fluid cells.
+// ---------------------------------------------------------------------------
+// Gather, collide, scatter of one cell.  With LINKS = false the cell has no
+// solid link and every slot is the plain AA one (32-bit offsets from a
+// per-direction base); with LINKS = true slots follow the bounce-back map.
+template <int Q, typename S, bool ODD, bool POROUS, bool LINKS, bool RR, bool HYB, bool OPEN>
+__device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename Store<S>::R *__restrict__ phi,
+                                          const uint8_t *__restrict__ flags, const KArgs &k, const Nb &n,
+                                          unsigned sm, uint8_t fl, int x, int z, int *__restrict__ errflag) {
   using R = typename Store<S>::R;
-  const int face = k.ny * k.nz;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * face) return;
-  const bool outlet = t >= face;
-  const int r = outlet ? t - face : t;
-  const int y = r % k.ny, z = r / k.ny;
-  const Nb n = make_nb(outlet ? k.nx - 1 : 0, y, z, k);
-  if (!(flags[n.cell] & (outlet ? FL_OUTLET : FL_INLET))) return;
-  const unsigned sm = ODD ? solid_mask<Q>(n, flags) : 0u;
   const size_t N = (size_t)k.N;
   R g[Q];
+  if (fl & FL_LID) {
+    lid_equilibrium<Q, R>(g, k);
+  } else {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
-  open_rebuild<Q, R>(g, outlet, z, k);
-  const R ph = POROUS ? phi[n.cell] : R(1);
-  if (!collide_bulk<Q, R, POROUS, RR>(g, ph, k)) atomicOr(errflag, 1);
+    for (int i = 0; i < Q; ++i) {
+      if (LINKS) {
+        g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+      } else {
+        int dir;
+        const int idx = plain_read<Q, ODD>(n, i, dir);
+        g[i] = Store<S>::ld(slot_at(pop, dir, N, idx));
+      }
+    }
+    if constexpr (OPEN) {
+      if (fl & (FL_INLET | FL_OUTLET)) open_rebuild<Q, R>(g, (fl & FL_OUTLET) != 0, z, k);
+    }
+    const R ph = POROUS ? phi[n.cell] : R(1);
+    R Sfd[6];
+    if constexpr (HYB) fd_strain<R>(n, flags, k, Sfd);
+    if (!collide_bulk<Q, R, POROUS, RR, HYB>(g, ph, k, Sfd)) atomicOr(errflag, 1);
+  }
+  // the outlet plane is left out of the fringe
+  if (!OPEN || !(fl & FL_OUTLET)) fringe_blend<Q, R>(g, x, z, k);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) Store<S>::st(pop + write_slot<Q, ODD>(n, sm, i, N), g[i]);
+  for (int i = 0; i < Q; ++i) {
+    if (LINKS) {
+      Store<S>::st(pop + write_slot<Q, ODD>(n, sm, i, N), g[i]);
+    } else {
+      int dir;
+      const int idx = plain_write<Q, ODD>(n, i, dir);
+      Store<S>::st(slot_at(pop, dir, N, idx), g[i]);
+    }
+  }
+}
+
+template <int Q, typename S, bool ODD, bool POROUS, bool SOLID, bool RR, bool HYB, bool OPEN = false>
+__global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                const typename Store<S>::R *__restrict__ phi, KArgs k,
+                                                Tiles t, int *__restrict__ errflag) {
+  int x, y, z;
+  if (!tile_xyz(k, t, blockIdx.x, x, y, z)) return;
+  const Nb n = make_nb(x, y, z, k);
+  const uint8_t fl = flags[n.cell];
+  // wall cells have a kernel of their own; OPEN: the cells of the inlet and
+  // outlet planes are updated here, in the rows whose cache lines they share
+  if (!(fl & FL_FLUID) || (fl & FL_WALL)) return;
+  unsigned sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  // cells without solid links (all but a thin layer) take the plain-address path
+  if (SOLID && ODD && sm != 0u)
+    bulk_cell<Q, S, ODD, POROUS, true, RR, HYB, OPEN>(pop, phi, flags, k, n, sm, fl, x, z, errflag);
+  else
+    bulk_cell<Q, S, ODD, POROUS, false, RR, HYB, OPEN>(pop, phi, flags, k, n, sm, fl, x, z, errflag);
 }
 
 // ---------------------------------------------------------------------------
@@ -1025,6 +1002,14 @@ static void launch_bulk(lbm_ctx *ctx, Tiles t) {
     kern<<<t.nblocks, BLOCK, lds_cap, ctx->stream>>>(pop, ctx->flags, phi, ctx->ka, t, ctx->errflag);
   };
   auto by_model = [&]<bool POROUS, bool SOLID>() {
+    // open x faces make x non-periodic, so their domains always have solid links
+    if constexpr (SOLID) {
+      if (ctx->has_open) {
+        if (ctx->ka.rr) go(k_bulk<Q, S, ODD, POROUS, true, true, false, true>);
+        else go(k_bulk<Q, S, ODD, POROUS, true, false, false, true>);
+        return;
+      }
+    }
     if (ctx->ka.rr && ctx->ka.fdw > 0.0) go(k_bulk<Q, S, ODD, POROUS, SOLID, true, true>);
     else if (ctx->ka.rr) go(k_bulk<Q, S, ODD, POROUS, SOLID, true, false>);
     else go(k_bulk<Q, S, ODD, POROUS, SOLID, false, false>);
@@ -1035,22 +1020,6 @@ static void launch_bulk(lbm_ctx *ctx, Tiles t) {
   } else {
     if (ctx->has_solid) by_model.template operator()<false, true>();
     else by_model.template operator()<false, false>();
-  }
-}
-
-template <int Q, typename S, bool ODD>
-static void launch_open(lbm_ctx *ctx) {
-  using R = typename Store<S>::R;
-  const int nb = (2 * ctx->ka.ny * ctx->ka.nz + 255) / 256;
-  S *pop = (S *)ctx->pop;
-  const R *phi = (const R *)ctx->phi;
-  auto go = [&](auto kern) { kern<<<nb, 256, 0, ctx->stream>>>(pop, ctx->flags, phi, ctx->ka, ctx->errflag); };
-  if (ctx->porous) {
-    if (ctx->ka.rr) go(k_open<Q, S, ODD, true, true>);
-    else go(k_open<Q, S, ODD, true, false>);
-  } else {
-    if (ctx->ka.rr) go(k_open<Q, S, ODD, false, true>);
-    else go(k_open<Q, S, ODD, false, false>);
   }
 }
 
@@ -1101,11 +1070,6 @@ int dev_step(lbm_ctx *ctx) {
         k_wall<Q, S, false><<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wref,
                                                          ctx->wrefwall, ctx->wrec, nw, ctx->ka, ctx->errflag);
       prof_end(ctx, 2);
-    }
-    // open x faces (they may be reference cells of wall records, so after K1/K3)
-    if (ctx->has_open) {
-      if (odd) launch_open<Q, S, true>(ctx);
-      else launch_open<Q, S, false>(ctx);
     }
     prof_begin(ctx, 1);
     if (odd) launch_bulk<Q, S, true>(ctx, t);
