@@ -87,6 +87,7 @@ def lib():
         L.orc_num_wall.restype = C.c_long
         L.orc_num_wall.argtypes = [vp]
         L.orc_wall_info.argtypes = [vp] + [vp] * 6
+        L.orc_set_vortices.argtypes = [vp, C.c_int, vp, vp, C.c_double, C.c_double]
         L.orc_velocity_set.argtypes = [C.c_int, vp, vp, vp]
         L.orc_equilibrium.argtypes = [C.c_int, C.c_double, vp, vp]
         L.orc_tau_eff.restype = C.c_double
@@ -197,6 +198,13 @@ class Oracle:
         f = np.ascontiguousarray(f, dtype=np.float64)
         df = None if df is None else np.ascontiguousarray(df, dtype=np.float64)
         self._check(lib().orc_set_populations(self.h, _ptr(f), _ptr(df)))
+
+    def set_vortices(self, yz, sign, intensity, sigma):
+        """Vortex-method seed points (y, z) on the inflow plane, cell-centre
+        coordinates (cell j spans [j, j + 1)), signs +-1, intensity I, size sigma."""
+        yz = np.ascontiguousarray(np.asarray(yz, dtype=np.float64).reshape(-1, 2))
+        sign = np.ascontiguousarray(np.asarray(sign, dtype=np.int32).reshape(-1))
+        self._check(lib().orc_set_vortices(self.h, len(sign), _ptr(yz), _ptr(sign), intensity, sigma))
 
     def set_phi_tangent(self, dphi):
         dphi = np.ascontiguousarray(dphi, dtype=np.float64).reshape(-1)

@@ -65,7 +65,9 @@
  *     fixed local pressure condition): the fluid cells of the planes x = 0
  *     (inlet) and x = nx - 1 (outlet) that are not lid cells replace their
  *     pre-collision populations before the collision.  The populations that
- *     enter through the face are unknown.  Inlet: u = (u_in(z), 0, 0)
+ *     enter through the face are unknown.  Inlet: u = (u_in(z), 0, 0), plus
+ *     the vortex method's in-plane perturbation when vortices are set (the
+ *     streamwise Langevin term, garbled in the paper, is left out),
  *     prescribed, rho from the known populations and u.n, and (regularized)
  *     the non-equilibrium of an unknown population is that of its opposite
  *     (known) one, Pi^neq is summed over all of them, and the cell's
@@ -400,6 +402,7 @@ struct SimBase {
   virtual int set_phi_tangent(const double* dphi) = 0;
   virtual int objective(const int planes[2], double* J, double* dJ) = 0;
   virtual int wall_info(long* cells, long* refs, double* normal, double* utau, double* G, double* tau) = 0;
+  virtual int set_vortices(int n, const double* yz, const int* sign, double intensity, double sigma) = 0;
   virtual long num_wall() const = 0;
   virtual int get_post_collision(double* f) = 0;
 };
@@ -421,6 +424,9 @@ struct Sim : SimBase {
   std::vector<T> uf;
   /* wall-model records of the current step (FP64) */
   std::vector<double> wt, wutan, wG, wtau, wutau;
+  /* inflow vortices of the vortex method: positions (y, z), circulations */
+  std::vector<double> vy, vz, vgam;
+  double vsig = 1.0;
 
   long idx(int x, int y, int z) const { return x + (long)p.nx * (y + (long)p.ny * z); }
   /* The equilibrium of the selected collision model (second or third order). */
@@ -456,6 +462,49 @@ struct Sim : SimBase {
   double u_in(double zc) const {
     double ztop = p.nz - 0.5;
     return p.u_ref * std::log(1.0 + zc / p.z0) / std::log(1.0 + ztop / p.z0);
+  }
+
+  /* Vortex method (Sec. 2.2.2): seed points p_i on the inflow plane with
+   * signs s_i; k_i = 3/2 (|u_mean(p_i)| I)^2 and
+   * Gamma_i = 4 s_i sqrt(pi / (6 ln 3 - 9 ln 2) k_i A / n), A the inlet area
+   * (ny nz cells).  The inflow direction is d = +x. */
+  int set_vortices(int n, const double* yz, const int* sign, double intensity, double sigma) override {
+    if (!p.open_x || n < 0 || (n > 0 && (!yz || !sign)) || !(sigma > 0.0) || !std::isfinite(sigma) ||
+        !(intensity >= 0.0) || !std::isfinite(intensity)) {
+      err = "vortices need open x faces, n >= 0, positions and signs, sigma > 0 and intensity >= 0";
+      return ORC_EINVAL;
+    }
+    const double pi = 3.14159265358979323846;
+    vy.assign(n, 0.0);
+    vz.assign(n, 0.0);
+    vgam.assign(n, 0.0);
+    vsig = sigma;
+    const double A = double(p.ny) * p.nz;
+    for (int i = 0; i < n; ++i) {
+      vy[i] = yz[2 * i];
+      vz[i] = yz[2 * i + 1];
+      const double um = std::fabs(u_in(vz[i]));
+      const double k = 1.5 * (um * intensity) * (um * intensity);
+      const double s = sign[i] >= 0 ? 1.0 : -1.0;
+      vgam[i] = 4.0 * s * std::sqrt(pi / (6.0 * std::log(3.0) - 9.0 * std::log(2.0)) * k * A / n);
+    }
+    return ORC_OK;
+  }
+  /* u_vortex(x) = 1/(2 pi) sum_i Gamma_i ((p_i - x) x d)(1 - exp(-|x - p_i|^2 / (2 sigma^2))) / |x - p_i|^2
+   * at the point (y, z) of the inflow plane; with d = +x,
+   * (p - x) x d = (0, (p - x)_z, -(p - x)_y).  The exponent's sign is the
+   * decaying one (the printed formula grows without bound). */
+  void u_vortex(double y, double z, double u[3]) const {
+    const double pi = 3.14159265358979323846;
+    u[0] = u[1] = u[2] = 0.0;
+    for (size_t i = 0; i < vgam.size(); ++i) {
+      const double dy = vy[i] - y, dz = vz[i] - z;
+      const double r2 = dy * dy + dz * dz;
+      if (r2 == 0.0) continue;
+      const double f = vgam[i] / (2.0 * pi) * (1.0 - std::exp(-r2 / (2.0 * vsig * vsig))) / r2;
+      u[1] += f * dz;
+      u[2] -= f * dy;
+    }
   }
 
   int init(const orc_params* prm, const uint8_t* mask, const double* wall_dist, const double* porosity,
@@ -774,8 +823,11 @@ struct Sim : SimBase {
      * rho (1 + u.n) = s_par + 2 s_out */
     T rho, u[3];
     if (inlet) {
+      double uv[3];
+      u_vortex(y + 0.5, z + 0.5, uv);
       u[0] = T(u_in(z + 0.5));
-      u[1] = u[2] = T(0.0);
+      u[1] = T(uv[1]);
+      u[2] = T(uv[2]);
       const T un = double(nx_out) * u[0];
       rho = (s_par + 2.0 * s_out) / (1.0 + un);
     } else {
@@ -1102,6 +1154,9 @@ int orc_objective(void* h, const int* planes, double* J, double* dJ) {
 }
 int orc_get_post_collision(void* h, double* f) { return static_cast<SimBase*>(h)->get_post_collision(f); }
 long orc_num_wall(void* h) { return static_cast<SimBase*>(h)->num_wall(); }
+int orc_set_vortices(void* h, int n, const double* yz, const int* sign, double intensity, double sigma) {
+  return static_cast<SimBase*>(h)->set_vortices(n, yz, sign, intensity, sigma);
+}
 int orc_wall_info(void* h, long* cells, long* refs, double* normal, double* utau, double* G, double* tau) {
   return static_cast<SimBase*>(h)->wall_info(cells, refs, normal, utau, G, tau);
 }

@@ -69,6 +69,11 @@ MUTATIONS = [
     ("inflow profile at the cell floor", "u[0] = T(u_in(z + 0.5));", "u[0] = T(u_in(z));"),
     ("inlet plane left as bulk cells", "if (p.open_x && kind[c] == K_BULK && x == 0) kind[c] = K_INLET;", ""),
     ("fringe over the outlet plane", "x >= fstart && kind[c] != K_OUTLET)", "x >= fstart)"),
+    ("vortex core growing instead of decaying", "(1.0 - std::exp(-r2 / (2.0 * vsig * vsig)))",
+     "(1.0 - std::exp(r2 / (2.0 * vsig * vsig)))"),
+    ("vortex turning the wrong way", "u[1] += f * dz;", "u[1] -= f * dz;"),
+    ("vortex circulation constant", "(6.0 * std::log(3.0) - 9.0 * std::log(2.0))",
+     "(6.0 * std::log(3.0) + 9.0 * std::log(2.0))"),
     ("regularized outlet", "if (!inlet) {\n      /* the outlet holds", "if (false) {\n      /* the outlet holds"),
 ]
 
@@ -97,6 +102,7 @@ PIN_TESTS = [
     (pins_open.test_open_uniform_stream_is_invariant, [(19, 0)]),
     (pins_open.test_open_outlet_outside_the_fringe, [()]),
     (pins_open.test_open_low_viscosity_stream_stable, [(19,)]),
+    (pins_open.test_vortex_inlet_exact, [(19, 0)]),
     (pins_open.test_open_poiseuille, [()]),
 ]
 

@@ -13,6 +13,9 @@
   magnitude and diverges within 400 steps.
 - Invariance: a uniform stream f^eq(1, U x) between an inlet imposing U and
   an outlet imposing rho = 1 stays exactly uniform.
+- Vortex method: with seed points on the inflow plane the inlet imposes the
+  mean profile plus the sum of Lamb-Oseen vortices about +x (exactness as
+  above, with that velocity).
 - The outlet plane is left out of the fringe; the planes before it are
   blended as usual.
 - Poiseuille: between two bounce-back walls, the developed laminar flow is
@@ -92,6 +95,77 @@ def test_open_faces_exact_on_regularized_states(q, collision):
             # the outlet's equilibrium has no third-order part for a velocity along x
             expect = _eq2(c, w, rho_out, np.array([u_out[y, z], 0.0, 0.0]))
             np.testing.assert_allclose(fs[:, base + nx - 1], expect, rtol=0, atol=2e-15)
+
+
+def _vortex_velocity(yc, zc, vort, sign, intensity, sigma, nz, ny, u_ref):
+    """In-plane velocity of the vortex method at the point (yc, zc) from the
+    Lamb-Oseen form of each vortex: speed Gamma/(2 pi r) (1 - exp(-r^2/(2
+    sigma^2))) about its centre, turning right-handed about the inflow
+    direction +x for Gamma > 0 (direction x-hat cross r-hat); Gamma_i from
+    k_i = 3/2 (|u_mean(p_i)| I)^2 as the paper defines it."""
+    n = len(sign)
+    u = np.zeros(3)
+    for (py, pz), s in zip(vort, sign):
+        um = abs(u_ref * np.log(1.0 + pz) / np.log(1.0 + (nz - 0.5)))
+        k = 1.5 * (um * intensity) ** 2
+        gam = 4.0 * s * np.sqrt(np.pi / (6 * np.log(3) - 9 * np.log(2)) * k * ny * nz / n)
+        ry, rz = yc - py, zc - pz
+        r = np.hypot(ry, rz)
+        speed = gam / (2 * np.pi * r) * (1.0 - np.exp(-r * r / (2 * sigma * sigma)))
+        u += speed * np.array([0.0, -rz / r, ry / r])
+    return u
+
+
+@pytest.mark.parametrize("q,collision", [(19, 0), (27, 1)])
+def test_vortex_inlet_exact(q, collision):
+    """The inlet with vortex-method seed points imposes u_mean(z) x + the
+    Lamb-Oseen sum: on a regularized state with exactly that velocity the
+    inlet cell collides like an interior copy of the complete state."""
+    nx, ny, nz = 4, 6, 5
+    N = nx * ny * nz
+    u_ref, tau0, cs, intensity, sigma = 0.05, 0.62, 0.12, 0.3, 1.3
+    vort = [(2.3, 1.7), (4.1, 3.2), (0.9, 4.4)]
+    sign = [1, -1, 1]
+    c, w, _ = O.velocity_set(q)
+    rng = np.random.default_rng(99 + q)
+    eq = (lambda rho, u: _eq2(c, w, rho, u)) if collision == 0 else (lambda rho, u: O.equilibrium3(q, rho, u))
+    f = np.empty((q, N))
+    for z in range(nz):
+        for y in range(ny):
+            base = nx * (y + ny * z)
+            u = _vortex_velocity(y + 0.5, z + 0.5, vort, sign, intensity, sigma, nz, ny, u_ref)
+            u[0] += _u_in(z, nz, u_ref)
+            st = eq(rng.uniform(0.98, 1.02), u) + _reg_neq(c, w, _rand_sym(rng, 2e-3))
+            f[:, base + 0] = st
+            f[:, base + 1] = st
+            for xx in range(2, nx):
+                f[:, base + xx] = eq(1.0, np.array([0.03, 0.0, 0.0]))
+            for i in range(q):
+                if c[i, 0] > 0:
+                    f[i, base] = rng.uniform(0.0, 0.2)
+    p = O.make_params(q, (nx, ny, nz), periodic=(0, 1, 1), tau0=tau0, cs_smag=cs, u_ref=u_ref, z0=1.0,
+                      collision=collision, open_x=1, rho_out=1.0)
+    s = O.Oracle(p)
+    s.set_vortices(vort, sign, intensity, sigma)
+    s.set_populations(f)
+    s.step(1)
+    fs = s.post_collision()
+    assert np.abs(f[:, 1::nx] - f[:, 0::nx]).max() > 1e-3  # the unknown populations really were replaced
+    for z in range(nz):
+        for y in range(ny):
+            base = nx * (y + ny * z)
+            np.testing.assert_allclose(fs[:, base], fs[:, base + 1], rtol=0, atol=2e-15)
+
+
+def test_vortices_validated():
+    p = O.make_params(19, (6, 4, 4), periodic=(0, 1, 1), tau0=0.6, u_ref=0.05, z0=1.0, open_x=1)
+    s = O.Oracle(p)
+    for args in (([(1.0, 1.0)], [1], 0.1, 0.0), ([(1.0, 1.0)], [1], -0.1, 1.0)):
+        with pytest.raises(O.OracleError):
+            s.set_vortices(*args)
+    closed = O.Oracle(O.make_params(19, (6, 4, 4), tau0=0.6))
+    with pytest.raises(O.OracleError):
+        closed.set_vortices([(1.0, 1.0)], [1], 0.1, 1.0)
 
 
 @pytest.mark.parametrize("q", [19, 27])
