@@ -217,6 +217,24 @@ long long lbm_revolve_cost(int T, int nsnap);
  * length; any pointer may be NULL): cell, reference cell, normal [n][3],
  * and from the last wall prepass u_tau, G, tau_eff.  Synchronises. */
 int lbm_wall_count(const lbm_ctx *ctx);
+
+/* Vortex-method inflow perturbation of the velocity inlet (Sec. 2.2.2; needs
+ * open_x).  n seed points on the inflow plane: yz host double [n][2], the
+ * (y, z) position in cell units (cell j spans [j, j + 1), its centre is
+ * j + 1/2), sign host int [n] (>= 0 for +1, < 0 for -1), turbulence
+ * intensity I >= 0, vortex size sigma > 0 (cells).  The library computes
+ * k_i = 3/2 (|u_mean(p_i)| I)^2 from the log-law profile at z_i and
+ * Gamma_i = 4 s_i sqrt(pi / (6 ln 3 - 9 ln 2) k_i A / n), A = ny nz, and from
+ * then on the inlet imposes u_mean(z) x plus
+ * u_vortex(x) = 1/(2 pi) sum_i Gamma_i ((p_i - x) x d)(1 - exp(-|x - p_i|^2 /
+ * (2 sigma^2))) / |x - p_i|^2 with d = +x (the decaying exponent; the
+ * streamwise Langevin term is not applied).  n = 0 restores the mean
+ * profile.  0 <= n <= LBM_MAX_VORTICES.  Synchronises the stream (the list
+ * is copied into the workspace), then fills the inlet velocity field on it.
+ * LBM_EINVAL (nothing changed) for invalid arguments or without open_x. */
+enum { LBM_MAX_VORTICES = 4096 };
+int lbm_set_inflow_vortices(lbm_ctx *ctx, int n, const double *yz, const int *sign, double intensity,
+                            double sigma);
 int lbm_wall_records(lbm_ctx *ctx, int *cell, int *ref, double *normal, double *utau, double *G,
                      double *tau);
 

@@ -20,7 +20,7 @@ __all__ = [
     "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes",
     "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural",
     "lbm_gradient", "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
-    "lbm_last_error", "lbm_free",
+    "lbm_set_inflow_vortices", "lbm_last_error", "lbm_free",
     "Lattice", "D3Q19", "D3Q27", "F64", "F32DEV", "F16DEV",
 ]
 
@@ -53,6 +53,9 @@ class Params(C.Structure):
         ("rho_out", C.c_double),
         ("stream", C.c_void_p),
     ]
+
+
+MAX_VORTICES = 4096  # LBM_MAX_VORTICES
 
 
 class LbmError(RuntimeError):
@@ -99,6 +102,7 @@ def load():
         "lbm_wall_records": (i, [vp, vp, vp, vp, vp, vp, vp]),
         "lbm_profile": (i, [vp, i]),
         "lbm_profile_read": (i, [vp, vp, vp]),
+        "lbm_set_inflow_vortices": (i, [vp, i, vp, vp, d, d]),
         "lbm_last_error": (C.c_char_p, [vp]),
         "lbm_free": (None, [vp]),
     }
@@ -116,7 +120,7 @@ def exported_symbols():
             "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes", "lbm_adjoint_seed",
             "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural", "lbm_gradient",
             "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
-            "lbm_last_error", "lbm_free"]
+            "lbm_set_inflow_vortices", "lbm_last_error", "lbm_free"]
 
 
 def _dptr(t):
@@ -319,6 +323,17 @@ def lbm_revolve_cost(T, nsnap) -> int:
     return load().lbm_revolve_cost(int(T), int(nsnap))
 
 
+def lbm_set_inflow_vortices(ctx, yz, sign, intensity, sigma):
+    """Vortex-method seed points (y, z) on the inflow plane (host arrays [n][2]
+    and [n]), turbulence intensity and vortex size; n = 0 clears them."""
+    yz = np.ascontiguousarray(np.asarray(yz, dtype=np.float64).reshape(-1, 2))
+    sign = np.ascontiguousarray(np.asarray(sign, dtype=np.int32).reshape(-1))
+    if len(sign) != len(yz):
+        raise ValueError("one sign per vortex expected")
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p) if a.size else None
+    _check(ctx, load().lbm_set_inflow_vortices(ctx, len(sign), ptr(yz), ptr(sign), float(intensity), float(sigma)))
+
+
 def lbm_wall_count(ctx) -> int:
     return load().lbm_wall_count(ctx)
 
@@ -469,6 +484,10 @@ class Lattice:
 
     def new_gradient(self):
         return self.torch.zeros(self.N, dtype=self.torch.float64, device="cuda")
+
+    def set_vortices(self, yz, sign, intensity, sigma):
+        """Vortex-method perturbation of the inlet (open x faces)."""
+        lbm_set_inflow_vortices(self.ctx, yz, sign, intensity, sigma)
 
     def wall_records(self):
         return lbm_wall_records(self.ctx)

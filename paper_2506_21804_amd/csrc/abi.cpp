@@ -108,7 +108,8 @@ bool params_ok(const lbm_params *p, std::string &msg) {
 }
 
 struct Layout {
-  size_t pop, flags, phi, tables, vel, wcell, wref, wrefwall, wlist, wrec, partial, result, errflag, total;
+  size_t pop, flags, phi, tables, vel, inflow, vort, wcell, wref, wrefwall, wlist, wrec, partial, result, errflag,
+      total;
 };
 
 Layout layout_of(const lbm_params &p, long long nwall, bool porous) {
@@ -126,6 +127,10 @@ Layout layout_of(const lbm_params &p, long long nwall, bool porous) {
   off += align_up(((size_t)p.nz + p.nx) * rb);
   L.vel = off;
   off += p.fd_weight > 0.0 ? align_up(3 * N * rb) : 0;
+  L.inflow = off;
+  off += p.open_x ? align_up(3 * (size_t)p.ny * p.nz * rb) : 0;
+  L.vort = off;
+  off += p.open_x ? align_up((size_t)LBM_MAX_VORTICES * 3 * sizeof(double)) : 0;
   L.wcell = off;
   off += align_up((size_t)nwall * sizeof(int));
   L.wref = off;
@@ -267,6 +272,8 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   ctx->phi = ctx->porous ? base + L.phi : nullptr;
   ctx->tables = base + L.tables;
   ctx->vel = p->fd_weight > 0.0 ? base + L.vel : nullptr;
+  ctx->inflow = p->open_x ? base + L.inflow : nullptr;
+  ctx->vort = p->open_x ? (double *)(base + L.vort) : nullptr;
   ctx->nwall = (int)nwall;
   ctx->wcell = (int *)(base + L.wcell);
   ctx->wref = (int *)(base + L.wref);
@@ -298,6 +305,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   k.fdw = p->fd_weight;
   k.vel = p->fd_weight > 0.0 ? ctx->vel : nullptr;
   k.open_x = p->open_x;
+  k.inflow = ctx->inflow;
   k.rho_out = p->open_x ? p->rho_out : 1.0;
   // inflow profile u_in(z) and fringe weights lambda(x)
   std::vector<double> tab((size_t)p->nz + p->nx, 0.0);
@@ -357,7 +365,8 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
     if ((e = hipMemcpy(ctx->wrec, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
       return fail(e, "upload wall records");
   }
-  if (dev_fill(ctx, ctx->errflag, ALIGN) != LBM_OK || dev_init_equilibrium(ctx, rho0, u0) != LBM_OK) {
+  if (dev_fill(ctx, ctx->errflag, ALIGN) != LBM_OK || (p->open_x && dev_inflow(ctx, 0, 1.0) != LBM_OK) ||
+      dev_init_equilibrium(ctx, rho0, u0) != LBM_OK) {
     int code = LBM_EHIP;
     g_static_error = ctx->err;
     delete ctx;
@@ -592,6 +601,36 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
 }
 
 int lbm_wall_count(const lbm_ctx *ctx) { return ctx ? ctx->nwall : -1; }
+
+int lbm_set_inflow_vortices(lbm_ctx *ctx, int n, const double *yz, const int *sign, double intensity,
+                            double sigma) {
+  if (!ctx) return LBM_EINVAL;
+  if (!ctx->p.open_x) return set_err(ctx, LBM_EINVAL, "vortices need open x faces");
+  if (n < 0 || n > LBM_MAX_VORTICES || (n > 0 && (!yz || !sign)))
+    return set_err(ctx, LBM_EINVAL, "vortex count must be in [0, LBM_MAX_VORTICES] with positions and signs");
+  if (!(sigma > 0.0) || !std::isfinite(sigma) || !(intensity >= 0.0) || !std::isfinite(intensity))
+    return set_err(ctx, LBM_EINVAL, "vortices need sigma > 0 and intensity >= 0, both finite");
+  for (int i = 0; i < 2 * n; ++i)
+    if (!std::isfinite(yz[i])) return set_err(ctx, LBM_EINVAL, "vortex positions must be finite");
+  // circulations: k_i = 3/2 (|u_mean(z_i)| I)^2, Gamma_i = 4 s_i sqrt(pi / (6 ln 3 - 9 ln 2) k_i A / n)
+  const double pi = 3.14159265358979323846;
+  const double A = (double)ctx->p.ny * ctx->p.nz;
+  const double ztop = ctx->p.nz - 0.5;
+  std::vector<double> v((size_t)3 * n);
+  for (int i = 0; i < n; ++i) {
+    const double z = yz[2 * i + 1];
+    const double um = std::fabs(ctx->p.u_ref * std::log(1.0 + z / ctx->p.z0) / std::log(1.0 + ztop / ctx->p.z0));
+    const double k = 1.5 * (um * intensity) * (um * intensity);
+    v[3 * i] = yz[2 * i];
+    v[3 * i + 1] = z;
+    v[3 * i + 2] = 4.0 * (sign[i] >= 0 ? 1.0 : -1.0) * std::sqrt(pi / (6.0 * std::log(3.0) - 9.0 * std::log(2.0)) * k * A / n);
+  }
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  if (n > 0 && (e = hipMemcpy(ctx->vort, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(ctx, e, "upload vortices");
+  return dev_inflow(ctx, n, sigma);
+}
 
 int lbm_wall_records(lbm_ctx *ctx, int *cell, int *ref, double *normal, double *utau, double *G, double *tau) {
   if (!ctx) return LBM_EINVAL;

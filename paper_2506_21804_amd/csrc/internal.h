@@ -55,6 +55,7 @@ struct KArgs {
   const void *vel;   // [3][N] velocity field of the current step, compute type (fdw > 0)
   const void *uin;   // [nz] fringe inflow profile, compute type
   const void *lam;   // [nx] fringe blend weight, compute type (0 before the fringe)
+  const void *inflow;  // [3][ny nz] inlet velocity, compute type (open_x)
 };
 
 // Adjoint field in caller memory (lbm_adjoint_bytes).  The value of a slot is
@@ -106,6 +107,8 @@ struct lbm_ctx {
   void *phi = nullptr;        // [N] compute type, porous only
   void *tables = nullptr;     // [nz] inflow + [nx] fringe weights, compute type
   void *vel = nullptr;        // [3][N] velocity field, compute type (hybrid collision only)
+  void *inflow = nullptr;     // [3][ny nz] inlet velocity, compute type (open_x only)
+  double *vort = nullptr;     // [LBM_MAX_VORTICES][3] vortex y, z, circulation (open_x only)
   int nwall = 0;
   int *wcell = nullptr;       // [nwall]
   int *wref = nullptr;        // [nwall]
@@ -154,6 +157,7 @@ std::vector<Action> revolve_schedule(int T, int nsnap);
 // ---- device launchers (kernels.hip, adjoint.hip) ---------------------------
 // Each returns LBM_OK or LBM_EHIP (with ctx->err set).
 int dev_init_equilibrium(lbm_ctx *ctx, const double *rho0, const double *u0);
+int dev_inflow(lbm_ctx *ctx, int nvort, double sigma);  // inlet velocity field from ctx->vort
 int dev_step(lbm_ctx *ctx);  // one time step at parity ctx->steps & 1
 int dev_moments(lbm_ctx *ctx, void *rho, void *u);
 int dev_reduce_diag(lbm_ctx *ctx);  // writes result[0..3]

@@ -301,8 +301,9 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k, cons
 //  - rho (1 + u.n) = s_0 + 2 s_+, where s_0 sums the populations with c.n = 0
 //    and s_+ those with c.n > 0 (in deviations: 1 + G_0 + 2 G_+, since their
 //    weights sum to 2/3 and 1/6);
-//  - inlet: u = (u_in(z), 0, 0), rho from that relation; outlet: rho =
-//    rho_out, u.n from it, no tangential velocity;
+//  - inlet: u from the inlet velocity field (u_in(z) along x plus the vortex
+//    method's in-plane part, k_inflow), rho from that relation; outlet:
+//    rho = rho_out, u.n from it, no tangential velocity;
 //  - inlet (regularized): the non-equilibrium h = g - g^eq of an unknown
 //    population is that of its opposite, Pi = sum c c h, and
 //    g = g^eq + 9/2 w (c.Pi.c - tr Pi/3);
@@ -310,11 +311,12 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k, cons
 //    populations feeds the over-relaxed (tau near 1/2) non-equilibrium back
 //    through the face: perturbations then grow without bound at small
 //    viscosity, while the equilibrium outlet keeps them at their size.
-// The velocity is along x, so the third-order equilibrium terms vanish on
-// D3Q19 and D3Q27 (no xxx component) and one equilibrium serves both models.
+// With the recursive regularized model the equilibrium is third order (for a
+// velocity along x, as at the outlet, its third-order terms vanish: the
+// lattices carry no xxx component).
 // ---------------------------------------------------------------------------
-template <int Q, typename R>
-__device__ __forceinline__ void open_rebuild(R g[Q], bool outlet, int z, const KArgs &k) {
+template <int Q, typename R, bool RR>
+__device__ __forceinline__ void open_rebuild(R g[Q], bool outlet, int y, int z, const KArgs &k) {
   constexpr int H = (Q - 1) / 2;
   const int nxo = outlet ? 1 : -1;  // x component of the outward normal
   R gpar = g[0], gout = R(0);
@@ -328,23 +330,41 @@ __device__ __forceinline__ void open_rebuild(R g[Q], bool outlet, int z, const K
     }
   }
   const R m = gpar + R(2) * gout;  // s_0 + 2 s_+ - 1
-  R drho, rho, ux;
+  R drho, rho, ux, uy = R(0), uz = R(0);
   if (outlet) {
     drho = R(k.rho_out - 1.0);
     rho = R(1) + drho;
     ux = (m - drho) / rho;  // u.n with n = +x
   } else {
-    ux = static_cast<const R *>(k.uin)[z];
+    // inlet velocity field: the mean profile plus the vortex method's in-plane part
+    const R *f = static_cast<const R *>(k.inflow);
+    const int face = k.ny * k.nz, c2 = y + k.ny * z;
+    ux = f[c2];
+    uy = f[face + c2];
+    uz = f[2 * face + c2];
     const R un = -ux;
     drho = (m - un) / (R(1) + un);
     rho = R(1) + drho;
   }
-  const R uu = ux * ux;
+  const R uu = ux * ux + uy * uy + uz * uz;
+  // equilibrium deviations, third order with the recursive regularized model
+  R K[7];
+  if constexpr (RR) {
+    R A[7];
+    cube_tensor(rho, ux, uy, uz, A);
+    third_coefs<Q, R>(A, K);
+  }
   R geq[Q];
+  geq[0] = R(Lat<Q>::w(0)) * (drho - R(1.5) * rho * uu);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const R cu = R(Lat<Q>::c(i, 0)) * ux;
-    geq[i] = R(Lat<Q>::w(i)) * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+  for (int i = 1; i <= H; ++i) {
+    const R w = R(Lat<Q>::w(i));
+    const R cu = dot3(Lat<Q>::c(i, 0), Lat<Q>::c(i, 1), Lat<Q>::c(i, 2), ux, uy, uz);
+    const R P = w * (drho + rho * (R(4.5) * cu * cu - R(1.5) * uu));
+    R Qo = w * R(3) * rho * cu;
+    if constexpr (RR) Qo += w * third_term<Q, R>(i, K);
+    geq[i] = P + Qo;
+    geq[i + H] = P - Qo;
   }
   if (outlet) {
 #pragma unroll
@@ -387,6 +407,34 @@ __device__ __forceinline__ void open_rebuild(R g[Q], bool outlet, int z, const K
   }
 }
 
+// Inlet velocity field, one thread per cell (y, z) of the inflow plane: the
+// mean profile u_in(z) along x plus the vortex method's in-plane velocity of
+// nvort vortices (y_i, z_i, Gamma_i) at the cell centre (Sec. 2.2.2):
+// u_vortex = 1/(2 pi) sum_i Gamma_i ((p_i - x) x d)(1 - exp(-r^2/(2 sigma^2)))/r^2
+// with d = +x, i.e. (0, Delta z, -Delta y) for Delta = p_i - x.  Summed in FP64.
+template <typename R>
+__global__ __launch_bounds__(256) void k_inflow(R *__restrict__ field, const double *__restrict__ vort, int nvort,
+                                                double sigma, KArgs k) {
+  const int face = k.ny * k.nz;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= face) return;
+  const int y = t % k.ny, z = t / k.ny;
+  const double yc = y + 0.5, zc = z + 0.5;
+  const double inv2s2 = 1.0 / (2.0 * sigma * sigma), inv2pi = 1.0 / (2.0 * 3.14159265358979323846);
+  double uy = 0.0, uz = 0.0;
+  for (int i = 0; i < nvort; ++i) {
+    const double dy = vort[3 * i] - yc, dz = vort[3 * i + 1] - zc;
+    const double r2 = dy * dy + dz * dz;
+    if (r2 == 0.0) continue;
+    const double f = vort[3 * i + 2] * inv2pi * (1.0 - exp(-r2 * inv2s2)) / r2;
+    uy += f * dz;
+    uz -= f * dy;
+  }
+  field[t] = static_cast<const R *>(k.uin)[z];
+  field[face + t] = R(uy);
+  field[2 * face + t] = R(uz);
+}
+
 // ---------------------------------------------------------------------------
 // K2: fused gather / collide / scatter over all non-wall fluid cells.
 // ---------------------------------------------------------------------------
@@ -396,7 +444,8 @@ __device__ __forceinline__ void open_rebuild(R g[Q], bool outlet, int z, const K
 template <int Q, typename S, bool ODD, bool POROUS, bool LINKS, bool RR, bool HYB, bool OPEN>
 __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename Store<S>::R *__restrict__ phi,
                                           const uint8_t *__restrict__ flags, const KArgs &k, const Nb &n,
-                                          unsigned sm, uint8_t fl, int x, int z, int *__restrict__ errflag) {
+                                          unsigned sm, uint8_t fl, int x, int y, int z,
+                                          int *__restrict__ errflag) {
   using R = typename Store<S>::R;
   const size_t N = (size_t)k.N;
   R g[Q];
@@ -414,7 +463,7 @@ __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename St
       }
     }
     if constexpr (OPEN) {
-      if (fl & (FL_INLET | FL_OUTLET)) open_rebuild<Q, R>(g, (fl & FL_OUTLET) != 0, z, k);
+      if (fl & (FL_INLET | FL_OUTLET)) open_rebuild<Q, R, RR>(g, (fl & FL_OUTLET) != 0, y, z, k);
     }
     const R ph = POROUS ? phi[n.cell] : R(1);
     R Sfd[6];
@@ -450,9 +499,9 @@ __global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8
   if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
   // cells without solid links (all but a thin layer) take the plain-address path
   if (SOLID && ODD && sm != 0u)
-    bulk_cell<Q, S, ODD, POROUS, true, RR, HYB, OPEN>(pop, phi, flags, k, n, sm, fl, x, z, errflag);
+    bulk_cell<Q, S, ODD, POROUS, true, RR, HYB, OPEN>(pop, phi, flags, k, n, sm, fl, x, y, z, errflag);
   else
-    bulk_cell<Q, S, ODD, POROUS, false, RR, HYB, OPEN>(pop, phi, flags, k, n, sm, fl, x, z, errflag);
+    bulk_cell<Q, S, ODD, POROUS, false, RR, HYB, OPEN>(pop, phi, flags, k, n, sm, fl, x, y, z, errflag);
 }
 
 // ---------------------------------------------------------------------------
@@ -976,6 +1025,15 @@ static int dispatch(lbm_ctx *ctx, F &&f) {
   if (ctx->p.storage == LBM_F64) return f.template operator()<27, double>();
   if (ctx->p.storage == LBM_F32DEV) return f.template operator()<27, float>();
   return f.template operator()<27, _Float16>();
+}
+
+int dev_inflow(lbm_ctx *ctx, int nvort, double sigma) {
+  const int nb = (ctx->ka.ny * ctx->ka.nz + 255) / 256;
+  if (ctx->p.storage == LBM_F64)
+    k_inflow<double><<<nb, 256, 0, ctx->stream>>>((double *)ctx->inflow, ctx->vort, nvort, sigma, ctx->ka);
+  else
+    k_inflow<float><<<nb, 256, 0, ctx->stream>>>((float *)ctx->inflow, ctx->vort, nvort, sigma, ctx->ka);
+  return check_launch(ctx, "k_inflow");
 }
 
 int dev_init_equilibrium(lbm_ctx *ctx, const double *rho0, const double *u0) {

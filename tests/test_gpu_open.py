@@ -3,10 +3,11 @@ outlet; Sec. 2.2.2, Sec. 3.2) of the HIP path with the FP64 oracle, through
 the C ABI.  Same bars as the other parity tests: FP64 storage within 1e-12
 of the oracle (density and velocity relative to the oracle field's max-norm,
 rho - 1 within 1e-10 of its own); FP32 within 1e-5 after 100 steps.  The
-cases cover the open-face kernel at both parities, with and without
+cases cover the open-face rebuild in the bulk kernel at both parities, with and without
 porosity, with both collision models, next to wall-modeled ground and
 buildings (whose reference cells may lie on the inlet plane), the fringe
-before the outlet and the lid above both faces."""
+before the outlet, the lid above both faces, and the vortex method on the
+inlet."""
 import dataclasses
 
 import numpy as np
@@ -105,6 +106,69 @@ def test_open_ragged_porous(gpu, q):
                                rho_out=1.002, u_ref=0.05, z0=1.0)
     _, rho, u, orho, ou = _run_both(gpu, case, 33, "f64")
     _check(f"open porous q={q} f64", moment_errors(rho, u, orho, ou), 1e-12)
+
+
+def _vortices(case, n, seed):
+    nx, ny, nz = case.shape
+    rng = np.random.default_rng(seed)
+    yz = np.stack([rng.uniform(0, ny, n), rng.uniform(0, nz, n)], 1)
+    sign = np.where(rng.uniform(size=n) < 0.5, -1, 1)
+    return yz, sign
+
+
+@pytest.mark.parametrize("collision,storage,tol,steps", [(0, "f64", 1e-12, 41), (1, "f64", 1e-12, 40),
+                                                         (0, "f32", 1e-5, 100)])
+def test_vortex_inlet_urban_crop(gpu, collision, storage, tol, steps):
+    """The vortex method's perturbation on the inlet (40 seed vortices,
+    intensity 0.2, size 3 cells), in the urban crop with open faces."""
+    case = _urban_open(collision=collision)
+    yz, sign = _vortices(case, 40, 11)
+    announce(f"vortex urban collision={collision} storage={storage} steps={steps}")
+    lat = gpu.Lattice(case, storage=storage, wall_dist="case")
+    lat.set_vortices(yz, sign, 0.2, 3.0)
+    lat.step(steps)
+    rho, u = lat.moments()
+    orc = oracle_for(case, 0, wall_dist=case.wall_dist)
+    orc.set_vortices(yz, sign, 0.2, 3.0)
+    orc.step(steps)
+    orho, ou = orc.moments()
+    rho, u = rho.cpu().numpy().astype(np.float64), u.cpu().numpy().astype(np.float64)
+    _check(f"vortex urban collision={collision} {storage}", moment_errors(rho, u, orho, ou), tol)
+    # the perturbation reaches the inlet plane's neighbours
+    x = np.arange(case.ncells) % case.shape[0]
+    assert np.abs(ou[1:, x == 1]).max() > 1e-4
+
+
+def test_vortex_reset_and_clear(gpu):
+    """Vortices replaced by a smaller set, then cleared, between steps."""
+    case = _urban_open()
+    lat = gpu.Lattice(case, storage="f64", wall_dist="case")
+    orc = oracle_for(case, 0, wall_dist=case.wall_dist)
+    for n, steps in ((40, 10), (5, 11), (0, 10)):
+        yz, sign = _vortices(case, n, 100 + n)
+        announce(f"vortex reset n={n} steps={steps}")
+        lat.set_vortices(yz, sign, 0.25, 2.5)
+        orc.set_vortices(yz, sign, 0.25, 2.5)
+        lat.step(steps)
+        orc.step(steps)
+    rho, u = lat.moments()
+    orho, ou = orc.moments()
+    rho, u = rho.cpu().numpy().astype(np.float64), u.cpu().numpy().astype(np.float64)
+    _check("vortex reset f64", moment_errors(rho, u, orho, ou), 1e-12)
+
+
+def test_vortex_arguments_checked(gpu):
+    case = _stream(19, (12, 3, 4), 0.04)
+    lat = gpu.Lattice(case, storage="f64")
+    yz, sign = np.array([[1.0, 1.0]]), np.array([1])
+    for bad in ((yz, sign, 0.1, 0.0), (yz, sign, -0.1, 1.0), (np.array([[np.nan, 1.0]]), sign, 0.1, 1.0),
+                (np.zeros((gpu.MAX_VORTICES + 1, 2)), np.ones(gpu.MAX_VORTICES + 1), 0.1, 1.0)):
+        with pytest.raises(gpu.LbmError) as e:
+            lat.set_vortices(*bad)
+        assert e.value.code == gpu.EINVAL
+    closed = gpu.Lattice(I.taylor_green(8, q=19), storage="f64")
+    with pytest.raises(gpu.LbmError):
+        closed.set_vortices(yz, sign, 0.1, 1.0)
 
 
 def test_open_adjoint_refused(gpu):
