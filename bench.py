@@ -156,6 +156,9 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "rr3"],
                     help="bulk collision model: BGK or recursive regularized (third order)")
+    ap.add_argument("--vortices", type=int, default=0,
+                    help="urban_open workloads: seeded vortex-method seed points on the inlet (intensity 0.1, "
+                         "size 4 cells); the time of one inlet-field update is reported")
     ap.add_argument("--fd-weight", type=float, default=0.0,
                     help="with --collision rr3: weight 1 - sigma of the finite-difference strain (hybrid)")
     ap.add_argument("--profile-steps", type=int, default=2000,
@@ -190,6 +193,21 @@ def main():
     nfluid = case.nfluid()
     nwall = lbm.lbm_wall_count(lat.ctx)
     n_open = open_face_cells(case)
+    vortex_ms = None
+    if args.vortices > 0:
+        if not case.open_x:
+            raise SystemExit("--vortices needs a workload with open x faces (urban_open, urban_open16)")
+        rng = np.random.default_rng(2506 + 7)
+        yz = np.stack([rng.uniform(0, case.shape[1], args.vortices), rng.uniform(0, case.shape[2], args.vortices)], 1)
+        sign = np.where(rng.uniform(size=args.vortices) < 0.5, -1, 1)
+        lat.set_vortices(yz, sign, 0.1, 4.0)
+        lat.sync()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            lat.set_vortices(yz, sign, 0.1, 4.0)
+        lat.sync()
+        vortex_ms = (time.perf_counter() - t0) / 10 * 1e3
+        wname += f"_vortices{args.vortices}"
     del case
     torch.cuda.empty_cache()
     stream = lat.stream
@@ -268,6 +286,9 @@ def main():
                                "wall": round(kms[2] / max(kcount[2], 1), 5), "bulk": round(k2_ms, 5)},
         "mass_drift_rel": None,
     }
+    if vortex_ms is not None:
+        # host-timed: copy of the seed points (after a stream synchronisation) and the field kernel
+        out["vortex_field_update_ms"] = round(vortex_ms, 4)
     out["mass"] = float(diag[0])
     del lat
     torch.cuda.empty_cache()
