@@ -221,7 +221,7 @@ int lbm_wall_count(const lbm_ctx *ctx);
 /* Vortex-method inflow perturbation of the velocity inlet (Sec. 2.2.2; needs
  * open_x).  n seed points on the inflow plane: yz host double [n][2], the
  * (y, z) position in cell units (cell j spans [j, j + 1), its centre is
- * j + 1/2), sign host int [n] (>= 0 for +1, < 0 for -1), turbulence
+ * j + 1/2; 0 <= y <= ny, 0 <= z <= nz), sign host int [n] (>= 0 for +1, < 0 for -1), turbulence
  * intensity I >= 0, vortex size sigma > 0 (cells).  The library computes
  * k_i = 3/2 (|u_mean(p_i)| I)^2 from the log-law profile at z_i and
  * Gamma_i = 4 s_i sqrt(pi / (6 ln 3 - 9 ln 2) k_i A / n), A = ny nz, and from

@@ -474,6 +474,11 @@ struct Sim : SimBase {
       err = "vortices need open x faces, n >= 0, positions and signs, sigma > 0 and intensity >= 0";
       return ORC_EINVAL;
     }
+    for (int i = 0; i < n; ++i)
+      if (!(yz[2 * i] >= 0.0 && yz[2 * i] <= p.ny && yz[2 * i + 1] >= 0.0 && yz[2 * i + 1] <= p.nz)) {
+        err = "vortex positions must lie on the inflow plane";
+        return ORC_EINVAL;
+      }
     const double pi = 3.14159265358979323846;
     vy.assign(n, 0.0);
     vz.assign(n, 0.0);

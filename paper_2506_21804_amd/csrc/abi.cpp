@@ -610,8 +610,9 @@ int lbm_set_inflow_vortices(lbm_ctx *ctx, int n, const double *yz, const int *si
     return set_err(ctx, LBM_EINVAL, "vortex count must be in [0, LBM_MAX_VORTICES] with positions and signs");
   if (!(sigma > 0.0) || !std::isfinite(sigma) || !(intensity >= 0.0) || !std::isfinite(intensity))
     return set_err(ctx, LBM_EINVAL, "vortices need sigma > 0 and intensity >= 0, both finite");
-  for (int i = 0; i < 2 * n; ++i)
-    if (!std::isfinite(yz[i])) return set_err(ctx, LBM_EINVAL, "vortex positions must be finite");
+  for (int i = 0; i < n; ++i)
+    if (!(yz[2 * i] >= 0.0 && yz[2 * i] <= ctx->p.ny && yz[2 * i + 1] >= 0.0 && yz[2 * i + 1] <= ctx->p.nz))
+      return set_err(ctx, LBM_EINVAL, "vortex positions must lie on the inflow plane, 0 <= y <= ny, 0 <= z <= nz");
   // circulations: k_i = 3/2 (|u_mean(z_i)| I)^2, Gamma_i = 4 s_i sqrt(pi / (6 ln 3 - 9 ln 2) k_i A / n)
   const double pi = 3.14159265358979323846;
   const double A = (double)ctx->p.ny * ctx->p.nz;

@@ -162,6 +162,7 @@ def test_vortex_arguments_checked(gpu):
     lat = gpu.Lattice(case, storage="f64")
     yz, sign = np.array([[1.0, 1.0]]), np.array([1])
     for bad in ((yz, sign, 0.1, 0.0), (yz, sign, -0.1, 1.0), (np.array([[np.nan, 1.0]]), sign, 0.1, 1.0),
+                (np.array([[1.0, -0.5]]), sign, 0.1, 1.0), (np.array([[3.5, 1.0]]), sign, 0.1, 1.0),
                 (np.zeros((gpu.MAX_VORTICES + 1, 2)), np.ones(gpu.MAX_VORTICES + 1), 0.1, 1.0)):
         with pytest.raises(gpu.LbmError) as e:
             lat.set_vortices(*bad)

@@ -160,7 +160,8 @@ def test_vortex_inlet_exact(q, collision):
 def test_vortices_validated():
     p = O.make_params(19, (6, 4, 4), periodic=(0, 1, 1), tau0=0.6, u_ref=0.05, z0=1.0, open_x=1)
     s = O.Oracle(p)
-    for args in (([(1.0, 1.0)], [1], 0.1, 0.0), ([(1.0, 1.0)], [1], -0.1, 1.0)):
+    for args in (([(1.0, 1.0)], [1], 0.1, 0.0), ([(1.0, 1.0)], [1], -0.1, 1.0), ([(1.0, -0.5)], [1], 0.1, 1.0),
+                 ([(4.5, 1.0)], [1], 0.1, 1.0)):
         with pytest.raises(O.OracleError):
             s.set_vortices(*args)
     closed = O.Oracle(O.make_params(19, (6, 4, 4), tau0=0.6))
