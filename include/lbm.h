@@ -209,6 +209,14 @@ int lbm_adjoint_from_natural(lbm_ctx *ctx, const void *natural, void *lambda);
 int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
                  void *grad_phi, double *J, long long *nforward);
 
+/* The same sweep for the time-averaged objective J = (1/T) sum_{t=1..T} j(f_t),
+ * with j the terminal objective above: the forward values are summed on the
+ * schedule's first descent, and each reverse step t >= 1 adds j'(f_t)/T to
+ * lambda inside the adjoint kernel.  *J receives the average.  Same
+ * arguments, conditions and synchronisation as lbm_gradient. */
+int lbm_gradient_mean(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
+                      void *grad_phi, double *J, long long *nforward);
+
 /* The forward-step count of the optimal binomial schedule for T steps and
  * nsnap snapshot slots (host only; the starting state occupies one slot). */
 long long lbm_revolve_cost(int T, int nsnap);

@@ -20,7 +20,7 @@ __all__ = [
     "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes",
     "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural",
     "lbm_gradient", "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
-    "lbm_set_inflow_vortices", "lbm_last_error", "lbm_free",
+    "lbm_set_inflow_vortices", "lbm_gradient_mean", "lbm_last_error", "lbm_free",
     "Lattice", "D3Q19", "D3Q27", "F64", "F32DEV", "F16DEV",
 ]
 
@@ -103,6 +103,7 @@ def load():
         "lbm_profile": (i, [vp, i]),
         "lbm_profile_read": (i, [vp, vp, vp]),
         "lbm_set_inflow_vortices": (i, [vp, i, vp, vp, d, d]),
+        "lbm_gradient_mean": (i, [vp, i, vp, vp, i, vp, vp, C.POINTER(d), C.POINTER(ll)]),
         "lbm_last_error": (C.c_char_p, [vp]),
         "lbm_free": (None, [vp]),
     }
@@ -120,7 +121,7 @@ def exported_symbols():
             "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes", "lbm_adjoint_seed",
             "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural", "lbm_gradient",
             "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
-            "lbm_set_inflow_vortices", "lbm_last_error", "lbm_free"]
+            "lbm_set_inflow_vortices", "lbm_gradient_mean", "lbm_last_error", "lbm_free"]
 
 
 def _dptr(t):
@@ -316,6 +317,17 @@ def lbm_gradient(ctx, T, planes, snapshots, nsnap, lam, grad):
     snaps = _dbuf(snapshots, int(nsnap) * lbm_state_bytes(ctx), "snapshots")
     _check(ctx, load().lbm_gradient(ctx, int(T), pl, snaps, int(nsnap), _lam(ctx, lam), _grad(ctx, grad),
                                     C.byref(J), C.byref(nf)))
+    return J.value, nf.value
+
+
+def lbm_gradient_mean(ctx, T, planes, snapshots, nsnap, lam, grad):
+    """As lbm_gradient, for the time average (1/T) sum_{t=1..T} j(f_t)."""
+    pl = (C.c_int * 2)(*planes)
+    J = C.c_double()
+    nf = C.c_longlong()
+    snaps = _dbuf(snapshots, int(nsnap) * lbm_state_bytes(ctx), "snapshots")
+    _check(ctx, load().lbm_gradient_mean(ctx, int(T), pl, snaps, int(nsnap), _lam(ctx, lam), _grad(ctx, grad),
+                                         C.byref(J), C.byref(nf)))
     return J.value, nf.value
 
 

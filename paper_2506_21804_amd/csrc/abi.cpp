@@ -527,8 +527,13 @@ int lbm_adjoint_from_natural(lbm_ctx *ctx, const void *natural, void *lambda) {
 
 long long lbm_revolve_cost(int T, int nsnap) { return revolve_cost(T, nsnap); }
 
-int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
-                 void *grad_phi, double *J, long long *nforward) {
+// Checkpointed reverse sweep for the terminal objective J = j(f_T) or, with
+// mean, the time average J = (1/T) sum_{t=1..T} j(f_t).  The average's
+// forward values are summed on the schedule's first descent (the first time
+// each step index is reached); its seeds enter the reverse steps t = T-1 .. 1
+// fused into the adjoint kernel, and the terminal seed is scaled by 1/T.
+static int gradient_sweep(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
+                          void *grad_phi, double *J, long long *nforward, bool mean) {
   if (!ctx) return LBM_EINVAL;
   if (T < 1 || nsnap < 1 || !snapshots || !lambda || !grad_phi || !planes)
     return set_err(ctx, LBM_EINVAL, "gradient needs T >= 1, nsnap >= 1 and non-null buffers");
@@ -551,10 +556,12 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
   // checkpoint is advanced back to T-1 and the reverse sweep starts.
   const std::vector<Action> acts = revolve_schedule(T, nsnap);
   long long have = 0;  // step index held by the context, relative to step0
+  long long seen = 0;  // largest step index reached so far
   int last_slot = 0;
   long long last_step = 0;
   bool seeded = false;
-  double Jv = 0.0;
+  double Jv = 0.0, Jsum = 0.0;
+  const double w = mean ? 1.0 / T : 1.0;
   for (const Action &a : acts) {
     switch (a.kind) {
       case ACT_RESTORE:
@@ -566,6 +573,20 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
         }
         break;
       case ACT_ADVANCE:
+        if (mean && have + a.arg > seen) {
+          // one step at a time through states not seen yet, summing j(f_t)
+          for (int s = 0; s < a.arg; ++s) {
+            if ((rc = lbm_step(ctx, 1)) != LBM_OK) return rc;
+            ++fwd;
+            if (++have > seen) {
+              double jt;
+              if ((rc = lbm_objective(ctx, planes, &jt)) != LBM_OK) return rc;
+              Jsum += jt;
+              seen = have;
+            }
+          }
+          break;
+        }
         if ((rc = lbm_step(ctx, a.arg)) != LBM_OK) return rc;
         fwd += a.arg;
         have += a.arg;
@@ -579,7 +600,8 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
           if ((rc = lbm_step(ctx, 1)) != LBM_OK) return rc;
           fwd += 1;
           if ((rc = lbm_objective(ctx, planes, &Jv)) != LBM_OK) return rc;
-          if ((rc = lbm_adjoint_seed(ctx, planes, lambda)) != LBM_OK) return rc;
+          Jsum += Jv;
+          if ((rc = dev_adjoint_seed(ctx, planes, lambda, w)) != LBM_OK) return rc;
           if ((rc = lbm_load_state(ctx, slot(last_slot))) != LBM_OK) return rc;
           if (T - 1 > last_step) {
             if ((rc = lbm_step(ctx, (int)(T - 1 - last_step))) != LBM_OK) return rc;
@@ -589,15 +611,27 @@ int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int 
           seeded = true;
         }
         if (ctx->steps != step0 + a.arg) return set_err(ctx, LBM_EINVAL, "internal: schedule out of step");
-        if ((rc = dev_adjoint_step(ctx, lambda, grad_phi)) != LBM_OK) return rc;
+        // the seed of step t (t >= 1) joins the reverse step that produces dJ/df_t
+        if ((rc = dev_adjoint_step(ctx, lambda, grad_phi, mean && a.arg >= 1 ? w : 0.0, planes)) != LBM_OK)
+          return rc;
         break;
     }
   }
   if ((rc = lbm_load_state(ctx, slot(0))) != LBM_OK) return rc;
   if ((rc = sync_and_check(ctx)) != LBM_OK) return rc;
-  if (J) *J = Jv;
+  if (J) *J = mean ? Jsum / T : Jv;
   if (nforward) *nforward = fwd;
   return LBM_OK;
+}
+
+int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
+                 void *grad_phi, double *J, long long *nforward) {
+  return gradient_sweep(ctx, T, planes, snapshots, nsnap, lambda, grad_phi, J, nforward, false);
+}
+
+int lbm_gradient_mean(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
+                      void *grad_phi, double *J, long long *nforward) {
+  return gradient_sweep(ctx, T, planes, snapshots, nsnap, lambda, grad_phi, J, nforward, true);
 }
 
 int lbm_wall_count(const lbm_ctx *ctx) { return ctx ? ctx->nwall : -1; }

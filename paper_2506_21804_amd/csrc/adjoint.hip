@@ -436,12 +436,51 @@ __device__ __forceinline__ int writer_of(const Nb &n, unsigned sm, int i) {
   return n.cell + nb_off<Q>(n, i, +1);
 }
 
-template <int Q, typename S, bool ODD, bool POROUS, bool SOLID, bool RR>
+// Seed of the objective J = c_s^2 (<rho>_{x=p0} - <rho>_{x=p1}) + <rho |u|^2 / 2>
+// at one cell, scaled by w: the part common to all populations (the density
+// terms) and the kinetic-energy part of population i, (c_i.u - |u|^2/2) / n_fluid.
+struct CellSeed {
+  double base, ux, uy, uz, uu, inf;
+  template <int Q>
+  __device__ __forceinline__ double kin(int i) const {
+    return (dot3(Lat<Q>::c(i, 0), Lat<Q>::c(i, 1), Lat<Q>::c(i, 2), ux, uy, uz) - 0.5 * uu) * inf;
+  }
+};
+template <int Q, typename R>
+__device__ __forceinline__ CellSeed cell_seed(const R g[Q], int x, int p0, int p1, const double *cnt, double w,
+                                              const KArgs &k) {
+  double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double gi = (double)g[i];
+    drho += gi;
+    acc(jx, Lat<Q>::c(i, 0), gi);
+    acc(jy, Lat<Q>::c(i, 1), gi);
+    acc(jz, Lat<Q>::c(i, 2), gi);
+  }
+  const double rho = 1.0 + drho;
+  CellSeed c;
+  c.ux = (jx + 0.5 * k.F[0]) / rho;
+  c.uy = (jy + 0.5 * k.F[1]) / rho;
+  c.uz = (jz + 0.5 * k.F[2]) / rho;
+  c.uu = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
+  c.base = 0.0;
+  if (x == p0) c.base += w / (3.0 * cnt[0]);
+  if (x == p1) c.base -= w / (3.0 * cnt[1]);
+  c.inf = w / cnt[2];
+  return c;
+}
+
+// SEED = true (time-averaged objectives): the step also adds w dJ/df of the
+// state it reads (the objective's seed at that step), after the transpose.
+template <int Q, typename S, bool ODD, bool POROUS, bool SOLID, bool RR, bool SEED = false>
 __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                     typename Store<S>::R *__restrict__ dev,
                                                     const double *__restrict__ m_prev, double *__restrict__ m_next,
                                                     const typename Store<S>::R *__restrict__ phi,
-                                                    double *__restrict__ grad, KArgs k, ATiles t) {
+                                                    double *__restrict__ grad, KArgs k, ATiles t, int p0 = 0,
+                                                    int p1 = 0, const double *__restrict__ cnt = nullptr,
+                                                    double sw = 0.0) {
   using R = typename Store<S>::R;
   int x, y, z;
   if (!atile_xyz(k, t, x, y, z)) return;
@@ -452,7 +491,17 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
   if (SOLID && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
   const size_t N = (size_t)k.N;
   if (fl & FL_LID) {
-    // the lid output does not depend on the state
+    // the lid output does not depend on the state: only the seed remains
+    if constexpr (SEED) {
+      R g[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+      const CellSeed cs = cell_seed<Q, R>(g, x, p0, p1, cnt, sw, k);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) dev[read_slot<Q, ODD>(n, sm, i, N)] = (R)cs.template kin<Q>(i);
+      m_next[n.cell] = cs.base;
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) dev[read_slot<Q, ODD>(n, sm, i, N)] = R(0);
     m_next[n.cell] = 0.0;
@@ -476,11 +525,16 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
 #pragma unroll
   for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
   const R ph = POROUS ? phi[n.cell] : R(1);
-  auto store = [&](int i, R v) { dev[read_slot<Q, ODD>(n, sm, i, N)] = v; };
+  CellSeed cs{};
+  if constexpr (SEED) cs = cell_seed<Q, R>(g, x, p0, p1, cnt, sw, k);
+  auto store = [&](int i, R v) {
+    if constexpr (SEED) v += (R)cs.template kin<Q>(i);
+    dev[read_slot<Q, ODD>(n, sm, i, N)] = v;
+  };
   R phib;
   if constexpr (RR) phib = collide_bulk_rr_vjp<Q, R, POROUS>(g, dmu, ph, k, store);
   else phib = collide_bulk_vjp<Q, R, POROUS>(g, dmu, ph, k, store);
-  m_next[n.cell] = m;
+  m_next[n.cell] = SEED ? m + cs.base : m;
   if (POROUS) grad[n.cell] += (double)phib;
 }
 
@@ -491,7 +545,7 @@ template <int Q, typename S, bool ODD, bool SOLID>
 __global__ __launch_bounds__(ABLOCK) void k_seed(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                  typename Store<S>::R *__restrict__ dev, double *__restrict__ m_cur, KArgs k,
                                                  ATiles t, int p0,
-                                                 int p1, const double *__restrict__ cnt) {
+                                                 int p1, const double *__restrict__ cnt, double w) {
   int x, y, z;
   if (!atile_xyz(k, t, x, y, z)) return;
   const Nb n = make_nb(x, y, z, k);
@@ -514,9 +568,9 @@ __global__ __launch_bounds__(ABLOCK) void k_seed(const S *__restrict__ pop, cons
   const double ux = (jx + 0.5 * k.F[0]) / rho, uy = (jy + 0.5 * k.F[1]) / rho, uz = (jz + 0.5 * k.F[2]) / rho;
   const double uu = ux * ux + uy * uy + uz * uz;
   double base = 0.0;
-  if (x == p0) base += 1.0 / (3.0 * cnt[0]);
-  if (x == p1) base -= 1.0 / (3.0 * cnt[1]);
-  const double inf = 1.0 / cnt[2];
+  if (x == p0) base += w / (3.0 * cnt[0]);
+  if (x == p1) base -= w / (3.0 * cnt[1]);
+  const double inf = w / cnt[2];
   using R = typename Store<S>::R;
   m_cur[n.cell] = base;  // common mode; the deviations carry the kinetic-energy part
 #pragma unroll
@@ -605,7 +659,7 @@ static AdjPtrs adj_ptrs(lbm_ctx *ctx, void *lamv) {
   return {odd ? m1 : m0, odd ? m0 : m1, (char *)lamv + L.d_off};
 }
 
-int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv) {
+int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const int *planes) {
   const ATiles t = atiles_of(ctx->ka);
   const AdjPtrs a = adj_ptrs(ctx, lamv);
   return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
@@ -614,22 +668,28 @@ int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv) {
     double *grad = (double *)gradv;
     const R *phi = (const R *)ctx->phi;
     // reads the common modes of the later state (the other parity), writes this parity's
+    const int p0 = planes ? planes[0] : 0, p1 = planes ? planes[1] : 0;
+    const double *cnt = ctx->result + 8 + 3;  // fluid-cell counts of the last objective evaluation
     auto go = [&](auto kern) {
       kern<<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, dev, a.m_other, a.m_cur, phi,
-                                                  grad, ctx->ka, t);
+                                                  grad, ctx->ka, t, p0, p1, cnt, seed_w);
+    };
+    auto by_seed = [&]<bool POROUS, bool RR>() {
+      if (seed_w != 0.0) go(k_adjoint<Q, S, ODD, POROUS, SOLID, RR, true>);
+      else go(k_adjoint<Q, S, ODD, POROUS, SOLID, RR, false>);
     };
     if (ctx->porous) {
-      if (ctx->ka.rr) go(k_adjoint<Q, S, ODD, true, SOLID, true>);
-      else go(k_adjoint<Q, S, ODD, true, SOLID, false>);
+      if (ctx->ka.rr) by_seed.template operator()<true, true>();
+      else by_seed.template operator()<true, false>();
     } else {
-      if (ctx->ka.rr) go(k_adjoint<Q, S, ODD, false, SOLID, true>);
-      else go(k_adjoint<Q, S, ODD, false, SOLID, false>);
+      if (ctx->ka.rr) by_seed.template operator()<false, true>();
+      else by_seed.template operator()<false, false>();
     }
     return check(ctx, "k_adjoint");
   });
 }
 
-int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lamv) {
+int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lamv, double w) {
   int rc = dev_objective(ctx, planes);  // fills the fluid-cell counts
   if (rc != LBM_OK) return rc;
   const ATiles t = atiles_of(ctx->ka);
@@ -638,7 +698,7 @@ int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lamv) {
     using R = typename Store<S>::R;
     k_seed<Q, S, ODD, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, (R *)a.dev,
                                                                    a.m_cur, ctx->ka, t, planes[0], planes[1],
-                                                                   ctx->result + 8 + 3);
+                                                                   ctx->result + 8 + 3, w);
     return check(ctx, "k_seed");
   });
 }

@@ -166,8 +166,11 @@ int dev_export(lbm_ctx *ctx, void *f);
 int dev_import(lbm_ctx *ctx, const void *f);
 int dev_layout_to_natural(lbm_ctx *ctx, const void *lam, void *nat);
 int dev_layout_from_natural(lbm_ctx *ctx, const void *nat, void *lam);
-int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lam);
-int dev_adjoint_step(lbm_ctx *ctx, void *lam, void *grad);
+// seed of the terminal objective, times w
+int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lam, double w = 1.0);
+// one reverse step; seed_w != 0 also adds seed_w dJ/df of the state held
+// (planes and the fluid-cell counts of the last objective evaluation)
+int dev_adjoint_step(lbm_ctx *ctx, void *lam, void *grad, double seed_w = 0.0, const int *planes = nullptr);
 int dev_fill(lbm_ctx *ctx, void *ptr, size_t bytes);  // zero fill with a kernel
 int dev_write_header(lbm_ctx *ctx, void *dst);
 

@@ -4,7 +4,8 @@
  - transpose test: <L v, w> from the oracle's tangent step equals <v, L^T w>
    from one GPU reverse step (populations and porosity directions), FP64;
  - the checkpointed GPU gradient dJ/dphi equals the oracle's tangent
-   derivative at sampled cells (FP64, 1e-10);
+   derivative at sampled cells (FP64, 1e-10), for the terminal objective
+   and for its time average over the trajectory;
  - the checkpointed gradient is bitwise equal to the full-storage one, and
    the sweep takes the binomial-optimal number of forward steps (plus the
    step to T and the re-advance to T-1);
@@ -98,6 +99,47 @@ def test_gradient_matches_oracle_tangent(gpu, collision):
     assert lat.steps == 0  # the context is back at step 0
 
 
+@pytest.mark.parametrize("collision", [0, 1])
+def test_gradient_mean_matches_oracle_tangent(gpu, collision):
+    """Time-averaged objective J = (1/T) sum_{t=1..T} j(f_t): value and
+    gradient against the oracle summed step by step (value; dual-number
+    derivative along unit porosity directions), FP64, with a schedule that
+    recomputes (T = 23 steps on 3 snapshot slots)."""
+    case = _case((16, 12, 8), collision=collision)
+    planes = (2, 13)
+    T, nsnap = 23, 3
+    lat = gpu.Lattice(case, storage="f64")
+    N = case.ncells
+    lam = lat.new_adjoint()
+    grad = torch.zeros(N, dtype=torch.float64, device="cuda")
+    snaps = lat.new_state_buffer(nsnap)
+    J, nfwd = gpu.lbm_gradient_mean(lat.ctx, T, planes, snaps, nsnap, lam, grad)
+    g = grad.cpu().numpy()
+    _, nfwd_terminal = gpu.lbm_gradient(lat.ctx, T, planes, snaps, nsnap, lam, torch.zeros_like(grad))
+    assert nfwd == nfwd_terminal
+    orc = oracle_for(case)
+    Jo = 0.0
+    for _ in range(T):
+        orc.step(1)
+        Jo += orc.objective(planes)[0]
+    Jo /= T
+    announce(f"mean objective collision={collision}: gpu {J:.15e} oracle {Jo:.15e}")
+    assert abs(J - Jo) <= 1e-12 * abs(Jo)
+    for cell in I.sample_cells(N, 5, seed_offset=6):
+        t = oracle_for(case, tangent=True)
+        e = np.zeros(N)
+        e[cell] = 1.0
+        t.set_phi_tangent(e)
+        dJ = 0.0
+        for _ in range(T):
+            t.step(1)
+            dJ += t.objective(planes)[1]
+        dJ /= T
+        announce(f"mean objective cell {cell}: gpu {g[cell]:.12e} tangent {dJ:.12e}")
+        assert abs(g[cell] - dJ) <= 1e-10 * max(abs(dJ), 1e-3 * np.abs(g).max())
+    assert lat.steps == 0
+
+
 def test_checkpointed_equals_full_storage(gpu):
     case = _case((16, 12, 8))
     planes = (2, 13)
@@ -183,3 +225,20 @@ def test_autograd_function(gpu):
     _, dJ = t.objective(planes)
     g = phi.grad.numpy()
     assert abs(g[cell] - dJ) <= 1e-10 * max(abs(dJ), 1e-3 * np.abs(g).max())
+
+
+def test_autograd_function_mean(gpu):
+    """objective(..., mean=True): the forward value without a gradient equals
+    the one with it, and backward gives lbm_gradient_mean's dJ/dphi."""
+    from paper_2506_21804_amd.autograd import objective
+    case = _case((16, 12, 8))
+    planes = (2, 13)
+    phi = torch.tensor(case.porosity, dtype=torch.float64, requires_grad=True)
+    J = objective(phi, case, storage="f64", T=9, planes=planes, nsnap=3, mean=True)
+    J.backward()
+    J_nograd = objective(phi.detach(), case, storage="f64", T=9, planes=planes, nsnap=3, mean=True)
+    assert abs(J.item() - J_nograd.item()) <= 1e-13 * abs(J.item())
+    lat = gpu.Lattice(case, storage="f64")
+    grad = torch.zeros(case.ncells, dtype=torch.float64, device="cuda")
+    gpu.lbm_gradient_mean(lat.ctx, 9, planes, lat.new_state_buffer(3), 3, lat.new_adjoint(), grad)
+    np.testing.assert_array_equal(phi.grad.numpy(), grad.cpu().numpy())
