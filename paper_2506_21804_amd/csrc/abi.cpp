@@ -658,7 +658,8 @@ int lbm_set_inflow_vortices(lbm_ctx *ctx, int n, const double *yz, const int *si
     const double k = 1.5 * (um * intensity) * (um * intensity);
     v[3 * i] = yz[2 * i];
     v[3 * i + 1] = z;
-    v[3 * i + 2] = 4.0 * (sign[i] >= 0 ? 1.0 : -1.0) * std::sqrt(pi / (6.0 * std::log(3.0) - 9.0 * std::log(2.0)) * k * A / n);
+    const double c = pi / (6.0 * std::log(3.0) - 9.0 * std::log(2.0));
+    v[3 * i + 2] = 4.0 * (sign[i] >= 0 ? 1.0 : -1.0) * std::sqrt(c * k * A / n);
   }
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");

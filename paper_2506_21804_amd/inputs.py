@@ -208,7 +208,8 @@ def urban(nx: int = 768, ny: int = 768, nz: int = 256, q: int = 27, seed_offset:
     periodic x with a fringe over the last ``fringe_len`` planes, periodic y,
     lid layer on top (with ``open_x``: a velocity inlet at x = 0 and a
     pressure outlet at x = nx - 1 instead of the periodic x axis, the fringe
-    kept before the outlet; the wall distance still treats x as unbounded); initial velocity u_ref ln(1 + z_c/z0)/ln(1 + z_top/z0)
+    kept before the outlet; the wall distance still treats x as unbounded);
+    initial velocity u_ref ln(1 + z_c/z0)/ln(1 + z_top/z0)
     in x (z_c = z + 1/2, z_top = nz - 1/2, z0 = 1) in fluid cells.
 
     C_S defaults to 0.2: with the BGK collision, nu = 1e-4 and wall-modeled
