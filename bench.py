@@ -69,6 +69,22 @@ def make_case(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def measured_traffic(workload, collision, fd_weight, profiles=None):
+    """HBM bytes per bulk launch from the committed counter file of this
+    workload, or None.  Counter-measured bytes apply only to the kernel they
+    were taken on: the same sources, workload, collision and
+    finite-difference weight."""
+    tf = os.path.join(profiles or os.path.join(ROOT, "profiles"), f"k_bulk_{workload}_traffic.json")
+    if not os.path.exists(tf):
+        return None
+    with open(tf) as fh:
+        t = json.load(fh)
+    if (t.get("kernel_hash") == kernel_source_hash() and t.get("collision") == collision
+            and t.get("fd_weight") == fd_weight):
+        return t.get("bytes_per_launch")
+    return None
+
+
 def open_face_cells(case):
     """Fluid cells of the inlet and outlet planes that are not lid cells (the
     open-face kernel updates them, the bulk kernel skips them)."""
@@ -250,16 +266,7 @@ def main():
     k2_bytes = N * 1 + (nfluid - nwall - n_open) * 2 * q * sb + (nfluid * 3 * rb if fdw > 0 else 0)
     achieved = k2_bytes / (k2_ms * 1e-3) / 1e9
     step_bytes = nfluid * (2 * q * sb + 1) + (nfluid * (q * sb + 6 * rb) if fdw > 0 else 0)
-    # counter-measured bytes apply only to the kernel they were taken on: the
-    # same sources, workload, collision and finite-difference weight
-    traffic = None
-    tf = os.path.join(ROOT, "profiles", f"k_bulk_{args.workload}_traffic.json")
-    if os.path.exists(tf):
-        with open(tf) as fh:
-            t = json.load(fh)
-        if (t.get("kernel_hash") == kernel_source_hash() and t.get("collision") == args.collision
-                and t.get("fd_weight") == fdw):
-            traffic = t.get("bytes_per_launch")
+    traffic = measured_traffic(args.workload, args.collision, fdw)
     diag = lat.diagnostics()
     out = {
         "metric": "MLUPS (million lattice-cell updates per second) per GPU",
