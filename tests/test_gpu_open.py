@@ -88,6 +88,14 @@ def test_open_urban_crop(gpu, collision, storage, tol, steps):
     _check(f"open urban collision={collision} {storage}", moment_errors(rho, u, orho, ou), tol)
 
 
+@pytest.mark.parametrize("collision", [0, 1])
+def test_open_urban_crop_d3q19(gpu, collision):
+    """The same canopy with open faces on D3Q19 (FP64)."""
+    case = _urban_open(q=19, collision=collision)
+    _, rho, u, orho, ou = _run_both(gpu, case, 41, "f64")
+    _check(f"open urban d3q19 collision={collision} f64", moment_errors(rho, u, orho, ou), 1e-12)
+
+
 def test_open_urban_fp16(gpu):
     """FP16 deviation storage: reported against the oracle with a loose bound."""
     case = _urban_open()
@@ -137,6 +145,23 @@ def test_vortex_inlet_urban_crop(gpu, collision, storage, tol, steps):
     # the perturbation reaches the inlet plane's neighbours
     x = np.arange(case.ncells) % case.shape[0]
     assert np.abs(ou[1:, x == 1]).max() > 1e-4
+
+
+def test_vortex_inlet_fp16(gpu):
+    """FP16 deviation storage with the vortex method: loose bound, as for FP16."""
+    case = _urban_open()
+    yz, sign = _vortices(case, 40, 12)
+    lat = gpu.Lattice(case, storage="f16", wall_dist="case")
+    lat.set_vortices(yz, sign, 0.2, 3.0)
+    lat.step(100)
+    rho, u = lat.moments()
+    orc = oracle_for(case, 0, wall_dist=case.wall_dist)
+    orc.set_vortices(yz, sign, 0.2, 3.0)
+    orc.step(100)
+    orho, ou = orc.moments()
+    e_rho, e_u, _ = moment_errors(rho.cpu().numpy().astype(np.float64), u.cpu().numpy().astype(np.float64), orho, ou)
+    announce(f"vortex urban f16: rho {e_rho:.3e} u {e_u:.3e}")
+    assert e_rho < 5e-3 and e_u < 5e-2
 
 
 def test_vortex_reset_and_clear(gpu):
