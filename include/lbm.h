@@ -204,8 +204,8 @@ int lbm_adjoint_from_natural(lbm_ctx *ctx, const void *natural, void *lambda);
  * checkpoint to T-1.  *J receives the objective at step T and *nforward the
  * forward steps taken (lbm_revolve_cost(T, nsnap) + 1 + that re-advance; T
  * exactly when nsnap > T).  On return the context holds the state of step 0
- * again.  Synchronises.  Not available with the wall model, the hybrid
- * collision or open x faces. */
+ * again.  Synchronises.  Not available with the wall model or the hybrid
+ * collision. */
 int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
                  void *grad_phi, double *J, long long *nforward);
 

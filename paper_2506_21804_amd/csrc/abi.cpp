@@ -507,7 +507,6 @@ int lbm_adjoint_step(lbm_ctx *ctx, void *lambda, void *grad_phi) {
   if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
   if (ctx->ka.fdw > 0.0)
     return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the finite-difference strain");
-  if (ctx->has_open) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the open x faces");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   return dev_adjoint_step(ctx, lambda, grad_phi);
@@ -540,7 +539,6 @@ static int gradient_sweep(lbm_ctx *ctx, int T, const int planes[2], void *snapsh
   if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
   if (ctx->ka.fdw > 0.0)
     return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the finite-difference strain");
-  if (ctx->has_open) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the open x faces");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   const size_t sb = lbm_state_bytes(ctx);

@@ -436,6 +436,204 @@ __device__ __forceinline__ int writer_of(const Nb &n, unsigned sm, int i) {
   return n.cell + nb_off<Q>(n, i, +1);
 }
 
+// Open x faces: the rebuild of an inlet or outlet cell's pre-collision
+// deviations (the same map as in the bulk kernel: regularized inlet at the
+// prescribed velocity, equilibrium outlet at rho_out) and the transpose of
+// its Jacobian.  With n the outward normal, the known populations are those
+// with c.n >= 0; m = G_0 + 2 G_+ sums them (G_0 over c.n = 0, G_+ over the
+// ones leaving through the face), and rho (1 + u.n) = 1 + m.
+template <int Q, typename R, bool RR>
+struct OpenMap {
+  static constexpr int H = (Q - 1) / 2;
+  bool outlet;
+  int nxo;                  // x component of the outward normal
+  R drho, rho, ux, uy, uz;  // rebuilt density and velocity
+  R K[7];                   // third-order coefficients of the unit-density equilibrium (RR)
+  __device__ __forceinline__ OpenMap(const R g[Q], bool out, int y, int z, const KArgs &k) : outlet(out) {
+    nxo = outlet ? 1 : -1;
+    R m = g[0];
+#pragma unroll
+    for (int i = 1; i <= H; ++i) {
+      const int cx = Lat<Q>::c(i, 0);
+      if (cx == 0) m += g[i] + g[i + H];
+      else m += R(2) * (cx * nxo > 0 ? g[i] : g[i + H]);
+    }
+    uy = R(0);
+    uz = R(0);
+    if (outlet) {
+      drho = R(k.rho_out - 1.0);
+      rho = R(1) + drho;
+      ux = (m - drho) / rho;
+    } else {
+      const R *f = static_cast<const R *>(k.inflow);
+      const int face = k.ny * k.nz, c2 = y + k.ny * z;
+      ux = f[c2];
+      uy = f[face + c2];
+      uz = f[2 * face + c2];
+      drho = (m + ux) / (R(1) - ux);  // u.n = -ux
+      rho = R(1) + drho;
+    }
+    if constexpr (RR) {
+      R A[7];
+      cube_tensor(R(1), ux, uy, uz, A);
+      third_coefs<Q, R>(A, K);
+    }
+  }
+  // unit-density equilibrium parts of direction i <= H: even e, odd o
+  // (f^eq_i - w_i = w_i (drho + rho (e + o)), f^eq_ibar: o -> -o)
+  __device__ __forceinline__ void unit(int i, R &e, R &o) const {
+    const R cu = dot3(Lat<Q>::c(i, 0), Lat<Q>::c(i, 1), Lat<Q>::c(i, 2), ux, uy, uz);
+    const R uu = ux * ux + uy * uy + uz * uz;
+    e = R(4.5) * cu * cu - R(1.5) * uu;
+    o = R(3) * cu;
+    if constexpr (RR) o += third_term<Q, R>(i, K);
+  }
+  __device__ __forceinline__ void geq(R out[Q]) const {
+    const R uu = ux * ux + uy * uy + uz * uz;
+    out[0] = R(Lat<Q>::w(0)) * (drho - R(1.5) * rho * uu);
+#pragma unroll
+    for (int i = 1; i <= H; ++i) {
+      R e, o;
+      unit(i, e, o);
+      const R w = R(Lat<Q>::w(i));
+      out[i] = w * (drho + rho * (e + o));
+      out[i + H] = w * (drho + rho * (e - o));
+    }
+  }
+  // rebuilt deviations
+  __device__ __forceinline__ void forward(const R g[Q], R out[Q]) const {
+    geq(out);
+    if (outlet) return;
+    R pxx = R(0), pyy = R(0), pzz = R(0), pxy = R(0), pxz = R(0), pyz = R(0);
+#pragma unroll
+    for (int i = 1; i <= H; ++i) {
+      const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+      R hs;
+      if (cx == 0) {
+        hs = (g[i] - out[i]) + (g[i + H] - out[i + H]);
+      } else {
+        const int kn = cx * nxo > 0 ? i : i + H;
+        hs = R(2) * (g[kn] - out[kn]);
+      }
+      acc(pxx, cx * cx, hs);
+      acc(pyy, cy * cy, hs);
+      acc(pzz, cz * cz, hs);
+      acc(pxy, cx * cy, hs);
+      acc(pxz, cx * cz, hs);
+      acc(pyz, cy * cz, hs);
+    }
+    const R tr3 = (pxx + pyy + pzz) * R(1.0 / 3.0);
+    out[0] -= R(4.5) * R(Lat<Q>::w(0)) * tr3;
+#pragma unroll
+    for (int i = 1; i <= H; ++i) {
+      const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+      R cPc = R(0);
+      acc(cPc, cx * cx, pxx);
+      acc(cPc, cy * cy, pyy);
+      acc(cPc, cz * cz, pzz);
+      acc(cPc, cx * cy, R(2) * pxy);
+      acc(cPc, cx * cz, R(2) * pxz);
+      acc(cPc, cy * cz, R(2) * pyz);
+      const R r = R(4.5) * R(Lat<Q>::w(i)) * (cPc - tr3);
+      out[i] += r;
+      out[i + H] += r;
+    }
+  }
+  // b: adjoint of the rebuilt deviations in, adjoint of the gathered ones out
+  // (the map is affine in the known populations at the inlet; at the outlet
+  // only through u.n, where this is the Jacobian at the current state)
+  __device__ __forceinline__ void transpose(R b[Q]) const {
+    R gb[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gb[i] = R(0);
+    R mb;
+    if (outlet) {
+      // f^eq_i(rho_out, (ux, 0, 0)): d/dux = w_i rho (3 c_x + 9 c_x^2 ux - 3 ux)
+      R uxb = R(0);
+#pragma unroll
+      for (int i = 1; i <= H; ++i) {
+        const R cx = R(Lat<Q>::c(i, 0));
+        const R w = R(Lat<Q>::w(i));
+        const R ev = R(9) * cx * cx * ux - R(3) * ux, od = R(3) * cx;
+        uxb += w * rho * ((ev + od) * b[i] + (ev - od) * b[i + H]);
+      }
+      uxb += R(Lat<Q>::w(0)) * rho * (-R(3) * ux) * b[0];
+      mb = uxb / rho;
+    } else {
+      // Pi adjoint: out_i += 9/2 w_i (c.Pi.c - tr Pi / 3)
+      R bxx = R(0), byy = R(0), bzz = R(0), bxy = R(0), bxz = R(0), byz = R(0);
+      const R third = R(1.0 / 3.0);
+      {
+        const R t = R(4.5) * R(Lat<Q>::w(0)) * b[0];
+        bxx -= t * third;
+        byy -= t * third;
+        bzz -= t * third;
+      }
+#pragma unroll
+      for (int i = 1; i <= H; ++i) {
+        const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+        const R t = R(4.5) * R(Lat<Q>::w(i)) * (b[i] + b[i + H]);
+        bxx += t * (R(cx * cx) - third);
+        byy += t * (R(cy * cy) - third);
+        bzz += t * (R(cz * cz) - third);
+        bxy += t * R(2 * cx * cy);
+        bxz += t * R(2 * cx * cz);
+        byz += t * R(2 * cy * cz);
+      }
+      // geq adjoint starts as b; the pair sums take the Pi adjoint back
+      R geqb[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) geqb[i] = b[i];
+#pragma unroll
+      for (int i = 1; i <= H; ++i) {
+        const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+        R hsb = R(0);
+        acc(hsb, cx * cx, bxx);
+        acc(hsb, cy * cy, byy);
+        acc(hsb, cz * cz, bzz);
+        acc(hsb, cx * cy, bxy);
+        acc(hsb, cx * cz, bxz);
+        acc(hsb, cy * cz, byz);
+        if (cx == 0) {
+          gb[i] += hsb;
+          gb[i + H] += hsb;
+          geqb[i] -= hsb;
+          geqb[i + H] -= hsb;
+        } else {
+          const int kn = cx * nxo > 0 ? i : i + H;
+          gb[kn] += R(2) * hsb;
+          geqb[kn] -= R(2) * hsb;
+        }
+      }
+      // f^eq at the prescribed velocity depends on drho only:
+      // d f^eq_i / d drho = w_i (1 + e + o)
+      R drhob = R(Lat<Q>::w(0)) * (R(1) - R(1.5) * (ux * ux + uy * uy + uz * uz)) * geqb[0];
+#pragma unroll
+      for (int i = 1; i <= H; ++i) {
+        R e, o;
+        unit(i, e, o);
+        const R w = R(Lat<Q>::w(i));
+        drhob += w * ((R(1) + e + o) * geqb[i] + (R(1) + e - o) * geqb[i + H]);
+      }
+      mb = drhob / (R(1) - ux);
+    }
+    // m = G_0 + 2 G_+
+    gb[0] += mb;
+#pragma unroll
+    for (int i = 1; i <= H; ++i) {
+      const int cx = Lat<Q>::c(i, 0);
+      if (cx == 0) {
+        gb[i] += mb;
+        gb[i + H] += mb;
+      } else {
+        gb[cx * nxo > 0 ? i : i + H] += R(2) * mb;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) b[i] = gb[i];
+  }
+};
+
 // Seed of the objective J = c_s^2 (<rho>_{x=p0} - <rho>_{x=p1}) + <rho |u|^2 / 2>
 // at one cell, scaled by w: the part common to all populations (the density
 // terms) and the kinetic-energy part of population i, (c_i.u - |u|^2/2) / n_fluid.
@@ -473,7 +671,7 @@ __device__ __forceinline__ CellSeed cell_seed(const R g[Q], int x, int p0, int p
 
 // SEED = true (time-averaged objectives): the step also adds w dJ/df of the
 // state it reads (the objective's seed at that step), after the transpose.
-template <int Q, typename S, bool ODD, bool POROUS, bool SOLID, bool RR, bool SEED = false>
+template <int Q, typename S, bool ODD, bool POROUS, bool SOLID, bool RR, bool SEED = false, bool OPEN = false>
 __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                     typename Store<S>::R *__restrict__ dev,
                                                     const double *__restrict__ m_prev, double *__restrict__ m_next,
@@ -508,7 +706,8 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
     return;
   }
   double scale = 1.0;
-  if (x >= k.fringe_start) scale = 1.0 - (double)static_cast<const R *>(k.lam)[x];
+  // the outlet plane is left out of the fringe
+  if (x >= k.fringe_start && !(OPEN && (fl & FL_OUTLET))) scale = 1.0 - (double)static_cast<const R *>(k.lam)[x];
   // mu_i = scale (M[writer_i] + d_i); the rest direction's writer is the cell itself
   const double mx = m_prev[n.cell];
   const double d0 = (double)dev[write_slot<Q, ODD>(n, sm, 0, N)];
@@ -532,6 +731,29 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
     dev[read_slot<Q, ODD>(n, sm, i, N)] = v;
   };
   R phib;
+  if constexpr (OPEN) {
+    if (fl & (FL_INLET | FL_OUTLET)) {
+      // open face: the collision acts on the rebuilt populations; the
+      // adjoint of the gathered ones is the transpose of the rebuild applied
+      // to m 1 + (VJP deviations), its common part taken in FP64
+      const OpenMap<Q, R, RR> om(g, (fl & FL_OUTLET) != 0, y, z, k);
+      R gre[Q];
+      om.forward(g, gre);
+      R ob[Q], one[Q];
+      auto collect = [&](int i, R v) { ob[i] = v; };
+      if constexpr (RR) phib = collide_bulk_rr_vjp<Q, R, POROUS>(gre, dmu, ph, k, collect);
+      else phib = collide_bulk_vjp<Q, R, POROUS>(gre, dmu, ph, k, collect);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) one[i] = R(1);
+      om.transpose(ob);
+      om.transpose(one);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) store(i, (R)(m * ((double)one[i] - 1.0)) + ob[i]);
+      m_next[n.cell] = SEED ? m + cs.base : m;
+      if (POROUS) grad[n.cell] += (double)phib;
+      return;
+    }
+  }
   if constexpr (RR) phib = collide_bulk_rr_vjp<Q, R, POROUS>(g, dmu, ph, k, store);
   else phib = collide_bulk_vjp<Q, R, POROUS>(g, dmu, ph, k, store);
   m_next[n.cell] = SEED ? m + cs.base : m;
@@ -675,6 +897,14 @@ int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const
                                                   grad, ctx->ka, t, p0, p1, cnt, seed_w);
     };
     auto by_seed = [&]<bool POROUS, bool RR>() {
+      // open x faces make x non-periodic, so their domains always have solid links
+      if constexpr (SOLID) {
+        if (ctx->has_open) {
+          if (seed_w != 0.0) go(k_adjoint<Q, S, ODD, POROUS, true, RR, true, true>);
+          else go(k_adjoint<Q, S, ODD, POROUS, true, RR, false, true>);
+          return;
+        }
+      }
       if (seed_w != 0.0) go(k_adjoint<Q, S, ODD, POROUS, SOLID, RR, true>);
       else go(k_adjoint<Q, S, ODD, POROUS, SOLID, RR, false>);
     };

@@ -12,7 +12,9 @@ import dataclasses
 
 import numpy as np
 import pytest
+import torch
 
+import oracle as O
 from paper_2506_21804_amd import inputs as I
 from gpu_helpers import announce, moment_errors, oracle_for
 
@@ -211,11 +213,76 @@ def test_vortex_arguments_checked(gpu):
         closed.set_vortices(yz, sign, 0.1, 1.0)
 
 
-def test_open_adjoint_refused(gpu):
-    case = _stream(19, (12, 3, 4), 0.04)
-    lat = gpu.Lattice(case, storage="f64")
-    lam, grad = lat.new_adjoint(), lat.new_gradient()
-    gpu.lbm_adjoint_seed(lat.ctx, (2, 9), lam)
-    with pytest.raises(gpu.LbmError) as e:
+def _open_porous(collision=0, fringe=0):
+    c = I.porous_channel(shape=(20, 12, 8), q=19 if collision == 0 else 27)
+    return dataclasses.replace(c, name="porous_open", periodic=(0, 1, 0), force=(0.0, 0.0, 0.0), open_x=1,
+                               rho_out=1.002, u_ref=0.05, z0=1.0, collision=collision, fringe_len=fringe)
+
+
+@pytest.mark.parametrize("collision,fringe,vort", [(0, 0, False), (1, 4, True)])
+def test_open_adjoint_transpose(gpu, collision, fringe, vort):
+    """<L v, w> from the oracle's tangent step equals <v, L^T w> from one GPU
+    reverse step, with open x faces (the rebuild's transpose at both faces),
+    at both parities, FP64; with a fringe before the outlet and vortices on
+    the inlet in the second case."""
+    case = _open_porous(collision, fringe)
+    q, N = case.q, case.ncells
+    c, w, _ = O.velocity_set(q)
+    f_n = I.random_state(w, N, seed_offset=31, amp=0.05)
+    rng = np.random.default_rng(32)
+    v, dphi, wv = rng.standard_normal((q, N)), rng.standard_normal(N), rng.standard_normal((q, N))
+    yz, sign = _vortices(case, 6, 33)
+    for parity in (0, 1):
+        orc = oracle_for(case, tangent=True)
+        if vort:
+            orc.set_vortices(yz, sign, 0.3, 2.0)
+        orc.set_populations(f_n, v)
+        orc.set_phi_tangent(dphi)
+        orc.step(1)
+        _, Lv = orc.populations(with_tangent=True)
+        lhs = float((Lv * wv).sum())
+        lat = gpu.Lattice(case, storage="f64")
+        if vort:
+            lat.set_vortices(yz, sign, 0.3, 2.0)
+        if parity:
+            lat.step(1)
+        lat.set_populations(torch.as_tensor(f_n))
+        snap = lat.new_state_buffer()
+        lat.save_state(snap)
+        lat.step(1)
+        lam = lat.new_adjoint()
+        gpu.lbm_adjoint_from_natural(lat.ctx, torch.as_tensor(wv, device="cuda"), lam)
+        lat.load_state(snap)
+        grad = torch.zeros(N, dtype=torch.float64, device="cuda")
         gpu.lbm_adjoint_step(lat.ctx, lam, grad)
-    assert e.value.code == gpu.EINVAL and "open x faces" in str(e.value)
+        nat = lat.new_natural()
+        gpu.lbm_adjoint_to_natural(lat.ctx, lam, nat)
+        lat.sync()
+        rhs = float((v * nat.cpu().numpy()).sum() + (dphi * grad.cpu().numpy()).sum())
+        announce(f"open transpose collision={collision} parity={parity}: <Lv,w> {lhs:.15e} <v,L^T w> {rhs:.15e}")
+        assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+
+
+@pytest.mark.parametrize("collision", [0, 1])
+def test_open_gradient_matches_tangent(gpu, collision):
+    """Checkpointed dJ/dphi with open x faces against the oracle's tangent,
+    at cells on the inlet and outlet planes and inside (FP64)."""
+    case = _open_porous(collision)
+    planes = (2, 17)
+    T, nsnap = 15, 3
+    N, nx = case.ncells, case.shape[0]
+    lat = gpu.Lattice(case, storage="f64")
+    grad = torch.zeros(N, dtype=torch.float64, device="cuda")
+    J, _ = gpu.lbm_gradient(lat.ctx, T, planes, lat.new_state_buffer(nsnap), nsnap, lat.new_adjoint(), grad)
+    g = grad.cpu().numpy()
+    Jo, _ = oracle_for(case, T).objective(planes)
+    assert abs(J - Jo) <= 1e-12 * abs(Jo)
+    for cell in (0 + nx * 5, nx - 1 + nx * 30, 7 + nx * 17):
+        t = oracle_for(case, tangent=True)
+        e = np.zeros(N)
+        e[cell] = 1.0
+        t.set_phi_tangent(e)
+        t.step(T)
+        _, dJ = t.objective(planes)
+        announce(f"open gradient cell {cell} (x={cell % nx}): gpu {g[cell]:.12e} tangent {dJ:.12e}")
+        assert abs(g[cell] - dJ) <= 1e-10 * max(abs(dJ), 1e-3 * np.abs(g).max())
