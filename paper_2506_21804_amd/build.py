@@ -15,6 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm_hip.so")
 SOURCES = ["abi.cpp", "geometry.cpp", "revolve.cpp", "kernels.hip", "adjoint.hip"]
+# adjoint.hip is compiled once more per (lattice, storage) pair, each copy
+# holding that pair's adjoint kernels (ADJ_PART), so that they build in parallel
+ADJOINT_PARTS = 6
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
@@ -25,8 +28,16 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",
          "-I", os.path.join(HERE, "..", "include")]
 
 
-def compile_command(src: str, obj: str) -> list:
-    return [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def compile_command(src: str, obj: str, extra=()) -> list:
+    return [HIPCC, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+
+
+def units() -> list:
+    """(source, object, extra flags) of every compilation unit."""
+    out = [(s, os.path.join(BUILD_DIR, s + ".o"), ()) for s in SOURCES]
+    out += [("adjoint.hip", os.path.join(BUILD_DIR, f"adjoint.part{k}.o"), (f"-DADJ_PART={k}",))
+            for k in range(ADJOINT_PARTS)]
+    return out
 
 
 def link_command(objs: list, out: str) -> list:
@@ -38,12 +49,13 @@ def build(verbose: bool = False) -> str:
     compile in parallel, then one link."""
     from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD_DIR, exist_ok=True)
-    objs = [os.path.join(BUILD_DIR, s + ".o") for s in SOURCES]
-    cmds = [compile_command(s, o) for s, o in zip(SOURCES, objs)]
+    us = units()
+    objs = [o for _, o, _ in us]
+    cmds = [compile_command(s, o, e) for s, o, e in us]
     if verbose:
         for c in cmds:
             print(" ".join(c), flush=True)
-    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 4)) as ex:
         results = list(ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds))
     for c, r in zip(cmds, results):
         if r.stderr:

@@ -881,10 +881,15 @@ static AdjPtrs adj_ptrs(lbm_ctx *ctx, void *lamv) {
   return {odd ? m1 : m0, odd ? m0 : m1, (char *)lamv + L.d_off};
 }
 
-int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const int *planes) {
+// The reverse step for one lattice and storage type.  Its kernels are many
+// (parity, geometry, porosity, collision model, seeds, open faces) and heavy,
+// so the build compiles this file once more per (Q, S) pair with ADJ_PART set,
+// each copy instantiating one pair; the main copy dispatches to them.
+template <int Q, typename S>
+int adjoint_step_qs(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const int *planes) {
   const ATiles t = atiles_of(ctx->ka);
   const AdjPtrs a = adj_ptrs(ctx, lamv);
-  return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
+  auto body = [&]<bool ODD, bool SOLID>() {
     using R = typename Store<S>::R;
     R *dev = (R *)a.dev;
     double *grad = (double *)gradv;
@@ -916,7 +921,45 @@ int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const
       else by_seed.template operator()<false, false>();
     }
     return check(ctx, "k_adjoint");
-  });
+  };
+  const bool odd = (ctx->steps & 1) != 0;
+  if (odd) return ctx->has_solid ? body.template operator()<true, true>() : body.template operator()<true, false>();
+  return ctx->has_solid ? body.template operator()<false, true>() : body.template operator()<false, false>();
+}
+
+#define LBM_ADJ_PAIRS(X) X(19, double) X(19, float) X(19, _Float16) X(27, double) X(27, float) X(27, _Float16)
+#define LBM_ADJ_DECL(Q, S) \
+  template int adjoint_step_qs<Q, S>(lbm_ctx *, void *, void *, double, const int *);
+#define LBM_ADJ_EXTERN(Q, S) \
+  extern template int adjoint_step_qs<Q, S>(lbm_ctx *, void *, void *, double, const int *);
+
+#if defined(ADJ_PART)
+// one (Q, S) pair per part
+#if ADJ_PART == 0
+LBM_ADJ_DECL(19, double)
+#elif ADJ_PART == 1
+LBM_ADJ_DECL(19, float)
+#elif ADJ_PART == 2
+LBM_ADJ_DECL(19, _Float16)
+#elif ADJ_PART == 3
+LBM_ADJ_DECL(27, double)
+#elif ADJ_PART == 4
+LBM_ADJ_DECL(27, float)
+#elif ADJ_PART == 5
+LBM_ADJ_DECL(27, _Float16)
+#endif
+#else
+LBM_ADJ_PAIRS(LBM_ADJ_EXTERN)
+
+int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const int *planes) {
+  if (ctx->q == 19) {
+    if (ctx->p.storage == LBM_F64) return adjoint_step_qs<19, double>(ctx, lamv, gradv, seed_w, planes);
+    if (ctx->p.storage == LBM_F32DEV) return adjoint_step_qs<19, float>(ctx, lamv, gradv, seed_w, planes);
+    return adjoint_step_qs<19, _Float16>(ctx, lamv, gradv, seed_w, planes);
+  }
+  if (ctx->p.storage == LBM_F64) return adjoint_step_qs<27, double>(ctx, lamv, gradv, seed_w, planes);
+  if (ctx->p.storage == LBM_F32DEV) return adjoint_step_qs<27, float>(ctx, lamv, gradv, seed_w, planes);
+  return adjoint_step_qs<27, _Float16>(ctx, lamv, gradv, seed_w, planes);
 }
 
 int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lamv, double w) {
@@ -954,5 +997,7 @@ int dev_layout_from_natural(lbm_ctx *ctx, const void *natv, void *lamv) {
     return check(ctx, "k_from_natural");
   });
 }
+
+#endif  // ADJ_PART
 
 }  // namespace lbmk
