@@ -87,6 +87,7 @@ def lib():
         L.orc_num_wall.restype = C.c_long
         L.orc_num_wall.argtypes = [vp]
         L.orc_wall_info.argtypes = [vp] + [vp] * 6
+        L.orc_wall_velocity.argtypes = [vp, vp, vp]
         L.orc_set_vortices.argtypes = [vp, C.c_int, vp, vp, C.c_double, C.c_double]
         L.orc_velocity_set.argtypes = [C.c_int, vp, vp, vp]
         L.orc_equilibrium.argtypes = [C.c_int, C.c_double, vp, vp]
@@ -225,7 +226,9 @@ class Oracle:
         utau, G, tau = np.empty(nw), np.empty(nw), np.empty(nw)
         self._check(lib().orc_wall_info(self.h, _ptr(cells), _ptr(refs), _ptr(normal), _ptr(utau),
                                         _ptr(G), _ptr(tau)))
-        return dict(cells=cells, refs=refs, normal=normal, utau=utau, G=G, tau=tau)
+        tangent, utan = np.empty((nw, 3)), np.empty(nw)
+        self._check(lib().orc_wall_velocity(self.h, _ptr(tangent), _ptr(utan)))
+        return dict(cells=cells, refs=refs, normal=normal, utau=utau, G=G, tau=tau, tangent=tangent, utan=utan)
 
 
 # ---- pure helpers -----------------------------------------------------------

@@ -402,6 +402,7 @@ struct SimBase {
   virtual int set_phi_tangent(const double* dphi) = 0;
   virtual int objective(const int planes[2], double* J, double* dJ) = 0;
   virtual int wall_info(long* cells, long* refs, double* normal, double* utau, double* G, double* tau) = 0;
+  virtual int wall_velocity(double* tangent, double* utan) = 0;
   virtual int set_vortices(int n, const double* yz, const int* sign, double intensity, double sigma) = 0;
   virtual long num_wall() const = 0;
   virtual int get_post_collision(double* f) = 0;
@@ -1081,6 +1082,16 @@ struct Sim : SimBase {
     }
     return ORC_OK;
   }
+  /* tangent t and modeled tangential speed u_tau u+_b of every wall record */
+  int wall_velocity(double* tangent, double* utan) override {
+    long nw = (long)wcell.size();
+    for (long k = 0; k < nw; ++k) {
+      if (tangent)
+        for (int a = 0; a < 3; ++a) tangent[3 * k + a] = wt[3 * k + a];
+      if (utan) utan[k] = wutan[k];
+    }
+    return ORC_OK;
+  }
 };
 
 template <>
@@ -1164,6 +1175,9 @@ int orc_set_vortices(void* h, int n, const double* yz, const int* sign, double i
 }
 int orc_wall_info(void* h, long* cells, long* refs, double* normal, double* utau, double* G, double* tau) {
   return static_cast<SimBase*>(h)->wall_info(cells, refs, normal, utau, G, tau);
+}
+int orc_wall_velocity(void* h, double* tangent, double* utan) {
+  return static_cast<SimBase*>(h)->wall_velocity(tangent, utan);
 }
 
 /* Pure helpers exposed for the pin tests. */

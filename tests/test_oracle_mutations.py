@@ -15,6 +15,7 @@ import test_oracle_pins as pins
 import test_oracle_pins_rr as pins_rr
 import test_oracle_pins_hybrid as pins_hy
 import test_oracle_pins_open as pins_open
+import test_oracle_pins_wall as pins_wall
 
 SRC = os.path.join(os.path.dirname(O.__file__), "lbm_oracle.cpp")
 
@@ -75,6 +76,20 @@ MUTATIONS = [
     ("vortex circulation constant", "(6.0 * std::log(3.0) - 9.0 * std::log(2.0))",
      "(6.0 * std::log(3.0) + 9.0 * std::log(2.0))"),
     ("regularized outlet", "if (!inlet) {\n      /* the outlet holds", "if (false) {\n      /* the outlet holds"),
+    ("u_tau solved at the first cell's distance", "solve_utau(U, wyr[k], nu, p.kappa, p.E, &utau, nullptr);",
+     "solve_utau(U, wyb[k], nu, p.kappa, p.E, &utau, nullptr);"),
+    ("second solve of the law dropped", "if (r == wcell[k]) {", "if (true) {"),
+    ("speed of u instead of its tangential part",
+     "double U = std::sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);",
+     "double U = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);"),
+    ("first-cell y+ from the reference distance", "double yplus_b = wyb[k] * utau / nu;",
+     "double yplus_b = wyr[k] * utau / nu;"),
+    ("objective pressure weight", "T Jv = (1.0 / 3.0) * (s0 / double(n0) - s1 / double(n1))",
+     "T Jv = 0.5 * (s0 / double(n0) - s1 / double(n1))"),
+    ("objective planes swapped", "(s0 / double(n0) - s1 / double(n1)) + ke", "(s1 / double(n1) - s0 / double(n0)) + ke"),
+    ("objective kinetic energy without the half", "ke += 0.5 * (m[0] * m[0]", "ke += (m[0] * m[0]"),
+    ("objective momentum without the half force", "for (int a = 0; a < 3; ++a) m[a] = j[a] + 0.5 * p.force[a];",
+     "for (int a = 0; a < 3; ++a) m[a] = j[a];"),
 ]
 
 PIN_TESTS = [
@@ -104,6 +119,8 @@ PIN_TESTS = [
     (pins_open.test_open_low_viscosity_stream_stable, [(19,)]),
     (pins_open.test_vortex_inlet_exact, [(19, 0)]),
     (pins_open.test_open_poiseuille, [()]),
+    (pins_wall.test_wall_law_at_first_cell, [("channel",), ("urban",)]),
+    (pins_wall.test_objective_density_step_and_uniform_stream, [()]),
 ]
 
 
