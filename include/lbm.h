@@ -142,6 +142,20 @@ int lbm_moments(lbm_ctx *ctx, void *rho, void *u);
  * and reports kernel-side faults. */
 int lbm_diagnostics(lbm_ctx *ctx, double out[4]);
 
+/* lbm_diagnostics for callers that cannot allocate device memory or must not
+ * depend on the workspace's reduction region (code under stream capture,
+ * tight serving loops): the same sums, computed by the same kernels in the
+ * same order (bit-identical results), with the reduction partials and sums
+ * held in a static device array of the library (1024 x 8 + 8 doubles, 64 KiB,
+ * one copy per GPU, kept until the process ends; its address is looked up
+ * once per device by lbm_init).  Allocates nothing.  The array is shared by
+ * every call on one GPU and holds the last call's values: calls that overlap
+ * on one GPU (two streams, two threads) race.  Any domain lbm_init accepts
+ * fits (the reduction never uses more than 1024 partials); a reduction that
+ * would need more gives LBM_ESIZE.  Synchronises and reports kernel-side
+ * faults like lbm_diagnostics. */
+int lbm_diagnostics_noalloc(lbm_ctx *ctx, double out[4]);
+
 /* Waits for the stream and reports kernel-side faults. */
 int lbm_sync(lbm_ctx *ctx);
 

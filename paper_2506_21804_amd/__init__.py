@@ -16,7 +16,7 @@ import numpy as np
 
 __all__ = [
     "load", "LbmError", "Params", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_moments",
-    "lbm_diagnostics", "lbm_sync", "lbm_steps_done", "lbm_shape", "lbm_get_populations", "lbm_set_populations",
+    "lbm_diagnostics", "lbm_diagnostics_noalloc", "lbm_sync", "lbm_steps_done", "lbm_shape", "lbm_get_populations", "lbm_set_populations",
     "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes",
     "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural",
     "lbm_gradient", "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
@@ -82,6 +82,7 @@ def load():
         "lbm_step": (i, [vp, i]),
         "lbm_moments": (i, [vp, vp, vp]),
         "lbm_diagnostics": (i, [vp, vp]),
+        "lbm_diagnostics_noalloc": (i, [vp, vp]),
         "lbm_sync": (i, [vp]),
         "lbm_steps_done": (ll, [vp]),
         "lbm_shape": (i, [vp, vp]),
@@ -116,7 +117,8 @@ def load():
 
 
 def exported_symbols():
-    return ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_moments", "lbm_diagnostics", "lbm_sync",
+    return ["lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_moments", "lbm_diagnostics",
+            "lbm_diagnostics_noalloc", "lbm_sync",
             "lbm_steps_done", "lbm_shape", "lbm_get_populations", "lbm_set_populations", "lbm_state_bytes",
             "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes", "lbm_adjoint_seed",
             "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural", "lbm_gradient",
@@ -233,6 +235,12 @@ def lbm_moments(ctx, rho, u):
 def lbm_diagnostics(ctx):
     out = (C.c_double * 4)()
     _check(ctx, load().lbm_diagnostics(ctx, out))
+    return np.array(out[:])
+
+
+def lbm_diagnostics_noalloc(ctx):
+    out = (C.c_double * 4)()
+    _check(ctx, load().lbm_diagnostics_noalloc(ctx, out))
     return np.array(out[:])
 
 

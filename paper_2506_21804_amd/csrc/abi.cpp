@@ -365,7 +365,8 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
     if ((e = hipMemcpy(ctx->wrec, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
       return fail(e, "upload wall records");
   }
-  if (dev_fill(ctx, ctx->errflag, ALIGN) != LBM_OK || (p->open_x && dev_inflow(ctx, 0, 1.0) != LBM_OK) ||
+  if (dev_scratch_setup(ctx) != LBM_OK || dev_fill(ctx, ctx->errflag, ALIGN) != LBM_OK ||
+      (p->open_x && dev_inflow(ctx, 0, 1.0) != LBM_OK) ||
       dev_init_equilibrium(ctx, rho0, u0) != LBM_OK) {
     int code = LBM_EHIP;
     g_static_error = ctx->err;
@@ -410,6 +411,23 @@ int lbm_diagnostics(lbm_ctx *ctx, double out[4]) {
   hipError_t e = hipMemcpy(r, ctx->result, sizeof(r), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(ctx, e, "read diagnostics");
   // mass = number of fluid cells + sum of density deviations
+  out[0] = r[4] + r[0];
+  out[1] = r[1];
+  out[2] = r[2];
+  out[3] = r[3];
+  return LBM_OK;
+}
+
+int lbm_diagnostics_noalloc(lbm_ctx *ctx, double out[4]) {
+  if (!ctx || !out) return ctx ? set_err(ctx, LBM_EINVAL, "null output") : LBM_EINVAL;
+  const double *res = nullptr;
+  int rc = dev_reduce_diag_noalloc(ctx, &res);
+  if (rc != LBM_OK) return rc;
+  rc = sync_and_check(ctx);
+  if (rc != LBM_OK) return rc;
+  double r[8];
+  hipError_t e = hipMemcpy(r, res, sizeof(r), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "read diagnostics");
   out[0] = r[4] + r[0];
   out[1] = r[1];
   out[2] = r[2];

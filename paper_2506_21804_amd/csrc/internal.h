@@ -120,6 +120,7 @@ struct lbm_ctx {
   int npartial = 0;           // number of partial slots (blocks) available
   double *result = nullptr;   // [8] finalised reductions
   int *errflag = nullptr;     // [1] bit 0 non-finite, bit 1 Newton
+  double *scratch = nullptr;  // device address of the static scratch on this context's device
   long long steps = 0;
   std::string err;
   bool profiling = false;
@@ -161,6 +162,12 @@ int dev_inflow(lbm_ctx *ctx, int nvort, double sigma);  // inlet velocity field 
 int dev_step(lbm_ctx *ctx);  // one time step at parity ctx->steps & 1
 int dev_moments(lbm_ctx *ctx, void *rho, void *u);
 int dev_reduce_diag(lbm_ctx *ctx);  // writes result[0..3]
+// Looks up (once per device) the address of the static scratch array and
+// stores it in ctx->scratch; the current device must be the context's.
+int dev_scratch_setup(lbm_ctx *ctx);
+// dev_reduce_diag with its partials and sums in the static scratch; *result
+// receives the device address of the sums.
+int dev_reduce_diag_noalloc(lbm_ctx *ctx, const double **result);
 int dev_objective(lbm_ctx *ctx, const int planes[2]);  // writes result[4]
 int dev_export(lbm_ctx *ctx, void *f);
 int dev_import(lbm_ctx *ctx, const void *f);

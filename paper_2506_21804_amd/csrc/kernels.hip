@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 #include "lattice.h"
@@ -894,6 +895,9 @@ __global__ __launch_bounds__(BLOCK) void k_import(S *__restrict__ pop, const uin
 // ---------------------------------------------------------------------------
 constexpr int RED_BLOCKS = 1024;
 constexpr int NRED = 8;
+// partials of RED_BLOCKS blocks, then NRED finalised sums
+constexpr int SCRATCH_DOUBLES = RED_BLOCKS * NRED + NRED;
+constexpr int MAX_DEVICES = 64;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -1181,23 +1185,80 @@ int dev_import(lbm_ctx *ctx, const void *f) {
   });
 }
 
-static int reduce(lbm_ctx *ctx, int mode, int p0, int p1, int offset) {
+static int reduce(lbm_ctx *ctx, int mode, int p0, int p1, int offset, double *partial, int npartial,
+                  double *result) {
   const Tiles t = tiles_of(ctx->ka);
-  const int grid = (int)std::min<unsigned>(t.nblocks, (unsigned)std::min(RED_BLOCKS, ctx->npartial));
+  const int grid = (int)std::min<unsigned>(t.nblocks, (unsigned)std::min(RED_BLOCKS, npartial));
   return dispatch(ctx, [&]<int Q, typename S>() {
     int rc = by_parity(ctx, [&]<bool ODD, bool SOLID>() {
       k_reduce<Q, S, ODD, SOLID><<<grid, BLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->ka, t, mode,
-                                                                  p0, p1, ctx->partial);
+                                                                  p0, p1, partial);
       return check_launch(ctx, "k_reduce");
     });
     if (rc != LBM_OK) return rc;
-    k_finalise<<<1, BLOCK, 0, ctx->stream>>>(ctx->partial, grid, ctx->result, offset);
+    k_finalise<<<1, BLOCK, 0, ctx->stream>>>(partial, grid, result, offset);
     return check_launch(ctx, "k_finalise");
   });
 }
 
-int dev_reduce_diag(lbm_ctx *ctx) { return reduce(ctx, 0, -1, -1, 0); }
-int dev_objective(lbm_ctx *ctx, const int planes[2]) { return reduce(ctx, 1, planes[0], planes[1], 8); }
+int dev_reduce_diag(lbm_ctx *ctx) { return reduce(ctx, 0, -1, -1, 0, ctx->partial, ctx->npartial, ctx->result); }
+int dev_objective(lbm_ctx *ctx, const int planes[2]) {
+  return reduce(ctx, 1, planes[0], planes[1], 8, ctx->partial, ctx->npartial, ctx->result);
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of lbm_diagnostics_noalloc: the reduction partials of at
+// most RED_BLOCKS blocks and the finalised sums, in a file-scope device array
+// (one copy per GPU, held until the process ends).  In host code the array's
+// name is not a device address; the address comes from hipGetSymbolAddress,
+// taken once per device in dev_scratch_setup and kept per device.
+// ---------------------------------------------------------------------------
+}  // namespace lbmk
+
+static __device__ __align__(256) double scratch[lbmk::SCRATCH_DOUBLES];
+
+namespace lbmk {
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+int dev_scratch_setup(lbm_ctx *ctx) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipGetDevice");
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    ctx->err = "device index beyond the static scratch table";
+    return LBM_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = ptr;
+  }
+  ctx->scratch = (double *)g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
+int dev_reduce_diag_noalloc(lbm_ctx *ctx, const double **result) {
+  if (!ctx->scratch) {
+    ctx->err = "static scratch not set up on this context's device";
+    return LBM_EHIP;
+  }
+  const Tiles t = tiles_of(ctx->ka);
+  const unsigned grid = std::min<unsigned>(t.nblocks, (unsigned)RED_BLOCKS);
+  if ((size_t)grid * NRED + NRED > (size_t)SCRATCH_DOUBLES) {
+    ctx->err = "reduction needs more partials than the static scratch holds";
+    return LBM_ESIZE;
+  }
+  double *partial = ctx->scratch;
+  double *res = ctx->scratch + (size_t)RED_BLOCKS * NRED;
+  *result = res;
+  return reduce(ctx, 0, -1, -1, 0, partial, RED_BLOCKS, res);
+}
 
 int dev_fill(lbm_ctx *ctx, void *ptr, size_t bytes) {
   const size_t n4 = bytes / 4;
