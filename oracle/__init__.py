@@ -47,6 +47,7 @@ class Params(C.Structure):
         ("fd_weight", C.c_double),
         ("open_x", C.c_int),
         ("rho_out", C.c_double),
+        ("slip", C.c_int),
     ]
 
 
@@ -88,6 +89,8 @@ def lib():
         L.orc_num_wall.argtypes = [vp]
         L.orc_wall_info.argtypes = [vp] + [vp] * 6
         L.orc_wall_velocity.argtypes = [vp, vp, vp]
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         L.orc_set_vortices.argtypes = [vp, C.c_int, vp, vp, C.c_double, C.c_double]
         L.orc_velocity_set.argtypes = [C.c_int, vp, vp, vp]
         L.orc_equilibrium.argtypes = [C.c_int, C.c_double, vp, vp]
@@ -110,7 +113,7 @@ def _ptr(a):
 
 def make_params(q, shape, periodic=(1, 1, 1), tau0=0.6, cs_smag=0.0, force=(0.0, 0.0, 0.0),
                 wall_model=0, kappa=0.41, E=9.0, fringe_len=0, u_ref=0.0, z0=1.0, lid=0,
-                collision=0, fd_weight=0.0, open_x=0, rho_out=1.0) -> Params:
+                collision=0, fd_weight=0.0, open_x=0, rho_out=1.0, slip=0) -> Params:
     p = Params()
     p.q = q
     p.nx, p.ny, p.nz = shape
@@ -122,6 +125,7 @@ def make_params(q, shape, periodic=(1, 1, 1), tau0=0.6, cs_smag=0.0, force=(0.0,
     p.collision = collision
     p.fd_weight = fd_weight
     p.open_x, p.rho_out = open_x, rho_out
+    p.slip = slip
     return p
 
 
@@ -310,3 +314,8 @@ def solve_utau(U, y, nu, kappa=0.41, E=9.0):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later oracle steps (the host's default: all cores)."""
+    lib().orc_set_num_threads(int(n))

@@ -26,7 +26,9 @@
  *      reconstruction (sigma = 0, solid velocity = modeled velocity,
  *      Sec. 2.2.1 last paragraph, non-equilibrium from Eq. (10));
  *      then the fringe blend / lid of the open-boundary urban setup;
- *   3. streaming with halfway bounce-back at solid links.
+ *   3. streaming with halfway bounce-back at solid links, and specular
+ *      reflection at full-slip box faces (the outer walls of the
+ *      street-canyon setup, Sec. 3.2).
  *
  * Readings of the paper where it is silent or garbled (each is also listed
  * in the design document):
@@ -108,6 +110,7 @@ typedef struct {
   double fd_weight; /* 1 - sigma of Eq. (7): weight of the finite-difference strain (collision 1 only) */
   int open_x;       /* 1: velocity inlet at x = 0 and pressure outlet at x = nx - 1 (non-periodic x) */
   double rho_out;   /* density imposed at the outlet (open_x only) */
+  int slip;         /* full-slip box faces: bit 2a the low face of axis a, bit 2a+1 the high face */
 } orc_params;
 }
 
@@ -458,6 +461,31 @@ struct Sim : SimBase {
     return neighbor_xyz(x, y, z, dx, dy, dz);
   }
   bool is_fluid(long c) const { return c >= 0 && fluid[c]; }
+  /* Full-slip faces: the axes along which the move (x, y, z) + d leaves the
+   * box, when every face it crosses is a full-slip face; 0 when the move
+   * stays inside or crosses any other face. */
+  int slip_cross(int x, int y, int z, int dx, int dy, int dz) const {
+    if (!p.slip) return 0;
+    const int q[3] = {x + dx, y + dy, z + dz};
+    const int n[3] = {p.nx, p.ny, p.nz};
+    int m = 0;
+    for (int a = 0; a < 3; ++a) {
+      if (p.periodic[a]) continue;
+      if (q[a] < 0) {
+        if (!((p.slip >> (2 * a)) & 1)) return 0;
+        m |= 1 << a;
+      } else if (q[a] >= n[a]) {
+        if (!((p.slip >> (2 * a + 1)) & 1)) return 0;
+        m |= 1 << a;
+      }
+    }
+    return m;
+  }
+  int dir_index(const int c[3]) const {
+    for (int i = 0; i < vs.q; ++i)
+      if (vs.c[i][0] == c[0] && vs.c[i][1] == c[1] && vs.c[i][2] == c[2]) return i;
+    return -1;
+  }
 
   /* Log-law inflow profile of the urban setup: u_ref ln(1+z_c/z0)/ln(1+z_top/z0). */
   double u_in(double zc) const {
@@ -544,6 +572,15 @@ struct Sim : SimBase {
             "rho_out > 0 and the inflow profile (z0 > 0, finite u_ref)";
       return ORC_EINVAL;
     }
+    for (int a = 0; a < 3; ++a)
+      if (p.periodic[a] && ((p.slip >> (2 * a)) & 3)) {
+        err = "full-slip faces need a non-periodic axis";
+        return ORC_EINVAL;
+      }
+    if ((p.slip & ~63) || (p.open_x && (p.slip & 3)) || (p.lid && (p.slip & 32))) {
+      err = "full-slip faces: six face bits, not on open x faces, not on the top face with a lid";
+      return ORC_EINVAL;
+    }
     vs = make_velocity_set(p.q);
     h3 = make_h3_basis(vs);
     N = (long)p.nx * p.ny * p.nz;
@@ -573,9 +610,12 @@ struct Sim : SimBase {
         if (kind[b] != K_BULK) continue;
         int s[3] = {0, 0, 0};
         bool any = false;
+        int bx, by, bz;
+        coords(b, bx, by, bz);
         for (int i = 1; i < vs.q; ++i) {
           long nb = neighbor(b, vs.c[i][0], vs.c[i][1], vs.c[i][2]);
-          if (!is_fluid(nb)) {
+          /* links through full-slip faces are not walls of the wall model */
+          if (!is_fluid(nb) && !slip_cross(bx, by, bz, vs.c[i][0], vs.c[i][1], vs.c[i][2])) {
             any = true;
             for (int a = 0; a < 3; ++a) s[a] -= vs.c[i][a];
           }
@@ -965,7 +1005,10 @@ struct Sim : SimBase {
           }
           for (int i = 0; i < vs.q; ++i) fs[(size_t)i * N + c] = fo[i];
         }
-    /* pull streaming with halfway bounce-back */
+    /* pull streaming with halfway bounce-back; across full-slip faces the
+     * population is reflected specularly: f_i(x) = f*_j(x - c_i with the
+     * crossed components set to zero), c_j = c_i with those components
+     * negated, when that cell is fluid (else bounce-back) */
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < p.nz; ++z)
       for (int y = 0; y < p.ny; ++y)
@@ -974,7 +1017,24 @@ struct Sim : SimBase {
           if (!fluid[c]) continue;
           for (int i = 0; i < vs.q; ++i) {
             long src = neighbor_xyz(x, y, z, -vs.c[i][0], -vs.c[i][1], -vs.c[i][2]);
-            f[(size_t)i * N + c] = is_fluid(src) ? fs[(size_t)i * N + src] : fs[(size_t)vs.opp[i] * N + c];
+            if (is_fluid(src)) {
+              f[(size_t)i * N + c] = fs[(size_t)i * N + src];
+              continue;
+            }
+            const int m = slip_cross(x, y, z, -vs.c[i][0], -vs.c[i][1], -vs.c[i][2]);
+            long rsrc = -1;
+            int j = -1;
+            if (m) {
+              int d[3], cj[3];
+              for (int a = 0; a < 3; ++a) {
+                const bool crossed = (m >> a) & 1;
+                d[a] = crossed ? 0 : -vs.c[i][a];
+                cj[a] = crossed ? -vs.c[i][a] : vs.c[i][a];
+              }
+              rsrc = neighbor_xyz(x, y, z, d[0], d[1], d[2]);
+              j = dir_index(cj);
+            }
+            f[(size_t)i * N + c] = is_fluid(rsrc) ? fs[(size_t)j * N + rsrc] : fs[(size_t)vs.opp[i] * N + c];
           }
         }
     if (bad) {
@@ -1259,6 +1319,14 @@ int orc_num_threads(void) {
   return omp_get_max_threads();
 #else
   return 1;
+#endif
+}
+/* Sets the number of OpenMP threads of later steps (n >= 1). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
 #endif
 }
 

@@ -49,6 +49,7 @@ class Case:
     fd_weight: float = 0.0  # 1 - sigma: weight of the finite-difference strain (collision 1 only)
     open_x: int = 0  # 1: velocity inlet at x = 0, pressure outlet at x = nx - 1 (x not periodic)
     rho_out: float = 1.0  # outlet density (open_x only)
+    slip: int = 0  # full-slip box faces: bit 2a the low face of axis a, bit 2a+1 the high face
     mask: np.ndarray | None = None
     wall_dist: np.ndarray | None = None
     porosity: np.ndarray | None = None
@@ -69,10 +70,12 @@ class Case:
 # Geometry helpers
 # ---------------------------------------------------------------------------
 
-def voxel_wall_distance(mask: np.ndarray, shape, periodic, radius: int = 2) -> np.ndarray:
+def voxel_wall_distance(mask: np.ndarray, shape, periodic, radius: int = 2, slip: int = 0) -> np.ndarray:
     """Distance from each cell centre to the nearest solid voxel (a unit cube)
     within ``radius`` cells in every axis; cells outside a non-periodic axis
-    count as solid.  Cells with no solid voxel in that neighbourhood get +inf.
+    count as solid, except beyond a full-slip face (``slip`` bit 2a: the low
+    face of axis a, 2a+1 the high face), where the geometry continues as its
+    mirror image.  Cells with no solid voxel in that neighbourhood get +inf.
 
     A cell next to a flat wall gets 0.5, next to a convex edge sqrt(0.5), next
     to a corner sqrt(0.75).  Radius 2 covers every wall cell and every cell
@@ -81,15 +84,22 @@ def voxel_wall_distance(mask: np.ndarray, shape, periodic, radius: int = 2) -> n
     nx, ny, nz = shape
     solid = (np.asarray(mask).reshape(nz, ny, nx) == 0)
     R = radius
-    # pad with wrap on periodic axes, with solid on the others
+    # pad with wrap on periodic axes, with solid on the others, mirrored
+    # beyond full-slip faces (array axis 0 is z, 2 is x)
     padded = solid
-    for ax, per in zip((0, 1, 2), (periodic[2], periodic[1], periodic[0])):
-        widths = [(0, 0)] * 3
-        widths[ax] = (R, R)
-        if per:
+    for ax, a in zip((0, 1, 2), (2, 1, 0)):
+        if periodic[a]:
+            widths = [(0, 0)] * 3
+            widths[ax] = (R, R)
             padded = np.pad(padded, widths, mode="wrap")
-        else:
-            padded = np.pad(padded, widths, mode="constant", constant_values=True)
+            continue
+        for side in (0, 1):
+            widths = [(0, 0)] * 3
+            widths[ax] = (R, 0) if side == 0 else (0, R)
+            if (slip >> (2 * a + side)) & 1:
+                padded = np.pad(padded, widths, mode="symmetric")
+            else:
+                padded = np.pad(padded, widths, mode="constant", constant_values=True)
     offs = []
     for dz in range(-R, R + 1):
         for dy in range(-R, R + 1):

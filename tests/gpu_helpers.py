@@ -12,7 +12,7 @@ def oracle_for(case, steps=0, tangent=False, wall_dist="case"):
                       force=case.force, wall_model=case.wall_model, kappa=case.kappa, E=case.E,
                       fringe_len=case.fringe_len, u_ref=case.u_ref, z0=case.z0, lid=case.lid,
                       collision=case.collision, fd_weight=case.fd_weight, open_x=case.open_x,
-                      rho_out=case.rho_out)
+                      rho_out=case.rho_out, slip=getattr(case, "slip", 0))
     wd = case.wall_dist if isinstance(wall_dist, str) else wall_dist
     s = O.Oracle(p, mask=case.mask, wall_dist=wd, porosity=case.porosity, rho0=case.rho0, u0=case.u0,
                  tangent=tangent)

@@ -16,6 +16,7 @@ import test_oracle_pins_rr as pins_rr
 import test_oracle_pins_hybrid as pins_hy
 import test_oracle_pins_open as pins_open
 import test_oracle_pins_wall as pins_wall
+import test_oracle_pins_slip as pins_slip
 
 SRC = os.path.join(os.path.dirname(O.__file__), "lbm_oracle.cpp")
 
@@ -90,6 +91,14 @@ MUTATIONS = [
     ("objective kinetic energy without the half", "ke += 0.5 * (m[0] * m[0]", "ke += (m[0] * m[0]"),
     ("objective momentum without the half force", "for (int a = 0; a < 3; ++a) m[a] = j[a] + 0.5 * p.force[a];",
      "for (int a = 0; a < 3; ++a) m[a] = j[a];"),
+    ("full-slip faces bounce back", "            if (m) {\n              int d[3], cj[3];",
+     "            if (false) {\n              int d[3], cj[3];"),
+    ("reflected population not flipped", "cj[a] = crossed ? -vs.c[i][a] : vs.c[i][a];", "cj[a] = vs.c[i][a];"),
+    ("reflected source without the tangential shift", "d[a] = crossed ? 0 : -vs.c[i][a];", "d[a] = 0;"),
+    ("reflection flips every component", "cj[a] = crossed ? -vs.c[i][a] : vs.c[i][a];", "cj[a] = -vs.c[i][a];"),
+    ("slip links counted as wall links",
+     "if (!is_fluid(nb) && !slip_cross(bx, by, bz, vs.c[i][0], vs.c[i][1], vs.c[i][2])) {",
+     "if (!is_fluid(nb)) {"),
 ]
 
 PIN_TESTS = [
@@ -121,6 +130,9 @@ PIN_TESTS = [
     (pins_open.test_open_poiseuille, [()]),
     (pins_wall.test_wall_law_at_first_cell, [("channel",), ("urban",)]),
     (pins_wall.test_objective_density_step_and_uniform_stream, [()]),
+    (pins_slip.test_slip_faces_mirror_periodic_double, [(19, 0)]),
+    (pins_slip.test_slip_top_over_bounce_back_ground_with_buildings, [()]),
+    (pins_slip.test_slip_faces_are_not_wall_modeled, [()]),
 ]
 
 
