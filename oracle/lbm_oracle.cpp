@@ -89,6 +89,7 @@
 #include <cstring>
 #include <initializer_list>
 #include <string>
+#include <type_traits>
 #include <vector>
 #ifdef _OPENMP
 #include <omp.h>
@@ -426,8 +427,9 @@ struct Sim : SimBase {
   std::vector<long> wall_index; /* cell -> wall record, -1 if none */
   /* pre-collision velocity field [3][N] of the current step (hybrid collision only) */
   std::vector<T> uf;
-  /* wall-model records of the current step (FP64) */
-  std::vector<double> wt, wutan, wG, wtau, wutau;
+  /* wall-model records of the current step (FP64 values; in tangent mode
+   * they carry their derivatives too) */
+  std::vector<T> wt, wutan, wG, wtau, wutau;
   /* inflow vortices of the vortex method: positions (y, z), circulations */
   std::vector<double> vy, vz, vgam;
   double vsig = 1.0;
@@ -653,11 +655,11 @@ struct Sim : SimBase {
       }
     }
     long nw = (long)wcell.size();
-    wt.assign(3 * nw, 0.0);
-    wutan.assign(nw, 0.0);
-    wG.assign(nw, 0.0);
-    wtau.assign(nw, p.tau0);
-    wutau.assign(nw, 0.0);
+    wt.assign(3 * nw, T(0.0));
+    wutan.assign(nw, T(0.0));
+    wG.assign(nw, T(0.0));
+    wtau.assign(nw, T(p.tau0));
+    wutau.assign(nw, T(0.0));
     /* initial populations: equilibrium of the initial density and velocity */
     f.assign((size_t)vs.q * N, T(0.0));
     fs.assign((size_t)vs.q * N, T(0.0));
@@ -683,7 +685,18 @@ struct Sim : SimBase {
     }
   }
 
-  /* Wall prepass: u_tau, modeled tangential speed and strain from f^n. */
+  /* A root found by Newton in double precision, as a value of type T: in
+   * tangent mode its derivative follows from the implicit function theorem,
+   * d root = -(dF/dp) dp / (dF/droot) for the residual F(root, p) = 0. */
+  static T root_of(double v, const T& param, double dF_dparam, double dF_droot) {
+    if constexpr (std::is_same<T, Dual>::value) return Dual(v, -dF_dparam * der(param) / dF_droot);
+    else return T(v);
+  }
+
+  /* Wall prepass: u_tau, modeled tangential speed and strain from f^n.  In
+   * tangent mode the records carry their derivatives: through the reference
+   * cell's velocity, the tangent direction, and the two Newton solves
+   * (implicit derivatives of their roots). */
   int wall_prepass() {
     const double nu = (p.tau0 - 0.5) / 3.0;
     int status = ORC_OK;
@@ -693,37 +706,44 @@ struct Sim : SimBase {
       T rho;
       T j[3];
       local_moments(r, rho, j);
-      double u[3];
-      for (int a = 0; a < 3; ++a) u[a] = (val(j[a]) + 0.5 * p.force[a]) / val(rho);
+      T u[3];
+      for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * p.force[a]) / rho;
       const double* n = &wnorm[3 * k];
-      double un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
-      double ut[3] = {u[0] - un * n[0], u[1] - un * n[1], u[2] - un * n[2]};
-      double U = std::sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
-      if (!(U > 1e-300)) {
-        wt[3 * k] = wt[3 * k + 1] = wt[3 * k + 2] = 0.0;
-        wutan[k] = 0.0;
-        wG[k] = 0.0;
-        wutau[k] = 0.0;
-        wtau[k] = 3.0 * nu + 0.5;
+      T un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+      T ut[3] = {u[0] - un * n[0], u[1] - un * n[1], u[2] - un * n[2]};
+      T U = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+      const double Uv = val(U);
+      if (!(Uv > 1e-300)) {
+        wt[3 * k] = wt[3 * k + 1] = wt[3 * k + 2] = T(0.0);
+        wutan[k] = T(0.0);
+        wG[k] = T(0.0);
+        wutau[k] = T(0.0);
+        wtau[k] = T(3.0 * nu + 0.5);
         continue;
       }
-      double utau = 0.0;
-      int rc = solve_utau(U, wyr[k], nu, p.kappa, p.E, &utau, nullptr);
+      double utv = 0.0;
+      int rc = solve_utau(Uv, wyr[k], nu, p.kappa, p.E, &utv, nullptr);
       if (rc != ORC_OK) { status = rc; continue; }
-      double uplus_b;
+      /* F(u_tau; U) = g(U/u_tau) - y_r u_tau / nu */
+      const double gpr = spalding_dg(Uv / utv, p.kappa, p.E);
+      T utau = root_of(utv, U, gpr / utv, -gpr * Uv / (utv * utv) - wyr[k] / nu);
+      T uplus_b;
       if (r == wcell[k]) {
         uplus_b = U / utau;
       } else {
-        double yplus_b = wyb[k] * utau / nu;
+        double yplus_b = wyb[k] * utv / nu;
         double start = uplus_upper_bound(yplus_b, p.kappa, p.E);
-        if (wyr[k] >= wyb[k]) start = std::fmin(start, U / utau);
-        rc = solve_uplus(yplus_b, start, p.kappa, p.E, &uplus_b);
+        if (wyr[k] >= wyb[k]) start = std::fmin(start, Uv / utv);
+        double upv;
+        rc = solve_uplus(yplus_b, start, p.kappa, p.E, &upv);
         if (rc != ORC_OK) { status = rc; continue; }
+        /* G(u+; u_tau) = g(u+) - y_b u_tau / nu */
+        uplus_b = root_of(upv, utau, -wyb[k] / nu, spalding_dg(upv, p.kappa, p.E));
       }
       for (int a = 0; a < 3; ++a) wt[3 * k + a] = ut[a] / U;
       wutan[k] = utau * uplus_b;
       double cs2 = p.cs_smag * p.cs_smag;
-      double G = 2.0 * utau * utau / (nu + std::sqrt(nu * nu + 4.0 * cs2 * utau * utau));
+      T G = 2.0 * utau * utau / (nu + sqrt(nu * nu + 4.0 * cs2 * utau * utau));
       wG[k] = G;
       wutau[k] = utau;
       wtau[k] = 3.0 * (nu + cs2 * G) + 0.5;
@@ -924,13 +944,13 @@ struct Sim : SimBase {
       for (int a = 0; a < 3; ++a) j[a] += double(vs.c[i][a]) * fi;
     }
     const double* n = &wnorm[3 * k];
-    const double* t = &wt[3 * k];
+    const T* t = &wt[3 * k];
     T u[3];
     for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * p.force[a]) / rho;
     T un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
     T uw[3];
     for (int a = 0; a < 3; ++a) uw[a] = wutan[k] * t[a] + un * n[a];
-    double tau = wtau[k], G = wG[k];
+    T tau = wtau[k], G = wG[k];
     T feq[27];
     eqm(rho, uw, feq);
     /* with the hybrid collision, the full finite-difference strain whose
@@ -1136,9 +1156,9 @@ struct Sim : SimBase {
       if (refs) refs[k] = wref[k];
       if (normal)
         for (int a = 0; a < 3; ++a) normal[3 * k + a] = wnorm[3 * k + a];
-      if (utau) utau[k] = wutau[k];
-      if (G) G[k] = wG[k];
-      if (tau) tau[k] = wtau[k];
+      if (utau) utau[k] = val(wutau[k]);
+      if (G) G[k] = val(wG[k]);
+      if (tau) tau[k] = val(wtau[k]);
     }
     return ORC_OK;
   }
@@ -1147,8 +1167,8 @@ struct Sim : SimBase {
     long nw = (long)wcell.size();
     for (long k = 0; k < nw; ++k) {
       if (tangent)
-        for (int a = 0; a < 3; ++a) tangent[3 * k + a] = wt[3 * k + a];
-      if (utan) utan[k] = wutan[k];
+        for (int a = 0; a < 3; ++a) tangent[3 * k + a] = val(wt[3 * k + a]);
+      if (utan) utan[k] = val(wutan[k]);
     }
     return ORC_OK;
   }
@@ -1182,16 +1202,12 @@ thread_local std::string g_create_error;
 extern "C" {
 
 /* Creates a simulation.  tangent = 0: plain FP64; tangent = 1: dual numbers
- * (wall model not supported in tangent mode). */
+ * (directional derivatives of everything, the wall model included). */
 void* orc_create(const orc_params* p, const uint8_t* mask, const double* wall_dist, const double* porosity,
                  const double* rho0, const double* u0, int tangent) {
   g_create_error.clear();
   if (!p) {
     g_create_error = "null parameters";
-    return nullptr;
-  }
-  if (tangent && p->wall_model) {
-    g_create_error = "tangent mode does not differentiate the wall model";
     return nullptr;
   }
   SimBase* s;

@@ -77,14 +77,14 @@ MUTATIONS = [
     ("vortex circulation constant", "(6.0 * std::log(3.0) - 9.0 * std::log(2.0))",
      "(6.0 * std::log(3.0) + 9.0 * std::log(2.0))"),
     ("regularized outlet", "if (!inlet) {\n      /* the outlet holds", "if (false) {\n      /* the outlet holds"),
-    ("u_tau solved at the first cell's distance", "solve_utau(U, wyr[k], nu, p.kappa, p.E, &utau, nullptr);",
-     "solve_utau(U, wyb[k], nu, p.kappa, p.E, &utau, nullptr);"),
+    ("u_tau solved at the first cell's distance", "solve_utau(Uv, wyr[k], nu, p.kappa, p.E, &utv, nullptr);",
+     "solve_utau(Uv, wyb[k], nu, p.kappa, p.E, &utv, nullptr);"),
     ("second solve of the law dropped", "if (r == wcell[k]) {", "if (true) {"),
     ("speed of u instead of its tangential part",
-     "double U = std::sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);",
-     "double U = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);"),
-    ("first-cell y+ from the reference distance", "double yplus_b = wyb[k] * utau / nu;",
-     "double yplus_b = wyr[k] * utau / nu;"),
+     "T U = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);",
+     "T U = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);"),
+    ("first-cell y+ from the reference distance", "double yplus_b = wyb[k] * utv / nu;",
+     "double yplus_b = wyr[k] * utv / nu;"),
     ("objective pressure weight", "T Jv = (1.0 / 3.0) * (s0 / double(n0) - s1 / double(n1))",
      "T Jv = 0.5 * (s0 / double(n0) - s1 / double(n1))"),
     ("objective planes swapped", "(s0 / double(n0) - s1 / double(n1)) + ke", "(s1 / double(n1) - s0 / double(n0)) + ke"),
@@ -96,6 +96,10 @@ MUTATIONS = [
     ("reflected population not flipped", "cj[a] = crossed ? -vs.c[i][a] : vs.c[i][a];", "cj[a] = vs.c[i][a];"),
     ("reflected source without the tangential shift", "d[a] = crossed ? 0 : -vs.c[i][a];", "d[a] = 0;"),
     ("reflection flips every component", "cj[a] = crossed ? -vs.c[i][a] : vs.c[i][a];", "cj[a] = -vs.c[i][a];"),
+    ("implicit derivative of u_tau with the wrong sign", "T utau = root_of(utv, U, gpr / utv,",
+     "T utau = root_of(utv, U, -gpr / utv,"),
+    ("implicit derivative of u+ ignoring u_tau", "uplus_b = root_of(upv, utau, -wyb[k] / nu,",
+     "uplus_b = root_of(upv, utau, 0.0 * wyb[k] / nu,"),
     ("slip links counted as wall links",
      "if (!is_fluid(nb) && !slip_cross(bx, by, bz, vs.c[i][0], vs.c[i][1], vs.c[i][2])) {",
      "if (!is_fluid(nb)) {"),
@@ -133,6 +137,7 @@ PIN_TESTS = [
     (pins_slip.test_slip_faces_mirror_periodic_double, [(19, 0)]),
     (pins_slip.test_slip_top_over_bounce_back_ground_with_buildings, [()]),
     (pins_slip.test_slip_faces_are_not_wall_modeled, [()]),
+    (pins_wall.test_tangent_through_wall_model_matches_central_differences, [()]),
 ]
 
 
