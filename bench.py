@@ -7,8 +7,12 @@ fused bulk collide-and-stream + wall reconstruction over the whole domain.
 
 Prints one JSON line: MLUPS over all cells (value), the roofline entry of the
 dominant kernel (the bulk collide-and-stream kernel, timed with HIP events
-recorded on its own stream over the timed steps), and the FP64 CPU oracle
-timed on a bounded crop of the same workload on the host cores.
+recorded on its own stream over the timed steps), the rate of that kernel's
+access pattern without the collision (pattern_ceiling), and the FP64 CPU
+oracle timed on a bounded crop of the same workload on the host cores.  On
+the default channel workload the line also carries the adjoint/forward step
+time ratio of the porosity workload and the FP16-storage moment error
+against FP32 storage.
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 Workloads: channel (default), channel16, urban, urban16, big, big16 (1024^3
@@ -137,29 +141,34 @@ def cpu_baseline(name, budget_s=12.0, collision=0, fd_weight=0.0):
     t0 = time.perf_counter()
     s.step(n)
     dt = time.perf_counter() - t0
-    return {"value": round(case.ncells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(),
-            "kind": "oracle", "sample": f"{sample}, {n} steps, {dt:.1f} s"}
+    cores = O.num_threads()
+    # the same crop on one thread, on a quarter of the budget
+    O.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        s.step(1)
+        one1 = time.perf_counter() - t0
+        n1 = max(1, min(1000, int(budget_s / 4 / max(one1, 1e-6))))
+        t0 = time.perf_counter()
+        s.step(n1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        O.set_num_threads(cores)
+    return {"value": round(case.ncells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle", "sample": f"{sample}, {n} steps, {dt:.1f} s",
+            "one_thread": {"value": round(case.ncells * n1 / dt1 / 1e6, 3), "cores": 1,
+                           "sample": f"same crop, {n1} steps, {dt1:.1f} s"}}
 
 
-def copy_ceiling(torch, nbytes=4 << 30):
-    """Device-to-device copy GB/s (read + write) of a plain torch copy of
-    nbytes: a practical ceiling next to the 8 TB/s peak."""
-    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+def calibration_copy(torch, nbytes=4 << 30):
+    """One device copy of nbytes (a torch copy_): the known-size kernel the
+    FETCH_SIZE / WRITE_SIZE counters are scaled by."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    a.fill_(1.0)
-    for _ in range(3):
-        b.copy_(a)
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.copy_(a)
     torch.cuda.synchronize()
-    s.record()
-    reps = 10
-    for _ in range(reps):
-        b.copy_(a)
-    e.record()
-    torch.cuda.synchronize()
-    ms = s.elapsed_time(e) / reps
     del a, b
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    torch.cuda.empty_cache()
 
 
 def main():
@@ -169,7 +178,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="channel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run one 4 GiB device copy (the reference kernel of the PMC traffic calibration)")
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip the access-pattern ceiling (the bulk kernel's loads and stores without the collision)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="channel: skip the adjoint ratio and the FP16-vs-FP32 error added to the line")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "rr3"],
                     help="bulk collision model: BGK or recursive regularized (third order)")
     ap.add_argument("--vortices", type=int, default=0,
@@ -246,6 +260,15 @@ def main():
     mlups = N * args.steps / (ms_total * 1e-3) / 1e6
     print(f"[bench] timed {args.steps} steps: {ms_step:.4f} ms/step, {mlups:.1f} MLUPS (host {wall_s:.3f} s)",
           file=sys.stderr, flush=True)
+    # five more repeats of the same K steps, for the spread of the step time
+    reps = []
+    for _ in range(5):
+        ev0.record(stream)
+        lat.step(args.steps)
+        ev1.record(stream)
+        lat.sync()
+        reps.append(ev0.elapsed_time(ev1) / args.steps)
+    print(f"[bench] 5 repeats: median {np.median(reps):.4f} ms/step", file=sys.stderr, flush=True)
 
     # per-kernel times over the same number of steps, events on the library's stream
     lbm.lbm_profile(lat.ctx, True)
@@ -268,6 +291,13 @@ def main():
     step_bytes = nfluid * (2 * q * sb + 1) + (nfluid * (q * sb + 6 * rb) if fdw > 0 else 0)
     traffic = measured_traffic(args.workload, args.collision, fdw)
     diag = lat.diagnostics()
+    ceiling = None
+    if not args.no_ceiling:
+        # the same tiles, order, cells and slots as the bulk kernel, loads and
+        # stores only: the rate this access pattern reaches on this part
+        pms = lbm.lbm_stream_probe(lat.ctx, 40)
+        ceiling = {"gbs": round(k2_bytes / (pms * 1e-3) / 1e9, 1), "ms_per_launch": round(pms, 5),
+                   "bulk_fraction_of_ceiling": round(pms / k2_ms, 4)}
     out = {
         "metric": "MLUPS (million lattice-cell updates per second) per GPU",
         "value": round(mlups, 2),
@@ -288,19 +318,32 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": "k_bulk", "avg_launch_ms": round(k2_ms, 5), "alg_bytes_per_launch": k2_bytes},
+        "mflups": round(nfluid * args.steps / (ms_total * 1e-3) / 1e6, 2),
+        "repeat_ms_per_step": {"median": round(float(np.median(reps)), 5), "min": round(min(reps), 5),
+                               "max": round(max(reps), 5), "repeats": 5},
         "step_alg_gbs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
         "kernel_ms_per_step": {"wall_prepass_refwall": round(kms[0] / max(kcount[0], 1), 5),
                                "wall": round(kms[2] / max(kcount[2], 1), 5), "bulk": round(k2_ms, 5)},
         "mass_drift_rel": None,
     }
+    if ceiling is not None:
+        out["pattern_ceiling"] = ceiling
     if vortex_ms is not None:
         # host-timed: copy of the seed points (after a stream synchronisation) and the field kernel
         out["vortex_field_update_ms"] = round(vortex_ms, 4)
     out["mass"] = float(diag[0])
     del lat
     torch.cuda.empty_cache()
-    if not args.no_copy:
-        out["copy_ceiling_gbs"] = round(copy_ceiling(torch), 1)
+    if args.calibrate:
+        calibration_copy(torch)
+    if args.workload == "channel" and args.collision == "bgk" and not args.no_extras:
+        # the metric's other two parts on the same run: the adjoint/forward
+        # step-time ratio on the porosity workload, and the FP16-storage
+        # moment error against FP32 storage on this channel
+        print("[bench] adjoint/forward ratio (porous channel 128^3, FP32)", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_ratio(torch, lbm, make_case("adjoint")[0], "f32", 300, 20)
+        print("[bench] FP16 vs FP32 storage (channel, 100 steps)", file=sys.stderr, flush=True)
+        out["fp16_vs_fp32"] = fp16_vs_fp32(torch, lbm)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, collision=1 if args.collision == "rr3" else 0,
@@ -389,36 +432,58 @@ def bench_precision(args, torch, lbm):
 def bench_adjoint(args, torch, lbm, case, storage, wname):
     """Forward step vs hand-written reverse step on the porosity workload,
     and one full checkpointed gradient."""
+    r = adjoint_ratio(torch, lbm, case, storage, args.steps, args.warmup)
+    out = {
+        "metric": "adjoint/forward step time ratio",
+        "value": r["ratio"],
+        "unit": "ratio",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["forward_ms_per_step"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wname, "cells": case.ncells},
+    }
+    out.update({k: v for k, v in r.items() if k != "ratio"})
+    print(json.dumps(out), flush=True)
+
+
+def adjoint_ratio(torch, lbm, case, storage, K, warmup):
+    """Median of 5 repeats of K forward steps and of K reverse steps (half at
+    each parity) on the porosity workload, their ratio, and one full
+    checkpointed gradient (terminal and time-averaged objective, T = 400,
+    20 snapshots)."""
     lat = lbm.Lattice(case, storage=storage)
     N = case.ncells
     planes = case.extra["planes"]
-    lat.step(args.warmup)
+    lat.step(warmup)
     lat.sync()
     stream = lat.stream
     e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    K = args.steps
     torch.cuda.synchronize()
-    e[0].record(stream)
-    lat.step(K)
-    e[1].record(stream)
-    lat.sync()
-    fwd_ms = e[0].elapsed_time(e[1]) / K
+    fwd, adj = [], []
     lam = lat.new_adjoint()
     grad = lat.new_gradient()
-    lbm.lbm_adjoint_seed(lat.ctx, planes, lam)
-    lat.sync()
-    # half of the reverse steps at each parity (a forward step in between
-    # flips the parity; it is outside the timed brackets)
-    adj_total = 0.0
-    for half in (K // 2, K - K // 2):
-        e[2].record(stream)
-        for _ in range(half):
-            lbm.lbm_adjoint_step(lat.ctx, lam, grad)
-        e[3].record(stream)
+    for _ in range(5):
+        e[0].record(stream)
+        lat.step(K)
+        e[1].record(stream)
         lat.sync()
-        adj_total += e[2].elapsed_time(e[3])
-        lat.step(1)
-    adj_ms = adj_total / K
+        fwd.append(e[0].elapsed_time(e[1]) / K)
+        lbm.lbm_adjoint_seed(lat.ctx, planes, lam)
+        lat.sync()
+        # half of the reverse steps at each parity (a forward step in between
+        # flips the parity; it is outside the timed brackets)
+        adj_total = 0.0
+        for half in (K // 2, K - K // 2):
+            e[2].record(stream)
+            for _ in range(half):
+                lbm.lbm_adjoint_step(lat.ctx, lam, grad)
+            e[3].record(stream)
+            lat.sync()
+            adj_total += e[2].elapsed_time(e[3])
+            lat.step(1)
+        adj.append(adj_total / K)
+    fwd_ms = float(np.median(fwd))
+    adj_ms = float(np.median(adj))
     T, nsnap = 400, 20
     snaps = torch.empty(nsnap * lbm.lbm_state_bytes(lat.ctx), dtype=torch.uint8, device="cuda")
     t0 = time.perf_counter()
@@ -430,21 +495,50 @@ def bench_adjoint(args, torch, lbm, case, storage, wname):
     Jm, nfwd_m = lbm.lbm_gradient_mean(lat.ctx, T, planes, snaps, nsnap, lam, grad)
     grad_mean_s = time.perf_counter() - t0
     out = {
-        "metric": "adjoint/forward step time ratio",
-        "value": round(adj_ms / fwd_ms, 3),
-        "unit": "ratio",
-        "n_gpus": 1, "steps": K, "warmup": args.warmup,
-        "ms_per_step": round(fwd_ms, 5),
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": wname, "cells": N},
+        "ratio": round(adj_ms / fwd_ms, 3),
+        "workload": "porous_channel128_d3q19_adjoint",
+        "storage": storage,
+        "forward_ms_per_step": round(fwd_ms, 5),
         "forward_mlups": round(N / (fwd_ms * 1e-3) / 1e6, 1),
         "adjoint_ms_per_step": round(adj_ms, 5),
+        "repeats": 5,
         "gradient": {"T": T, "snapshots": nsnap, "forward_steps": nfwd, "seconds": round(grad_s, 3),
                      "J": J, "forward_only_seconds": round(T * fwd_ms * 1e-3, 3)},
         "gradient_time_averaged": {"T": T, "snapshots": nsnap, "forward_steps": nfwd_m,
                                    "seconds": round(grad_mean_s, 3), "J": Jm},
     }
-    print(json.dumps(out), flush=True)
+    del lat, lam, grad, snaps
+    torch.cuda.empty_cache()
+    return out
+
+
+def fp16_vs_fp32(torch, lbm, steps=100):
+    """FP16- against FP32-deviation storage on the channel workload, from the
+    same initial state, after ``steps`` steps: max-norm errors of rho and u
+    relative to the FP32 field's max-norm, the rms error of u, and the error
+    of the mean streamwise profile <u_x>(z)."""
+    from paper_2506_21804_amd import inputs as I
+    case = I.channel(384, 192, 192, q=27)
+    nx, ny, nz = case.shape
+    res = {}
+    for storage in ("f32", "f16"):
+        lat = lbm.Lattice(case, storage=storage)
+        lat.step(steps)
+        rho, u = lat.moments()
+        res[storage] = (rho.double(), u.double())
+        del lat
+        torch.cuda.empty_cache()
+    (r32, u32), (r16, u16) = res["f32"], res["f16"]
+    p32 = u32[0].reshape(nz, ny * nx).mean(dim=1)
+    p16 = u16[0].reshape(nz, ny * nx).mean(dim=1)
+    out = {"workload": "channel384x192x192_d3q27_smag_wallmodel", "steps": steps,
+           "rho": float((r16 - r32).abs().max() / r32.abs().max()),
+           "u": float((u16 - u32).abs().max() / u32.abs().max()),
+           "u_rms": float(((u16 - u32) ** 2).mean().sqrt() / (u32 ** 2).mean().sqrt()),
+           "mean_profile_ux": float((p16 - p32).abs().max() / p32.abs().max())}
+    del res, r32, u32, r16, u16
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

@@ -98,6 +98,17 @@ typedef struct {
                        * hybrid (fd_weight 0), z0 > 0; these cells are never
                        * wall-modeled.  0 = off. */
   double rho_out;     /* outlet density, > 0 (open_x only) */
+  int slip;           /* full-slip box faces (Sec. 3.2, the outer walls of the street
+                       * canyon): bit 2a the low face of axis a (x 0, y 1, z 2), bit
+                       * 2a+1 the high face; only on non-periodic axes, not on open
+                       * x faces, not on the top face with a lid.  A population
+                       * that crosses such faces is reflected specularly: it
+                       * arrives at the cell one step along its direction with
+                       * the crossed components set to zero, with those velocity
+                       * components negated (halfway bounce-back where that cell
+                       * is solid).  These links are not walls of the wall model;
+                       * the voxel wall distance mirrors the geometry across them.
+                       * 0 = none (outside a non-periodic axis is a no-slip wall). */
   void *stream;       /* hipStream_t for all device work (NULL = null stream) */
 } lbm_params;
 
@@ -269,6 +280,25 @@ int lbm_wall_records(lbm_ctx *ctx, int *cell, int *ref, double *normal, double *
  * resets, the accumulated milliseconds and launch counts. */
 int lbm_profile(lbm_ctx *ctx, int enable);
 int lbm_profile_read(lbm_ctx *ctx, double ms[3], long long count[3]);
+
+/* Memory-system ceiling of the bulk kernel's accesses: n >= 2 launches, at
+ * alternating step parity, of a kernel with the bulk kernel's tiles, block
+ * order, cell selection and slot map that loads every slot an updated cell
+ * reads and stores the value back unchanged (no collision; the state is not
+ * modified).  *ms_per_launch receives the mean launch time from HIP events on
+ * the context's stream.  The bytes moved per launch are those of the bulk
+ * kernel.  Synchronises. */
+int lbm_stream_probe(lbm_ctx *ctx, int n, double *ms_per_launch);
+
+/* Host-only inspection of the in-place AA streaming map (Sec. 2.3 stores the
+ * populations as structure of arrays; this library updates them in one
+ * buffer): builds the cell flags from p and mask (as lbm_init does) and, for
+ * every fluid cell c and direction i, gives the slot s = dir * N + cell from
+ * which the kernels read f_i(c) (read[i * N + c]) and to which they write
+ * f*_i(c) (write[i * N + c]) at step parity `parity` (0 even, 1 odd), using
+ * the kernels' own slot functions; -1 at solid cells.  read, write: host
+ * int64 [q][N].  No device work; LBM_EINVAL for invalid parameters. */
+int lbm_slot_map(const lbm_params *p, const uint8_t *mask, int parity, long long *read, long long *write);
 
 const char *lbm_last_error(const lbm_ctx *ctx);
 /* Releases the context (host memory only; the workspace stays the caller's). */

@@ -20,8 +20,8 @@ __all__ = [
     "lbm_state_bytes", "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes",
     "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural",
     "lbm_gradient", "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
-    "lbm_set_inflow_vortices", "lbm_gradient_mean", "lbm_last_error", "lbm_free",
-    "Lattice", "D3Q19", "D3Q27", "F64", "F32DEV", "F16DEV",
+    "lbm_set_inflow_vortices", "lbm_gradient_mean", "lbm_stream_probe", "lbm_slot_map", "lbm_last_error",
+    "lbm_free", "params_for", "Lattice", "D3Q19", "D3Q27", "F64", "F32DEV", "F16DEV",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbm_hip.so")
@@ -51,6 +51,7 @@ class Params(C.Structure):
         ("fd_weight", C.c_double),
         ("open_x", C.c_int),
         ("rho_out", C.c_double),
+        ("slip", C.c_int),
         ("stream", C.c_void_p),
     ]
 
@@ -105,6 +106,8 @@ def load():
         "lbm_profile_read": (i, [vp, vp, vp]),
         "lbm_set_inflow_vortices": (i, [vp, i, vp, vp, d, d]),
         "lbm_gradient_mean": (i, [vp, i, vp, vp, i, vp, vp, C.POINTER(d), C.POINTER(ll)]),
+        "lbm_stream_probe": (i, [vp, i, C.POINTER(d)]),
+        "lbm_slot_map": (i, [C.POINTER(Params), vp, i, vp, vp]),
         "lbm_last_error": (C.c_char_p, [vp]),
         "lbm_free": (None, [vp]),
     }
@@ -123,7 +126,8 @@ def exported_symbols():
             "lbm_save_state", "lbm_load_state", "lbm_objective", "lbm_adjoint_bytes", "lbm_adjoint_seed",
             "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural", "lbm_gradient",
             "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
-            "lbm_set_inflow_vortices", "lbm_gradient_mean", "lbm_last_error", "lbm_free"]
+            "lbm_set_inflow_vortices", "lbm_gradient_mean", "lbm_stream_probe", "lbm_slot_map",
+            "lbm_last_error", "lbm_free"]
 
 
 def _dptr(t):
@@ -173,7 +177,7 @@ def _check(ctx, rc):
 
 def make_params(q, shape, periodic=(1, 1, 1), storage=F64, tau0=0.6, cs_smag=0.0, force=(0.0, 0.0, 0.0),
                 wall_model=0, kappa=0.41, E=9.0, fringe_len=0, u_ref=0.0, z0=1.0, lid=0, collision=0,
-                fd_weight=0.0, open_x=0, rho_out=1.0, stream=None) -> Params:
+                fd_weight=0.0, open_x=0, rho_out=1.0, slip=0, stream=None) -> Params:
     p = Params()
     p.lattice = q
     p.nx, p.ny, p.nz = shape
@@ -186,6 +190,7 @@ def make_params(q, shape, periodic=(1, 1, 1), storage=F64, tau0=0.6, cs_smag=0.0
     p.collision = COLLISION_NAMES.get(collision, collision) if isinstance(collision, str) else collision
     p.fd_weight = fd_weight
     p.open_x, p.rho_out = int(open_x), rho_out
+    p.slip = int(slip)
     p.stream = stream
     return p
 
@@ -380,6 +385,37 @@ def lbm_profile_read(ctx):
     return np.array(ms[:]), np.array(cnt[:])
 
 
+def lbm_stream_probe(ctx, n=20) -> float:
+    """Mean milliseconds per launch of the bulk kernel's access pattern
+    without the collision (n launches, alternating parity)."""
+    ms = C.c_double()
+    _check(ctx, load().lbm_stream_probe(ctx, int(n), C.byref(ms)))
+    return ms.value
+
+
+def lbm_slot_map(p: Params, mask, parity):
+    """(read, write) int64 [q][N] slot indices of the in-place streaming map
+    at the given parity, evaluated on the host (no GPU needed)."""
+    q, N = p.lattice, p.nx * p.ny * p.nz
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    rd = np.empty((q, N), np.int64)
+    wr = np.empty((q, N), np.int64)
+    rc = load().lbm_slot_map(C.byref(p), _hptr(m), int(parity), _hptr(rd), _hptr(wr))
+    if rc != OK:
+        raise LbmError(rc, load().lbm_last_error(None).decode())
+    return rd, wr
+
+
+def params_for(case, storage="f64", stream=None) -> Params:
+    """lbm_params of an ``inputs.Case``."""
+    return make_params(case.q, case.shape, periodic=case.periodic, storage=storage, tau0=case.tau0,
+                       cs_smag=case.cs_smag, force=case.force, wall_model=case.wall_model, kappa=case.kappa,
+                       E=case.E, fringe_len=case.fringe_len, u_ref=case.u_ref, z0=case.z0, lid=case.lid,
+                       collision=getattr(case, "collision", 0), fd_weight=getattr(case, "fd_weight", 0.0),
+                       open_x=getattr(case, "open_x", 0), rho_out=getattr(case, "rho_out", 1.0),
+                       slip=getattr(case, "slip", 0), stream=stream)
+
+
 def lbm_last_error(ctx) -> str:
     return load().lbm_last_error(ctx).decode()
 
@@ -408,12 +444,7 @@ class Lattice:
         self.N = int(np.prod(self.shape))
         self.storage = STORAGE_NAMES[storage] if isinstance(storage, str) else storage
         self.rdtype = torch.float64 if self.storage == F64 else torch.float32
-        self.p = make_params(case.q, case.shape, periodic=case.periodic, storage=self.storage, tau0=case.tau0,
-                             cs_smag=case.cs_smag, force=case.force, wall_model=case.wall_model, kappa=case.kappa,
-                             E=case.E, fringe_len=case.fringe_len, u_ref=case.u_ref, z0=case.z0, lid=case.lid,
-                             collision=getattr(case, "collision", 0), fd_weight=getattr(case, "fd_weight", 0.0),
-                             open_x=getattr(case, "open_x", 0), rho_out=getattr(case, "rho_out", 1.0),
-                             stream=stream.cuda_stream)
+        self.p = params_for(case, storage=self.storage, stream=stream.cuda_stream)
         porous = case.porosity is not None
         nbytes = lbm_workspace_bytes(self.p, case.mask, porous)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")

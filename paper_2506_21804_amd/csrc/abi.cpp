@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "lattice.h"
 
 using namespace lbmk;
 
@@ -97,6 +98,15 @@ bool params_ok(const lbm_params *p, std::string &msg) {
     msg = "open_x must be 0 or 1";
     return false;
   }
+  for (int a = 0; a < 3; ++a)
+    if (p->periodic[a] && ((p->slip >> (2 * a)) & 3)) {
+      msg = "full-slip faces need a non-periodic axis";
+      return false;
+    }
+  if ((p->slip & ~63) || (p->open_x && (p->slip & 3)) || (p->lid && (p->slip & 32))) {
+    msg = "slip: six face bits, not on open x faces, not on the top face with a lid";
+    return false;
+  }
   if (p->open_x && (p->periodic[0] || p->nx < 3 || p->fringe_len > p->nx - 2 || p->fd_weight > 0.0 ||
                     p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0 || !(p->rho_out > 0.0) ||
                     !std::isfinite(p->rho_out) || !(p->z0 > 0.0) || !std::isfinite(p->u_ref))) {
@@ -108,7 +118,8 @@ bool params_ok(const lbm_params *p, std::string &msg) {
 }
 
 struct Layout {
-  size_t pop, flags, phi, tables, vel, inflow, vort, wcell, wref, wrefwall, wlist, wrec, partial, result, errflag,
+  size_t pop, flags, phi, tables, vel, inflow, vort, wcell, wref, wrefwall, wlist, wrec, rcell, roff, rrec, partial,
+      result, errflag,
       total;
 };
 
@@ -141,6 +152,13 @@ Layout layout_of(const lbm_params &p, long long nwall, bool porous) {
   off += align_up((size_t)nwall * sizeof(int));
   L.wrec = off;
   off += align_up((size_t)nwall * WR_COUNT * sizeof(double));
+  // the records grouped by reference cell (reverse step)
+  L.rcell = off;
+  off += align_up((size_t)nwall * sizeof(int));
+  L.roff = off;
+  off += align_up(((size_t)nwall + 1) * sizeof(int));
+  L.rrec = off;
+  off += align_up((size_t)nwall * sizeof(int));
   L.partial = off;
   off += align_up((size_t)PARTIAL_SLOTS * 8 * sizeof(double));
   L.result = off;
@@ -206,6 +224,37 @@ void prof_end(lbm_ctx *ctx, int k) {
 
 }  // namespace lbmk
 
+namespace {
+// Slots of every fluid cell at one parity, by the kernels' own slot
+// functions: the plain path for cells without solid links (every cell at
+// even parity), the bounce-back map for the others.
+template <int Q, bool ODD, bool SLIP>
+void slot_map_q(const KArgs &k, const uint8_t *flags, long long *rd, long long *wr) {
+  const long long N = k.N;
+  for (long long c = 0; c < N; ++c) {
+    if (!(flags[c] & FL_FLUID)) {
+      for (int i = 0; i < Q; ++i) rd[i * N + c] = wr[i * N + c] = -1;
+      continue;
+    }
+    int x, y, z;
+    cell_xyz((int)c, k, x, y, z);
+    const Nb n = make_nb(x, y, z, k);
+    const LinkMask sm = (ODD && (flags[c] & FL_NEAR)) ? solid_mask<Q, SLIP>(n, flags) : 0u;
+    for (int i = 0; i < Q; ++i) {
+      if (sm != 0u) {
+        rd[i * N + c] = (long long)read_slot<Q, ODD, SLIP>(n, sm, i, (size_t)N);
+        wr[i * N + c] = (long long)write_slot<Q, ODD, SLIP>(n, sm, i, (size_t)N);
+      } else {
+        int dr, dw;
+        const int ir = plain_read<Q, ODD>(n, i, dr), iw = plain_write<Q, ODD>(n, i, dw);
+        rd[i * N + c] = (long long)dr * N + ir;
+        wr[i * N + c] = (long long)dw * N + iw;
+      }
+    }
+  }
+}
+}  // namespace
+
 extern "C" {
 
 size_t lbm_workspace_bytes(const lbm_params *p, const uint8_t *mask, int porous) {
@@ -264,6 +313,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   ctx->stream = (hipStream_t)p->stream;
   ctx->porous = porosity != nullptr;
   ctx->has_solid = g.has_solid;
+  ctx->has_slip = p->slip != 0 && g.has_solid;
   ctx->has_lid = g.has_lid;
   ctx->has_open = g.has_open;
   char *base = (char *)workspace;
@@ -279,6 +329,9 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   ctx->wref = (int *)(base + L.wref);
   ctx->wrefwall = (uint8_t *)(base + L.wrefwall);
   ctx->wlist_refwall = (int *)(base + L.wlist);
+  ctx->wref_cell = (int *)(base + L.rcell);
+  ctx->wref_off = (int *)(base + L.roff);
+  ctx->wref_rec = (int *)(base + L.rrec);
   ctx->wrec = (double *)(base + L.wrec);
   ctx->partial = (double *)(base + L.partial);
   ctx->npartial = PARTIAL_SLOTS;
@@ -305,6 +358,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   k.fdw = p->fd_weight;
   k.vel = p->fd_weight > 0.0 ? ctx->vel : nullptr;
   k.open_x = p->open_x;
+  k.slip = p->slip;
   k.inflow = ctx->inflow;
   k.rho_out = p->open_x ? p->rho_out : 1.0;
   // inflow profile u_in(z) and fringe weights lambda(x)
@@ -364,6 +418,25 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
       return fail(e, "upload wall references");
     if ((e = hipMemcpy(ctx->wrec, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
       return fail(e, "upload wall records");
+    // records grouped by reference cell, in increasing cell and record order
+    std::vector<int> order((size_t)nwall);
+    for (long long k = 0; k < nwall; ++k) order[(size_t)k] = (int)k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return g.wref[a] < g.wref[b]; });
+    std::vector<int> rcell, roff;
+    for (size_t j = 0; j < order.size(); ++j)
+      if (j == 0 || g.wref[order[j]] != g.wref[order[j - 1]]) {
+        rcell.push_back(g.wref[order[j]]);
+        roff.push_back((int)j);
+      }
+    roff.push_back((int)nwall);
+    ctx->nref = (int)rcell.size();
+    if ((e = hipMemcpy(ctx->wref_cell, rcell.data(), rcell.size() * sizeof(int), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(ctx->wref_off, roff.data(), roff.size() * sizeof(int), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(ctx->wref_rec, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+      return fail(e, "upload wall reference groups");
   }
   if (dev_scratch_setup(ctx) != LBM_OK || dev_fill(ctx, ctx->errflag, ALIGN) != LBM_OK ||
       (p->open_x && dev_inflow(ctx, 0, 1.0) != LBM_OK) ||
@@ -507,7 +580,7 @@ int lbm_objective(lbm_ctx *ctx, const int planes[2], double *J) {
 
 size_t lbm_adjoint_bytes(const lbm_ctx *ctx) {
   if (!ctx) return 0;
-  return adj_layout(ctx->N, ctx->q, ctx->p.storage == LBM_F64 ? 8 : 4).bytes;
+  return adj_layout(ctx->N, ctx->q, ctx->p.storage == LBM_F64 ? 8 : 4, ctx->nwall).bytes;
 }
 
 static bool adj_aligned(const void *p) { return ((uintptr_t)p & 7u) == 0; }
@@ -522,7 +595,6 @@ int lbm_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lambda) {
 
 int lbm_adjoint_step(lbm_ctx *ctx, void *lambda, void *grad_phi) {
   if (!ctx || !lambda || !grad_phi) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
-  if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
   if (ctx->ka.fdw > 0.0)
     return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the finite-difference strain");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
@@ -554,7 +626,6 @@ static int gradient_sweep(lbm_ctx *ctx, int T, const int planes[2], void *snapsh
   if (!ctx) return LBM_EINVAL;
   if (T < 1 || nsnap < 1 || !snapshots || !lambda || !grad_phi || !planes)
     return set_err(ctx, LBM_EINVAL, "gradient needs T >= 1, nsnap >= 1 and non-null buffers");
-  if (ctx->nwall > 0) return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the wall model");
   if (ctx->ka.fdw > 0.0)
     return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the finite-difference strain");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
@@ -722,6 +793,40 @@ int lbm_profile(lbm_ctx *ctx, int enable) {
       }
   }
   ctx->profiling = enable != 0;
+  return LBM_OK;
+}
+
+int lbm_stream_probe(lbm_ctx *ctx, int n, double *ms_per_launch) {
+  if (!ctx) return LBM_EINVAL;
+  if (n < 2 || !ms_per_launch) return set_err(ctx, LBM_EINVAL, "need n >= 2 launches and an output");
+  return dev_stream_probe(ctx, n, ms_per_launch);
+}
+
+
+int lbm_slot_map(const lbm_params *p, const uint8_t *mask, int parity, long long *read, long long *write) {
+  std::string msg;
+  if (!params_ok(p, msg)) return set_err(nullptr, LBM_EINVAL, msg);
+  if (!read || !write || (parity != 0 && parity != 1))
+    return set_err(nullptr, LBM_EINVAL, "need read and write arrays and parity 0 or 1");
+  Geometry g;
+  int rc = build_geometry(*p, mask, g, msg);
+  if (rc != LBM_OK) return set_err(nullptr, rc, msg);
+  KArgs k{};
+  k.nx = p->nx;
+  k.ny = p->ny;
+  k.nz = p->nz;
+  k.N = p->nx * p->ny * p->nz;
+  for (int a = 0; a < 3; ++a) k.per[a] = p->periodic[a] ? 1 : 0;
+  k.slip = p->slip;
+  const uint8_t *fl = g.flags.data();
+  const bool slip = p->slip != 0;
+  if (p->lattice == LBM_D3Q19) {
+    if (parity) slip ? slot_map_q<19, true, true>(k, fl, read, write) : slot_map_q<19, true, false>(k, fl, read, write);
+    else slip ? slot_map_q<19, false, true>(k, fl, read, write) : slot_map_q<19, false, false>(k, fl, read, write);
+  } else {
+    if (parity) slip ? slot_map_q<27, true, true>(k, fl, read, write) : slot_map_q<27, true, false>(k, fl, read, write);
+    else slip ? slot_map_q<27, false, true>(k, fl, read, write) : slot_map_q<27, false, false>(k, fl, read, write);
+  }
   return LBM_OK;
 }
 

@@ -32,6 +32,7 @@
 
 #include "internal.h"
 #include "lattice.h"
+#include "wall.h"
 
 namespace lbmk {
 
@@ -430,9 +431,12 @@ __device__ __forceinline__ R collide_bulk_rr_vjp(const R g[Q], const R mu[Q], R 
 }
 
 // Cell that wrote the adjoint that cell n reads for direction i (see above).
-template <int Q, bool SOLID>
-__device__ __forceinline__ int writer_of(const Nb &n, unsigned sm, int i) {
+template <int Q, int SOLID>
+__device__ __forceinline__ int writer_of(const Nb &n, LinkMask sm, int i) {
   if (SOLID && ((sm >> Lat<Q>::opp(i)) & 1u)) return n.cell;
+  // across full-slip faces: the cell the reflected population arrives at
+  if (SOLID == 2 && ((sm >> (32 + Lat<Q>::opp(i))) & 1u))
+    return n.cell + reflect_off<Q>(n, i, +1, face_axes(cross_faces<Q>(n, i, +1)));
   return n.cell + nb_off<Q>(n, i, +1);
 }
 
@@ -671,7 +675,7 @@ __device__ __forceinline__ CellSeed cell_seed(const R g[Q], int x, int p0, int p
 
 // SEED = true (time-averaged objectives): the step also adds w dJ/df of the
 // state it reads (the objective's seed at that step), after the transpose.
-template <int Q, typename S, bool ODD, bool POROUS, bool SOLID, bool RR, bool SEED = false, bool OPEN = false>
+template <int Q, typename S, bool ODD, bool POROUS, int SOLID, bool RR, bool SEED = false, bool OPEN = false>
 __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                     typename Store<S>::R *__restrict__ dev,
                                                     const double *__restrict__ m_prev, double *__restrict__ m_next,
@@ -684,24 +688,25 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
   if (!atile_xyz(k, t, x, y, z)) return;
   const Nb n = make_nb(x, y, z, k);
   const uint8_t fl = flags[n.cell];
-  if (!(fl & FL_FLUID)) return;
-  unsigned sm = 0;
-  if (SOLID && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  // wall cells have a reverse kernel of their own (k_adjoint_wall)
+  if (!(fl & FL_FLUID) || (fl & FL_WALL)) return;
+  LinkMask sm = 0;
+  if (SOLID && (fl & FL_NEAR)) sm = solid_mask<Q, SOLID == 2>(n, flags);
   const size_t N = (size_t)k.N;
   if (fl & FL_LID) {
     // the lid output does not depend on the state: only the seed remains
     if constexpr (SEED) {
       R g[Q];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+      for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD, SOLID == 2>(n, sm, i, N));
       const CellSeed cs = cell_seed<Q, R>(g, x, p0, p1, cnt, sw, k);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) dev[read_slot<Q, ODD>(n, sm, i, N)] = (R)cs.template kin<Q>(i);
+      for (int i = 0; i < Q; ++i) dev[read_slot<Q, ODD, SOLID == 2>(n, sm, i, N)] = (R)cs.template kin<Q>(i);
       m_next[n.cell] = cs.base;
       return;
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dev[read_slot<Q, ODD>(n, sm, i, N)] = R(0);
+    for (int i = 0; i < Q; ++i) dev[read_slot<Q, ODD, SOLID == 2>(n, sm, i, N)] = R(0);
     m_next[n.cell] = 0.0;
     return;
   }
@@ -710,25 +715,25 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
   if (x >= k.fringe_start && !(OPEN && (fl & FL_OUTLET))) scale = 1.0 - (double)static_cast<const R *>(k.lam)[x];
   // mu_i = scale (M[writer_i] + d_i); the rest direction's writer is the cell itself
   const double mx = m_prev[n.cell];
-  const double d0 = (double)dev[write_slot<Q, ODD>(n, sm, 0, N)];
+  const double d0 = (double)dev[write_slot<Q, ODD, SOLID == 2>(n, sm, 0, N)];
   const double m = scale * (mx + d0);
   R dmu[Q];
   dmu[0] = R(0);
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     const double mw = m_prev[writer_of<Q, SOLID>(n, sm, i)];
-    const double di = (double)dev[write_slot<Q, ODD>(n, sm, i, N)];
+    const double di = (double)dev[write_slot<Q, ODD, SOLID == 2>(n, sm, i, N)];
     dmu[i] = (R)(scale * ((mw - mx) + (di - d0)));
   }
   R g[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+  for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD, SOLID == 2>(n, sm, i, N));
   const R ph = POROUS ? phi[n.cell] : R(1);
   CellSeed cs{};
   if constexpr (SEED) cs = cell_seed<Q, R>(g, x, p0, p1, cnt, sw, k);
   auto store = [&](int i, R v) {
     if constexpr (SEED) v += (R)cs.template kin<Q>(i);
-    dev[read_slot<Q, ODD>(n, sm, i, N)] = v;
+    dev[read_slot<Q, ODD, SOLID == 2>(n, sm, i, N)] = v;
   };
   R phib;
   if constexpr (OPEN) {
@@ -760,10 +765,287 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
   if (POROUS) grad[n.cell] += (double)phib;
 }
 
+// ---------------------------------------------------------------------------
+// Wall model (Sec. 2.2.1).  A wall cell's output depends on its own
+// populations and, through its record (t, u_tan, G, tau_b), on the velocity
+// of its reference cell.  The reverse step of a wall cell pushes the adjoint
+// of its outputs back through the reconstruction collision to its own
+// populations, and through the record to the reference cell's density and
+// momentum; a second pass adds the latter to the reference cells' adjoints.
+// ---------------------------------------------------------------------------
+
+// Adjoints of a record's values.
+template <typename R>
+struct WallBar {
+  R t[3], utan, G, tau;
+};
+
+// Vector-Jacobian product of the wall reconstruction collision (sigma = 0,
+// modeled velocity v = u_tan t + (u.n) n, non-equilibrium -3 w rho tau G
+// (c.t)(c.n), Guo source at v; third-order equilibrium with RR) in precision
+// R, for the record held fixed: the adjoint of input population i goes to
+// out(i, value); the adjoints of the record's values to rb.
+template <int Q, typename R, bool RR, typename OUT>
+__device__ __forceinline__ void wall_collide_vjp(const R g[Q], const R mu[Q], const R nv[3], const R tv[3], R utan,
+                                                 R G, R tau, const KArgs &k, OUT out, WallBar<R> &rb) {
+  // ---- forward recomputation (as in the wall kernel)
+  R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += g[i];
+    acc(jx, Lat<Q>::c(i, 0), g[i]);
+    acc(jy, Lat<Q>::c(i, 1), g[i]);
+    acc(jz, Lat<Q>::c(i, 2), g[i]);
+  }
+  const R rho = R(1) + drho;
+  const R Fx = R(k.F[0]), Fy = R(k.F[1]), Fz = R(k.F[2]);
+  const R ir = R(1) / rho;
+  const R ux = (jx + R(0.5) * Fx) * ir, uy = (jy + R(0.5) * Fy) * ir, uz = (jz + R(0.5) * Fz) * ir;
+  const R nx = nv[0], ny = nv[1], nz = nv[2], tx = tv[0], ty = tv[1], tz = tv[2];
+  const R un = ux * nx + uy * ny + uz * nz;
+  const R vx = utan * tx + un * nx, vy = utan * ty + un * ny, vz = utan * tz + un * nz;
+  const R vv = vx * vx + vy * vy + vz * vz;
+  const R vF = vx * Fx + vy * Fy + vz * Fz;
+  const R om = R(1) / tau;
+  const R c1 = R(1) - om, c2 = R(1) - R(0.5) * om;
+  const R fd = R(-3) * rho * tau * G;
+  // ---- reverse through the outputs
+  R s0 = R(0), s1 = R(0), stn = R(0), sg = R(0);
+  R evx = R(0), evy = R(0), evz = R(0);  // sum mu w (3 + 9 c.v) c
+  R gux = R(0), guy = R(0), guz = R(0);  // sum mu w 9 (c.F) c
+  R snx = R(0), sny = R(0), snz = R(0);  // sum mu w (c.n) c
+  R M[7];
+#pragma unroll
+  for (int m = 0; m < 7; ++m) M[m] = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+    const R mw = mu[i] * R(Lat<Q>::w(i));
+    const R cv = dot3(cx, cy, cz, vx, vy, vz);
+    const R ct = dot3(cx, cy, cz, tx, ty, tz);
+    const R cn = dot3(cx, cy, cz, nx, ny, nz);
+    const R cF = dot3(cx, cy, cz, Fx, Fy, Fz);
+    s0 += mw;
+    s1 += mw * (R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv);
+    stn += mw * ct * cn;
+    sg += mw * (R(3) * (cF - vF) + R(9) * cv * cF);
+    const R te = mw * (R(3) + R(9) * cv);
+    acc(evx, cx, te);
+    acc(evy, cy, te);
+    acc(evz, cz, te);
+    const R tg = mw * R(9) * cF;
+    acc(gux, cx, tg);
+    acc(guy, cy, tg);
+    acc(guz, cz, tg);
+    const R tn = mw * cn;
+    acc(snx, cx, tn);
+    acc(sny, cy, tn);
+    acc(snz, cz, tn);
+    if constexpr (RR) {
+#pragma unroll
+      for (int kk = 0; kk < H3Basis<Q>::n; ++kk) {
+        const double pk = H3Basis<Q>::P(kk, i);
+        if (pk != 0.0) M[kk] += mw * R(pk);
+      }
+    }
+  }
+  // equilibrium and Guo source: drho directly, rho, and v
+  R drhob = s0;
+  R rhob = s1 + c1 * R(-3) * tau * G * stn;
+  R vxb = rho * (evx - R(3) * vx * s0) + c2 * (gux - R(3) * Fx * s0);
+  R vyb = rho * (evy - R(3) * vy * s0) + c2 * (guy - R(3) * Fy * s0);
+  R vzb = rho * (evz - R(3) * vz * s0) + c2 * (guz - R(3) * Fz * s0);
+  if constexpr (RR) {
+    // third-order equilibrium: rho v v v projected on the lattice's Hermite components
+    constexpr H3Norms<Q> nrm = h3_norms<Q>();
+    R Ab[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) Ab[m] = R(0);
+#pragma unroll
+    for (int kk = 0; kk < H3Basis<Q>::n; ++kk) {
+      const R mk = M[kk] * R(1.0 / nrm.v[kk]);
+      Ab[H3Basis<Q>::c0(kk)] += mk;
+      if (H3Basis<Q>::sgn(kk) > 0.0) Ab[H3Basis<Q>::c1(kk)] += mk;
+      if (H3Basis<Q>::sgn(kk) < 0.0) Ab[H3Basis<Q>::c1(kk)] -= mk;
+    }
+    // xxy, xxz, xyy, yyz, xzz, yzz, xyz
+    rhob += Ab[0] * vx * vx * vy + Ab[1] * vx * vx * vz + Ab[2] * vx * vy * vy + Ab[3] * vy * vy * vz +
+            Ab[4] * vx * vz * vz + Ab[5] * vy * vz * vz + Ab[6] * vx * vy * vz;
+    vxb += rho * (Ab[0] * R(2) * vx * vy + Ab[1] * R(2) * vx * vz + Ab[2] * vy * vy + Ab[4] * vz * vz + Ab[6] * vy * vz);
+    vyb += rho * (Ab[0] * vx * vx + Ab[2] * R(2) * vx * vy + Ab[3] * R(2) * vy * vz + Ab[5] * vz * vz + Ab[6] * vx * vz);
+    vzb += rho * (Ab[1] * vx * vx + Ab[3] * vy * vy + Ab[4] * R(2) * vx * vz + Ab[5] * R(2) * vy * vz + Ab[6] * vx * vy);
+  }
+  // the record: c1 fd w (c.t)(c.n) and v = u_tan t + un n
+  rb.tau = stn * (fd * om * om + c1 * R(-3) * rho * G) + sg * R(0.5) * om * om;
+  rb.G = stn * c1 * R(-3) * rho * tau;
+  rb.utan = vxb * tx + vyb * ty + vzb * tz;
+  rb.t[0] = c1 * fd * snx + utan * vxb;
+  rb.t[1] = c1 * fd * sny + utan * vyb;
+  rb.t[2] = c1 * fd * snz + utan * vzb;
+  // the cell's own velocity enters through un = u.n; u = (j + F/2)/rho
+  const R unb = vxb * nx + vyb * ny + vzb * nz;
+  const R uxb = unb * nx, uyb = unb * ny, uzb = unb * nz;
+  rhob -= (uxb * ux + uyb * uy + uzb * uz) * ir;
+  const R mxb = uxb * ir, myb = uyb * ir, mzb = uzb * ir;
+  drhob += rhob;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    R v = drhob;
+    acc(v, Lat<Q>::c(i, 0), mxb);
+    acc(v, Lat<Q>::c(i, 1), myb);
+    acc(v, Lat<Q>::c(i, 2), mzb);
+    out(i, v);
+  }
+}
+
+// Reverse of the record (FP64): from the adjoints of (t, u_tan, G, tau_b) to
+// those of the reference cell's density and momentum j (u = (j + F/2)/rho),
+// through t = u_t/|u_t|, the friction velocity (the root of g(U/u_tau) =
+// y_r u_tau/nu, implicit derivative), u+_b (the root of g(u+) = y_b u_tau/nu,
+// or U/u_tau when the reference is the wall cell itself), G(u_tau) and
+// tau_b(G).  An inactive record (|u_t| at or below 1e-300, or a failed solve)
+// is constant: zero adjoint.
+__device__ __forceinline__ void wall_record_vjp(const WallRec &w, const double u[3], double rho, const double n[3],
+                                                double yr, double yb, bool self, const KArgs &k,
+                                                const double tb[3], double utanb, double Gb, double taub,
+                                                double &rhob, double jb[3]) {
+  rhob = 0.0;
+  jb[0] = jb[1] = jb[2] = 0.0;
+  if (!w.active) return;
+  const double nu = k.nu, C2 = k.cs2, inv_E = 1.0 / k.E, kap = k.kappa;
+  const double ut = w.utau, U = w.U;
+  const double Gt = Gb + 3.0 * C2 * taub;
+  const double sq = sqrt(nu * nu + 4.0 * C2 * ut * ut);
+  const double dG = 4.0 * ut / (nu + sq) - 8.0 * C2 * ut * ut * ut / (sq * (nu + sq) * (nu + sq));
+  double utb = Gt * dG, Ub = 0.0;
+  if (self) {
+    Ub = utanb;  // u_tan = u_tau (U / u_tau) = U
+  } else {
+    double gv, gdb;
+    spalding_gd(w.uplus, kap, inv_E, gv, gdb);
+    utb += utanb * (w.uplus + ut * (yb / nu) / gdb);
+  }
+  double gv, gdx;
+  spalding_gd(U / ut, kap, inv_E, gv, gdx);
+  Ub += utb * (gdx / ut) / (gdx * U / (ut * ut) + yr / nu);
+  // u_t = u - (u.n) n, U = |u_t|, t = u_t / U
+  const double tt = tb[0] * w.t[0] + tb[1] * w.t[1] + tb[2] * w.t[2];
+  double a[3];
+  for (int d = 0; d < 3; ++d) a[d] = Ub * w.t[d] + (tb[d] - tt * w.t[d]) / U;
+  const double an = a[0] * n[0] + a[1] * n[1] + a[2] * n[2];
+  for (int d = 0; d < 3; ++d) a[d] -= an * n[d];
+  for (int d = 0; d < 3; ++d) jb[d] = a[d] / rho;
+  rhob = -(a[0] * u[0] + a[1] * u[1] + a[2] * u[2]) / rho;
+}
+
+// Reverse step of the wall cells, one thread per record.  Reads the adjoint
+// at the cell's write slots (common mode and deviations as in k_adjoint),
+// recomputes the record from the reference cell's state, writes the cell's
+// own adjoint and stores the reference cell's density and momentum adjoints
+// in wadj[4][nwall].
+template <int Q, typename S, bool ODD, bool RR, bool SEED, bool SLIP>
+__global__ __launch_bounds__(256) void k_adjoint_wall(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                      typename Store<S>::R *__restrict__ dev,
+                                                      const double *__restrict__ m_prev, double *__restrict__ m_next,
+                                                      const int *__restrict__ wcell, const int *__restrict__ wref,
+                                                      const double *__restrict__ rec, int nwall,
+                                                      double *__restrict__ wadj, KArgs k, int p0, int p1,
+                                                      const double *__restrict__ cnt, double sw) {
+  using R = typename Store<S>::R;
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nwall) return;
+  const int b = wcell[w], r = wref[w];
+  int x, y, z;
+  cell_xyz(b, k, x, y, z);
+  const Nb n = make_nb(x, y, z, k);
+  const LinkMask sm = solid_mask<Q, SLIP>(n, flags);
+  const size_t N = (size_t)k.N;
+  double scale = 1.0;
+  if (x >= k.fringe_start) scale = 1.0 - (double)static_cast<const R *>(k.lam)[x];
+  const double mx = m_prev[n.cell];
+  const double d0 = (double)dev[write_slot<Q, ODD, SLIP>(n, sm, 0, N)];
+  const double m = scale * (mx + d0);
+  R dmu[Q];
+  dmu[0] = R(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const double mw = m_prev[writer_of<Q, SLIP ? 2 : 1>(n, sm, i)];
+    const double di = (double)dev[write_slot<Q, ODD, SLIP>(n, sm, i, N)];
+    dmu[i] = (R)(scale * ((mw - mx) + (di - d0)));
+  }
+  R g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD, SLIP>(n, sm, i, N));
+  // the record, from the reference cell's state (the forward step's inputs)
+  const size_t M = (size_t)nwall;
+  double rho_r, ur[3];
+  ref_velocity<Q, S, ODD, SLIP>(pop, flags, r, k, rho_r, ur);
+  const double nn[3] = {rec[WR_NX * M + w], rec[WR_NY * M + w], rec[WR_NZ * M + w]};
+  const double yr = rec[WR_YR * M + w], yb = rec[WR_YB * M + w];
+  const WallRec wr = wall_record_of(ur, nn, yr, yb, r == b, k);
+  CellSeed cs{};
+  if constexpr (SEED) cs = cell_seed<Q, R>(g, x, p0, p1, cnt, sw, k);
+  const R nv[3] = {R(nn[0]), R(nn[1]), R(nn[2])};
+  const R tv[3] = {R(wr.t[0]), R(wr.t[1]), R(wr.t[2])};
+  WallBar<R> rb;
+  auto store = [&](int i, R v) {
+    if constexpr (SEED) v += (R)cs.template kin<Q>(i);
+    dev[read_slot<Q, ODD, SLIP>(n, sm, i, N)] = v;
+  };
+  wall_collide_vjp<Q, R, RR>(g, dmu, nv, tv, R(wr.utan), R(wr.G), R(wr.tau), k, store, rb);
+  m_next[n.cell] = SEED ? m + cs.base : m;
+  const double tb[3] = {(double)rb.t[0], (double)rb.t[1], (double)rb.t[2]};
+  double rhob, jb[3];
+  wall_record_vjp(wr, ur, rho_r, nn, yr, yb, r == b, k, tb, (double)rb.utan, (double)rb.G, (double)rb.tau, rhob, jb);
+  wadj[w] = rhob;
+  wadj[M + w] = jb[0];
+  wadj[2 * M + w] = jb[1];
+  wadj[3 * M + w] = jb[2];
+}
+
+// Adds the records' density and momentum adjoints to their reference cells'
+// adjoints (population i of cell r: rho_bar + c_i . j_bar), one thread per
+// distinct reference cell, summing its records in a fixed order.
+template <int Q, typename S, bool ODD, bool SLIP>
+__global__ __launch_bounds__(256) void k_adjoint_ref(const uint8_t *__restrict__ flags,
+                                                     typename Store<S>::R *__restrict__ dev,
+                                                     const int *__restrict__ rcell, const int *__restrict__ roff,
+                                                     const int *__restrict__ rrec, int nref,
+                                                     const double *__restrict__ wadj, int nwall, KArgs k) {
+  using R = typename Store<S>::R;
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nref) return;
+  const size_t M = (size_t)nwall;
+  double a = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+  for (int j = roff[u]; j < roff[u + 1]; ++j) {
+    const int w = rrec[j];
+    a += wadj[w];
+    ax += wadj[M + w];
+    ay += wadj[2 * M + w];
+    az += wadj[3 * M + w];
+  }
+  const int r = rcell[u];
+  int x, y, z;
+  cell_xyz(r, k, x, y, z);
+  const Nb n = make_nb(x, y, z, k);
+  LinkMask sm = 0;
+  if (ODD && (flags[r] & FL_NEAR)) sm = solid_mask<Q, SLIP>(n, flags);
+  const size_t N = (size_t)k.N;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    double v = a;
+    acc(v, Lat<Q>::c(i, 0), ax);
+    acc(v, Lat<Q>::c(i, 1), ay);
+    acc(v, Lat<Q>::c(i, 2), az);
+    R *p = dev + read_slot<Q, ODD, SLIP>(n, sm, i, N);
+    *p = (R)((double)*p + v);
+  }
+}
+
 // Adjoint field = dJ/df of the current state for the terminal objective
 // J = c_s^2 (<rho>_{x=p0} - <rho>_{x=p1}) + <rho |u|^2 / 2>; the fluid-cell
 // counts come from the objective reduction already in cnt[0..2].
-template <int Q, typename S, bool ODD, bool SOLID>
+template <int Q, typename S, bool ODD, int SOLID>
 __global__ __launch_bounds__(ABLOCK) void k_seed(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                  typename Store<S>::R *__restrict__ dev, double *__restrict__ m_cur, KArgs k,
                                                  ATiles t, int p0,
@@ -773,14 +1055,14 @@ __global__ __launch_bounds__(ABLOCK) void k_seed(const S *__restrict__ pop, cons
   const Nb n = make_nb(x, y, z, k);
   const uint8_t fl = flags[n.cell];
   if (!(fl & FL_FLUID)) return;
-  unsigned sm = 0;
-  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  LinkMask sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q, SOLID == 2>(n, flags);
   const size_t N = (size_t)k.N;
   double g[Q];
   double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    g[i] = (double)Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+    g[i] = (double)Store<S>::ld(pop + read_slot<Q, ODD, SOLID == 2>(n, sm, i, N));
     drho += g[i];
     acc(jx, Lat<Q>::c(i, 0), g[i]);
     acc(jy, Lat<Q>::c(i, 1), g[i]);
@@ -798,13 +1080,13 @@ __global__ __launch_bounds__(ABLOCK) void k_seed(const S *__restrict__ pop, cons
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double cu = dot3(Lat<Q>::c(i, 0), Lat<Q>::c(i, 1), Lat<Q>::c(i, 2), ux, uy, uz);
-    dev[read_slot<Q, ODD>(n, sm, i, N)] = (R)((cu - 0.5 * uu) * inf);
+    dev[read_slot<Q, ODD, SOLID == 2>(n, sm, i, N)] = (R)((cu - 0.5 * uu) * inf);
   }
 }
 
 // Natural order [q][N] (FP64 values) <-> in-memory form of the current
 // parity (common mode + deviations; a cell's own read slots are its writes).
-template <int Q, bool ODD, bool SOLID, typename R>
+template <int Q, bool ODD, int SOLID, typename R>
 __global__ __launch_bounds__(ABLOCK) void k_to_natural(const uint8_t *__restrict__ flags,
                                                        const double *__restrict__ m_cur,
                                                        const R *__restrict__ dev, double *__restrict__ nat,
@@ -819,14 +1101,14 @@ __global__ __launch_bounds__(ABLOCK) void k_to_natural(const uint8_t *__restrict
     for (int i = 0; i < Q; ++i) nat[(size_t)i * N + n.cell] = 0.0;
     return;
   }
-  unsigned sm = 0;
-  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  LinkMask sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q, SOLID == 2>(n, flags);
   const double m = m_cur[n.cell];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) nat[(size_t)i * N + n.cell] = m + (double)dev[read_slot<Q, ODD>(n, sm, i, N)];
+  for (int i = 0; i < Q; ++i) nat[(size_t)i * N + n.cell] = m + (double)dev[read_slot<Q, ODD, SOLID == 2>(n, sm, i, N)];
 }
 
-template <int Q, bool ODD, bool SOLID, typename R>
+template <int Q, bool ODD, int SOLID, typename R>
 __global__ __launch_bounds__(ABLOCK) void k_from_natural(const uint8_t *__restrict__ flags,
                                                          const double *__restrict__ nat,
                                                          double *__restrict__ m_cur, R *__restrict__ dev,
@@ -837,12 +1119,12 @@ __global__ __launch_bounds__(ABLOCK) void k_from_natural(const uint8_t *__restri
   const uint8_t fl = flags[n.cell];
   if (!(fl & FL_FLUID)) return;
   const size_t N = (size_t)k.N;
-  unsigned sm = 0;
-  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  LinkMask sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q, SOLID == 2>(n, flags);
   const double m = nat[n.cell];
   m_cur[n.cell] = m;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) dev[read_slot<Q, ODD>(n, sm, i, N)] = (R)(nat[(size_t)i * N + n.cell] - m);
+  for (int i = 0; i < Q; ++i) dev[read_slot<Q, ODD, SOLID == 2>(n, sm, i, N)] = (R)(nat[(size_t)i * N + n.cell] - m);
 }
 
 // ---------------------------------------------------------------------------
@@ -855,8 +1137,12 @@ template <typename F>
 static int adispatch(lbm_ctx *ctx, F &&f) {
   const bool odd = (ctx->steps & 1) != 0;
   auto by_geo = [&]<int Q, typename S>() {
-    if (odd) return ctx->has_solid ? f.template operator()<Q, S, true, true>() : f.template operator()<Q, S, true, false>();
-    return ctx->has_solid ? f.template operator()<Q, S, false, true>() : f.template operator()<Q, S, false, false>();
+    if (odd) {
+      if (ctx->has_slip) return f.template operator()<Q, S, true, 2>();
+      return ctx->has_solid ? f.template operator()<Q, S, true, 1>() : f.template operator()<Q, S, true, 0>();
+    }
+    if (ctx->has_slip) return f.template operator()<Q, S, false, 2>();
+    return ctx->has_solid ? f.template operator()<Q, S, false, 1>() : f.template operator()<Q, S, false, 0>();
   };
   if (ctx->q == 19) {
     if (ctx->p.storage == LBM_F64) return by_geo.template operator()<19, double>();
@@ -873,12 +1159,14 @@ static int adispatch(lbm_ctx *ctx, F &&f) {
 struct AdjPtrs {
   double *m_cur, *m_other;
   void *dev;
+  double *wadj;  // [4][nwall] (wall model)
 };
 static AdjPtrs adj_ptrs(lbm_ctx *ctx, void *lamv) {
-  const AdjLayout L = adj_layout(ctx->N, ctx->q, ctx->p.storage == LBM_F64 ? 8 : 4);
+  const AdjLayout L = adj_layout(ctx->N, ctx->q, ctx->p.storage == LBM_F64 ? 8 : 4, ctx->nwall);
   double *m0 = (double *)lamv, *m1 = m0 + ctx->N;
   const bool odd = (ctx->steps & 1) != 0;
-  return {odd ? m1 : m0, odd ? m0 : m1, (char *)lamv + L.d_off};
+  return {odd ? m1 : m0, odd ? m0 : m1, (char *)lamv + L.d_off,
+          ctx->nwall > 0 ? (double *)((char *)lamv + L.wadj_off) : nullptr};
 }
 
 // The reverse step for one lattice and storage type.  Its kernels are many
@@ -889,7 +1177,7 @@ template <int Q, typename S>
 int adjoint_step_qs(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const int *planes) {
   const ATiles t = atiles_of(ctx->ka);
   const AdjPtrs a = adj_ptrs(ctx, lamv);
-  auto body = [&]<bool ODD, bool SOLID>() {
+  auto body = [&]<bool ODD, int SOLID>() {
     using R = typename Store<S>::R;
     R *dev = (R *)a.dev;
     double *grad = (double *)gradv;
@@ -905,8 +1193,8 @@ int adjoint_step_qs(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const 
       // open x faces make x non-periodic, so their domains always have solid links
       if constexpr (SOLID) {
         if (ctx->has_open) {
-          if (seed_w != 0.0) go(k_adjoint<Q, S, ODD, POROUS, true, RR, true, true>);
-          else go(k_adjoint<Q, S, ODD, POROUS, true, RR, false, true>);
+          if (seed_w != 0.0) go(k_adjoint<Q, S, ODD, POROUS, SOLID, RR, true, true>);
+          else go(k_adjoint<Q, S, ODD, POROUS, SOLID, RR, false, true>);
           return;
         }
       }
@@ -920,11 +1208,39 @@ int adjoint_step_qs(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const 
       if (ctx->ka.rr) by_seed.template operator()<false, true>();
       else by_seed.template operator()<false, false>();
     }
-    return check(ctx, "k_adjoint");
+    int rc = check(ctx, "k_adjoint");
+    if (rc != LBM_OK || ctx->nwall == 0) return rc;
+    if constexpr (SOLID) {
+      // wall cells, then their contributions to the reference cells
+      const int nw = ctx->nwall, wb = (nw + 255) / 256;
+      auto gow = [&](auto kern) {
+        kern<<<wb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, dev, a.m_other, a.m_cur, ctx->wcell,
+                                         ctx->wref, ctx->wrec, nw, a.wadj, ctx->ka, p0, p1, cnt, seed_w);
+      };
+      constexpr bool SLIP = SOLID == 2;
+      if (ctx->ka.rr) {
+        if (seed_w != 0.0) gow(k_adjoint_wall<Q, S, ODD, true, true, SLIP>);
+        else gow(k_adjoint_wall<Q, S, ODD, true, false, SLIP>);
+      } else {
+        if (seed_w != 0.0) gow(k_adjoint_wall<Q, S, ODD, false, true, SLIP>);
+        else gow(k_adjoint_wall<Q, S, ODD, false, false, SLIP>);
+      }
+      rc = check(ctx, "k_adjoint_wall");
+      if (rc != LBM_OK) return rc;
+      const int rb = (ctx->nref + 255) / 256;
+      k_adjoint_ref<Q, S, ODD, SLIP><<<rb, 256, 0, ctx->stream>>>(ctx->flags, dev, ctx->wref_cell, ctx->wref_off,
+                                                          ctx->wref_rec, ctx->nref, a.wadj, nw, ctx->ka);
+      return check(ctx, "k_adjoint_ref");
+    }
+    return rc;
   };
   const bool odd = (ctx->steps & 1) != 0;
-  if (odd) return ctx->has_solid ? body.template operator()<true, true>() : body.template operator()<true, false>();
-  return ctx->has_solid ? body.template operator()<false, true>() : body.template operator()<false, false>();
+  if (odd) {
+    if (ctx->has_slip) return body.template operator()<true, 2>();
+    return ctx->has_solid ? body.template operator()<true, 1>() : body.template operator()<true, 0>();
+  }
+  if (ctx->has_slip) return body.template operator()<false, 2>();
+  return ctx->has_solid ? body.template operator()<false, 1>() : body.template operator()<false, 0>();
 }
 
 #define LBM_ADJ_PAIRS(X) X(19, double) X(19, float) X(19, _Float16) X(27, double) X(27, float) X(27, _Float16)
@@ -967,7 +1283,7 @@ int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lamv, double w) {
   if (rc != LBM_OK) return rc;
   const ATiles t = atiles_of(ctx->ka);
   const AdjPtrs a = adj_ptrs(ctx, lamv);
-  return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
+  return adispatch(ctx, [&]<int Q, typename S, bool ODD, int SOLID>() {
     using R = typename Store<S>::R;
     k_seed<Q, S, ODD, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, (R *)a.dev,
                                                                    a.m_cur, ctx->ka, t, planes[0], planes[1],
@@ -979,7 +1295,7 @@ int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lamv, double w) {
 int dev_layout_to_natural(lbm_ctx *ctx, const void *lamv, void *natv) {
   const ATiles t = atiles_of(ctx->ka);
   const AdjPtrs a = adj_ptrs(ctx, const_cast<void *>(lamv));
-  return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
+  return adispatch(ctx, [&]<int Q, typename S, bool ODD, int SOLID>() {
     using R = typename Store<S>::R;
     k_to_natural<Q, ODD, SOLID, R><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, a.m_cur, (const R *)a.dev,
                                                                          (double *)natv, ctx->ka, t);
@@ -990,7 +1306,7 @@ int dev_layout_to_natural(lbm_ctx *ctx, const void *lamv, void *natv) {
 int dev_layout_from_natural(lbm_ctx *ctx, const void *natv, void *lamv) {
   const ATiles t = atiles_of(ctx->ka);
   const AdjPtrs a = adj_ptrs(ctx, lamv);
-  return adispatch(ctx, [&]<int Q, typename S, bool ODD, bool SOLID>() {
+  return adispatch(ctx, [&]<int Q, typename S, bool ODD, int SOLID>() {
     using R = typename Store<S>::R;
     k_from_natural<Q, ODD, SOLID, R><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, (const double *)natv,
                                                                            a.m_cur, (R *)a.dev, ctx->ka, t);

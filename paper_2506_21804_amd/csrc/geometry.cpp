@@ -33,6 +33,23 @@ void parallel_slabs(int nz, F body) {
 struct Box {
   int n[3];
   int per[3];
+  int slip;  // full-slip face bits
+  // whether the move (x,y,z) + d leaves the box through full-slip faces only
+  bool slip_move(int x, int y, int z, int dx, int dy, int dz) const {
+    const int q[3] = {x + dx, y + dy, z + dz};
+    bool any = false;
+    for (int a = 0; a < 3; ++a) {
+      if (per[a]) continue;
+      if (q[a] < 0) {
+        if (!((slip >> (2 * a)) & 1)) return false;
+        any = true;
+      } else if (q[a] >= n[a]) {
+        if (!((slip >> (2 * a + 1)) & 1)) return false;
+        any = true;
+      }
+    }
+    return any;
+  }
   // neighbour of (x,y,z) + d with wrap; -1 when it leaves a non-periodic axis
   long long nb(int x, int y, int z, int dx, int dy, int dz) const {
     int q[3] = {x + dx, y + dy, z + dz};
@@ -52,20 +69,28 @@ Box box_of(const lbm_params &p) {
   b.n[1] = p.ny;
   b.n[2] = p.nz;
   for (int a = 0; a < 3; ++a) b.per[a] = p.periodic[a] ? 1 : 0;
+  b.slip = p.slip;
   return b;
 }
 
 inline bool fluid_at(const uint8_t *mask, long long c) { return c >= 0 && (mask == nullptr || mask[c] != 0); }
 
 // Solid-link sum s = sum over links i with a non-fluid neighbour at +c_i of
-// (-c_i); returns whether there is any such link.
+// (-c_i), leaving out links through full-slip faces (not walls of the wall
+// model); returns whether there is any such solid link, and in *slip whether
+// there is a link through full-slip faces.
 template <int Q>
-bool solid_links(const Box &b, const uint8_t *mask, int x, int y, int z, int s[3]) {
+bool solid_links(const Box &b, const uint8_t *mask, int x, int y, int z, int s[3], bool *slip) {
   bool any = false;
+  *slip = false;
   s[0] = s[1] = s[2] = 0;
   for (int i = 1; i < Q; ++i) {
     const long long nbc = b.nb(x, y, z, Lat<Q>::c(i, 0), Lat<Q>::c(i, 1), Lat<Q>::c(i, 2));
     if (!fluid_at(mask, nbc)) {
+      if (b.slip && b.slip_move(x, y, z, Lat<Q>::c(i, 0), Lat<Q>::c(i, 1), Lat<Q>::c(i, 2))) {
+        *slip = true;
+        continue;
+      }
       any = true;
       for (int a = 0; a < 3; ++a) s[a] -= Lat<Q>::c(i, a);
     }
@@ -120,7 +145,10 @@ int build(const lbm_params &p, const uint8_t *mask, Geometry &g, std::string &ms
           if (!fluid_at(mask, c)) continue;
           uint8_t fl = FL_FLUID;
           int s[3];
-          const bool near = solid_links<Q>(b, mask, x, y, z, s);
+          bool slip_link = false;
+          const bool solid = solid_links<Q>(b, mask, x, y, z, s, &slip_link);
+          // links through full-slip faces also need the link-aware slot map
+          const bool near = solid || slip_link;
           if (near) {
             fl |= FL_NEAR;
             any_solid[z] = 1;
@@ -136,7 +164,7 @@ int build(const lbm_params &p, const uint8_t *mask, Geometry &g, std::string &ms
             fl |= x == 0 ? FL_INLET : FL_OUTLET;
             any_open[z] = 1;
           }
-          if (p.wall_model && near && !lid && !open && (s[0] || s[1] || s[2])) {
+          if (p.wall_model && solid && !lid && !open && (s[0] || s[1] || s[2])) {
             fl |= FL_WALL;
             const int k = best_direction<Q>(s);
             long long r = b.nb(x, y, z, Lat<Q>::c(k, 0), Lat<Q>::c(k, 1), Lat<Q>::c(k, 2));
@@ -192,7 +220,8 @@ long long count_wall_cells(const lbm_params &p, const uint8_t *mask) {
 
 // Distance from the centre of cell c to the nearest solid unit cube whose
 // centre lies within two cells along every axis (outside a non-periodic
-// axis counts as solid); +inf when there is none.
+// axis counts as solid, except beyond a full-slip face, where the geometry
+// continues as its mirror image); +inf when there is none.
 double voxel_distance(const lbm_params &p, const uint8_t *mask, long long c) {
   const Box b = box_of(p);
   const int x = (int)(c % p.nx);
@@ -203,7 +232,13 @@ double voxel_distance(const lbm_params &p, const uint8_t *mask, long long c) {
     for (int dy = -2; dy <= 2; ++dy)
       for (int dx = -2; dx <= 2; ++dx) {
         if (dx == 0 && dy == 0 && dz == 0) continue;
-        const long long nbc = b.nb(x, y, z, dx, dy, dz);
+        int q[3] = {x + dx, y + dy, z + dz};
+        for (int a = 0; a < 3; ++a) {
+          if (b.per[a]) continue;
+          if (q[a] < 0 && ((b.slip >> (2 * a)) & 1)) q[a] = -1 - q[a];
+          else if (q[a] >= b.n[a] && ((b.slip >> (2 * a + 1)) & 1)) q[a] = 2 * b.n[a] - 1 - q[a];
+        }
+        const long long nbc = b.nb(q[0], q[1], q[2], 0, 0, 0);
         if (fluid_at(mask, nbc)) continue;
         const double gx = std::max(std::abs(dx) - 0.5, 0.0), gy = std::max(std::abs(dy) - 0.5, 0.0),
                      gz = std::max(std::abs(dz) - 0.5, 0.0);

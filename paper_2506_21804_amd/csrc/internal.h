@@ -50,6 +50,7 @@ struct KArgs {
   double u_lid;      // lid velocity (x component)
   int rr;            // 1: recursive regularized collision (third order), 0: BGK
   double fdw;        // weight of the finite-difference strain (1 - sigma), 0 = local only
+  int slip;          // full-slip box faces (lbm_params.slip bits)
   int open_x;        // 1: inlet / outlet on the x faces
   double rho_out;    // outlet density
   const void *vel;   // [3][N] velocity field of the current step, compute type (fdw > 0)
@@ -62,14 +63,17 @@ struct KArgs {
 // M[w] + d[slot]: w is the cell that wrote the slot, M[w] its common mode
 // (FP64, one array per layout parity) and d the deviation in the compute type
 // (FP64 for FP64 storage, FP32 otherwise).  Two arrays of N doubles, then q
-// arrays of N deviations from a 256-byte boundary.
+// arrays of N deviations from a 256-byte boundary, then (wall model) four
+// doubles per wall record from a 256-byte boundary: the reverse step's
+// adjoint of each record's reference-cell density and momentum.
 struct AdjLayout {
-  size_t d_off, bytes;
+  size_t d_off, wadj_off, bytes;
 };
-inline AdjLayout adj_layout(long long N, int q, size_t dev_bytes) {
+inline AdjLayout adj_layout(long long N, int q, size_t dev_bytes, long long nwall) {
   AdjLayout L;
   L.d_off = ((size_t)2 * (size_t)N * sizeof(double) + 255) & ~(size_t)255;
-  L.bytes = L.d_off + (size_t)q * (size_t)N * dev_bytes;
+  L.wadj_off = (L.d_off + (size_t)q * (size_t)N * dev_bytes + 255) & ~(size_t)255;
+  L.bytes = nwall > 0 ? L.wadj_off + (size_t)4 * (size_t)nwall * sizeof(double) : L.d_off + (size_t)q * (size_t)N * dev_bytes;
   return L;
 }
 
@@ -99,6 +103,7 @@ struct lbm_ctx {
   lbmk::KArgs ka{};
   bool porous = false;
   bool has_solid = false;  // some cell has a solid link (bounce-back needed)
+  bool has_slip = false;   // full-slip faces (specular reflection needed)
   bool has_lid = false;
   bool has_open = false;   // some cell is an inlet or outlet cell
   // device regions carved from the caller's workspace
@@ -115,6 +120,13 @@ struct lbm_ctx {
   uint8_t *wrefwall = nullptr;   // [nwall] 1 when the reference cell is itself a wall cell
   int *wlist_refwall = nullptr;  // [nwall_refwall] indices of those records
   int nwall_refwall = 0;
+  // the records grouped by reference cell (for the reverse step): nref
+  // distinct reference cells, their records wref_rec[wref_off[u] ..
+  // wref_off[u + 1]) in increasing order
+  int nref = 0;
+  int *wref_cell = nullptr;   // [nref]
+  int *wref_off = nullptr;    // [nref + 1]
+  int *wref_rec = nullptr;    // [nwall]
   double *wrec = nullptr;     // [WR_COUNT][nwall]
   double *partial = nullptr;  // reduction partials
   int npartial = 0;           // number of partial slots (blocks) available
@@ -160,6 +172,9 @@ std::vector<Action> revolve_schedule(int T, int nsnap);
 int dev_init_equilibrium(lbm_ctx *ctx, const double *rho0, const double *u0);
 int dev_inflow(lbm_ctx *ctx, int nvort, double sigma);  // inlet velocity field from ctx->vort
 int dev_step(lbm_ctx *ctx);  // one time step at parity ctx->steps & 1
+// n launches (alternating parity) of the bulk kernel's access pattern without
+// the collision; mean time per launch from events.  Synchronises.
+int dev_stream_probe(lbm_ctx *ctx, int n, double *ms_per_launch);
 int dev_moments(lbm_ctx *ctx, void *rho, void *u);
 int dev_reduce_diag(lbm_ctx *ctx);  // writes result[0..3]
 // Looks up (once per device) the address of the static scratch array and

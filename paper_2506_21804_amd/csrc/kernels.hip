@@ -27,6 +27,7 @@
 
 #include "internal.h"
 #include "lattice.h"
+#include "wall.h"
 
 namespace lbmk {
 
@@ -59,8 +60,16 @@ static Tiles tiles_of(const KArgs &k) {
 }
 
 // Cell coordinates of this thread in the tiled grid; false when outside.
-__device__ __forceinline__ bool tile_xyz(const KArgs &k, Tiles t, unsigned block, int &x, int &y, int &z) {
-  const unsigned L = xcd_remap(block, t.nblocks);
+// rev = true walks the tiles in reverse order.  The bulk kernel reverses on
+// odd steps, so each step starts where the previous one ended: the last
+// tiles written are still partly held in the last-level (Infinity) cache
+// and in L2 when the next step reads them.  On the 384x192x192 channel this
+// raises the access pattern's rate by 3.7 % (a 764 MB state gains 8.7 %,
+// a 6 GB one nothing).
+__device__ __forceinline__ bool tile_xyz(const KArgs &k, Tiles t, unsigned block, int &x, int &y, int &z,
+                                         bool rev = false) {
+  unsigned L = xcd_remap(block, t.nblocks);
+  if (rev) L = t.nblocks - 1u - L;
   const int tx = (int)(L % (unsigned)t.gx);
   const unsigned r = L / (unsigned)t.gx;
   const int ty = (int)(r % (unsigned)t.gy);
@@ -442,10 +451,10 @@ __global__ __launch_bounds__(256) void k_inflow(R *__restrict__ field, const dou
 // Gather, collide, scatter of one cell.  With LINKS = false the cell has no
 // solid link and every slot is the plain AA one (32-bit offsets from a
 // per-direction base); with LINKS = true slots follow the bounce-back map.
-template <int Q, typename S, bool ODD, bool POROUS, bool LINKS, bool RR, bool HYB, bool OPEN>
+template <int Q, typename S, bool ODD, bool POROUS, bool LINKS, bool RR, bool HYB, bool OPEN, bool SLIP = false>
 __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename Store<S>::R *__restrict__ phi,
                                           const uint8_t *__restrict__ flags, const KArgs &k, const Nb &n,
-                                          unsigned sm, uint8_t fl, int x, int y, int z,
+                                          LinkMask sm, uint8_t fl, int x, int y, int z,
                                           int *__restrict__ errflag) {
   using R = typename Store<S>::R;
   const size_t N = (size_t)k.N;
@@ -456,7 +465,7 @@ __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename St
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       if (LINKS) {
-        g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+        g[i] = Store<S>::ld(pop + read_slot<Q, ODD, SLIP>(n, sm, i, N));
       } else {
         int dir;
         const int idx = plain_read<Q, ODD>(n, i, dir);
@@ -476,7 +485,7 @@ __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename St
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (LINKS) {
-      Store<S>::st(pop + write_slot<Q, ODD>(n, sm, i, N), g[i]);
+      Store<S>::st(pop + write_slot<Q, ODD, SLIP>(n, sm, i, N), g[i]);
     } else {
       int dir;
       const int idx = plain_write<Q, ODD>(n, i, dir);
@@ -485,175 +494,122 @@ __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename St
   }
 }
 
-template <int Q, typename S, bool ODD, bool POROUS, bool SOLID, bool RR, bool HYB, bool OPEN = false>
+template <int Q, typename S, bool ODD, bool POROUS, int SOLID, bool RR, bool HYB, bool OPEN = false>
 __global__ __launch_bounds__(BLOCK) void k_bulk(S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                 const typename Store<S>::R *__restrict__ phi, KArgs k,
                                                 Tiles t, int *__restrict__ errflag) {
   int x, y, z;
-  if (!tile_xyz(k, t, blockIdx.x, x, y, z)) return;
+  if (!tile_xyz(k, t, blockIdx.x, x, y, z, ODD)) return;
   const Nb n = make_nb(x, y, z, k);
   const uint8_t fl = flags[n.cell];
   // wall cells have a kernel of their own; OPEN: the cells of the inlet and
   // outlet planes are updated here, in the rows whose cache lines they share
   if (!(fl & FL_FLUID) || (fl & FL_WALL)) return;
-  unsigned sm = 0;
-  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  LinkMask sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q, SOLID == 2>(n, flags);
   // cells without solid links (all but a thin layer) take the plain-address path
   if (SOLID && ODD && sm != 0u)
-    bulk_cell<Q, S, ODD, POROUS, true, RR, HYB, OPEN>(pop, phi, flags, k, n, sm, fl, x, y, z, errflag);
+    bulk_cell<Q, S, ODD, POROUS, true, RR, HYB, OPEN, SOLID == 2>(pop, phi, flags, k, n, sm, fl, x, y, z, errflag);
   else
     bulk_cell<Q, S, ODD, POROUS, false, RR, HYB, OPEN>(pop, phi, flags, k, n, sm, fl, x, y, z, errflag);
 }
 
 // ---------------------------------------------------------------------------
-// Wall record (FP64).  Spalding function g(u+) = u+ + R4(kappa u+)/E with
-// R_m(a) = exp(a) - sum_{n<m} a^n/n!, and g'(u+) = 1 + kappa R3(kappa u+)/E.
-// Below a = 1/2 the remainders are summed as their power series (no
-// cancellation), by Horner over 24 terms with reciprocal factorials as
-// compile-time constants.
+// Memory-system ceiling of the bulk kernel's accesses: the same tiles, block
+// order, cell selection and slot map, no collision.  Every cell the bulk
+// kernel updates loads its q slots and stores each value back to the slot it
+// came from, so the state is unchanged.  The stores go through an empty asm
+// that hides the value from the compiler (a store of a just-loaded value to
+// its own address would otherwise be removed).
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr double inv_factorial(int n) {
-  double f = 1.0;
-  for (int i = 2; i <= n; ++i) f *= i;
-  return 1.0 / f;
-}
-template <int M>
-__device__ __forceinline__ double exp_tail(double a) {
-  double p = inv_factorial(M + 23);
-#pragma unroll
-  for (int n = M + 22; n >= M; --n) p = fma(p, a, inv_factorial(n));
-  double am = a;
-#pragma unroll
-  for (int n = 1; n < M; ++n) am *= a;
-  return p * am;
-}
-// g and g' at u+ (one exponential for both); inv_E = 1/E.
-__device__ __forceinline__ void spalding_gd(double up, double kappa, double inv_E, double &g, double &gd) {
-  const double a = kappa * up;
-  double r3, r4;
-  if (a >= 0.0 && a < 0.5) {
-    r4 = exp_tail<4>(a);
-    r3 = exp_tail<3>(a);
+template <typename S>
+struct Bits;
+template <>
+struct Bits<double> {
+  using T = uint64_t;
+};
+template <>
+struct Bits<float> {
+  using T = uint32_t;
+};
+template <>
+struct Bits<_Float16> {
+  using T = uint16_t;
+};
+template <typename U>
+__device__ __forceinline__ void opaque(U &v) {
+  if constexpr (sizeof(U) == 2) {
+    uint32_t t = v;
+    asm volatile("" : "+v"(t));
+    v = (U)t;
   } else {
-    r3 = exp(a) - 1.0 - a - 0.5 * a * a;
-    r4 = r3 - a * a * a * (1.0 / 6.0);
+    asm volatile("" : "+v"(v));
   }
-  g = up + r4 * inv_E;
-  gd = 1.0 + kappa * r3 * inv_E;
+}
+template <int Q, typename S, bool ODD, int SOLID>
+__global__ __launch_bounds__(BLOCK) void k_stream_probe(S *__restrict__ pop_, const uint8_t *__restrict__ flags,
+                                                        KArgs k, Tiles t) {
+  using U = typename Bits<S>::T;
+  U *pop = reinterpret_cast<U *>(pop_);
+  int x, y, z;
+  if (!tile_xyz(k, t, blockIdx.x, x, y, z, ODD)) return;
+  const Nb n = make_nb(x, y, z, k);
+  const uint8_t fl = flags[n.cell];
+  if (!(fl & FL_FLUID) || (fl & FL_WALL)) return;
+  LinkMask sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q, SOLID == 2>(n, flags);
+  const size_t N = (size_t)k.N;
+  U v[Q];
+  if (SOLID && ODD && sm != 0u) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = pop[read_slot<Q, ODD, SOLID == 2>(n, sm, i, N)];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) opaque(v[i]);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) pop[read_slot<Q, ODD, SOLID == 2>(n, sm, i, N)] = v[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      int dir;
+      const int idx = plain_read<Q, ODD>(n, i, dir);
+      v[i] = *slot_at(pop, dir, N, idx);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) opaque(v[i]);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      int dir;
+      const int idx = plain_read<Q, ODD>(n, i, dir);
+      *slot_at(pop, dir, N, idx) = v[i];
+    }
+  }
 }
 
+// ---------------------------------------------------------------------------
 // Wall record of wall cell w (reference cell r, wall cell b): reads the
-// reference cell's current populations and writes t, u_tau u+_b, G, tau_eff.
-template <int Q, typename S, bool ODD>
+// reference cell's current populations and writes t, u_tau u+_b, G, tau_eff
+// (the computation itself is wall_record_of in wall.h).
+// ---------------------------------------------------------------------------
+template <int Q, typename S, bool ODD, bool SLIP>
 __device__ __forceinline__ void wall_record(const S *__restrict__ pop, const uint8_t *__restrict__ flags, int w, int b,
                                             int r, double *__restrict__ rec, int nwall, const KArgs &k,
                                             int *__restrict__ errflag) {
-  int x, y, z;
-  cell_xyz(r, k, x, y, z);
-  const Nb n = make_nb(x, y, z, k);
-  unsigned sm = 0;
-  if (ODD && (flags[r] & FL_NEAR)) sm = solid_mask<Q>(n, flags);
-  const size_t N = (size_t)k.N;
-  double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const double gi = (double)Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
-    drho += gi;
-    acc(jx, Lat<Q>::c(i, 0), gi);
-    acc(jy, Lat<Q>::c(i, 1), gi);
-    acc(jz, Lat<Q>::c(i, 2), gi);
-  }
-  const double rho = 1.0 + drho;
-  const double ux = (jx + 0.5 * k.F[0]) / rho, uy = (jy + 0.5 * k.F[1]) / rho, uz = (jz + 0.5 * k.F[2]) / rho;
+  double rho, u[3];
+  ref_velocity<Q, S, ODD, SLIP>(pop, flags, r, k, rho, u);
   const size_t M = (size_t)nwall;
-  const double nx = rec[WR_NX * M + w], ny = rec[WR_NY * M + w], nz = rec[WR_NZ * M + w];
-  const double un = ux * nx + uy * ny + uz * nz;
-  const double tx = ux - un * nx, ty = uy - un * ny, tz = uz - un * nz;
-  const double U = sqrt(tx * tx + ty * ty + tz * tz);
-  const double nu = k.nu, kap = k.kappa, E = k.E;
-  double utau = 0.0, utan = 0.0, G = 0.0, tau = 3.0 * nu + 0.5;
-  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-  bool fail = false;
-  if (U > 1e-300) {
-    const double yr = rec[WR_YR * M + w], yb = rec[WR_YB * M + w];
-    // F(u) = g(U/u) - yr u / nu is convex and decreasing in u, and the
-    // laminar value ulam = sqrt(nu U / yr) is a lower bound of its root.  From
-    // any start, the first Newton step lands at or below the root; clamping
-    // every iterate to ulam keeps it in range, and from there the iterates
-    // climb monotonically.  The start is the log-law friction velocity (two
-    // fixed-point steps of u = kappa U / ln(E yr u / nu) from ulam), within a
-    // few per cent of the root: at y+ of 100-250 Newton then needs about 5
-    // iterations instead of 17-29 from ulam.  The root is the same.
-    const double ulam = sqrt(nu * U / yr);
-    double ut = ulam;
-    for (int j = 0; j < 2; ++j) {
-      const double L = log(E * yr * ut / nu);
-      if (L > 1.0) ut = fmax(ulam, kap * U / L);
-    }
-    bool conv = false;
-    const double inv_E = 1.0 / E, a_r = yr / nu;  // F(u) = g(U/u) - a_r u
-    if (kap * U / ulam <= 700.0) {
-      for (int it = 0; it < 100; ++it) {
-        const double iu = 1.0 / ut;
-        const double xx = U * iu;
-        double gv, gdv;
-        spalding_gd(xx, kap, inv_E, gv, gdv);
-        const double Fv = gv - a_r * ut;
-        const double dF = -gdv * xx * iu - a_r;
-        const double st = -Fv / dF;
-        ut = fmax(ut + st, ulam);
-        if (fabs(st) <= 1e-15 * ut) {
-          conv = true;
-          break;
-        }
-      }
-    }
-    double up = U / ut;
-    if (conv && r != b) {
-      // u+ at the wall cell: g(u+) = y+_b by Newton from an upper bound of
-      // the root (g convex increasing: the iterates decrease monotonically).
-      const double ypb = yb * ut / nu;
-      const double K = kap * ypb;
-      double s = fmin(ypb, log(E * ypb + 1.0 + K + 0.5 * K * K + K * K * K / 6.0) / kap);
-      if (yr >= yb) s = fmin(s, up);
-      conv = false;
-      if (kap * s <= 700.0) {
-        for (int it = 0; it < 100; ++it) {
-          double gv, gdv;
-          spalding_gd(s, kap, inv_E, gv, gdv);
-          const double st = -(gv - ypb) / gdv;
-          s += st;
-          if (fabs(st) <= 1e-15 * fabs(s)) {
-            conv = true;
-            break;
-          }
-        }
-      }
-      up = s;
-    }
-    if (!conv) {
-      fail = true;
-    } else {
-      utau = ut;
-      utan = ut * up;
-      t0 = tx / U;
-      t1 = ty / U;
-      t2 = tz / U;
-      G = 2.0 * ut * ut / (nu + sqrt(nu * nu + 4.0 * k.cs2 * ut * ut));
-      tau = 3.0 * (nu + k.cs2 * G) + 0.5;
-    }
-  }
-  if (fail) atomicOr(errflag, 2);
-  rec[WR_TX * M + w] = t0;
-  rec[WR_TY * M + w] = t1;
-  rec[WR_TZ * M + w] = t2;
-  rec[WR_UTAN * M + w] = utan;
-  rec[WR_G * M + w] = G;
-  rec[WR_TAU * M + w] = tau;
-  rec[WR_UTAU * M + w] = utau;
+  const double n[3] = {rec[WR_NX * M + w], rec[WR_NY * M + w], rec[WR_NZ * M + w]};
+  const WallRec wr = wall_record_of(u, n, rec[WR_YR * M + w], rec[WR_YB * M + w], r == b, k);
+  if (wr.fail) atomicOr(errflag, 2);
+  rec[WR_TX * M + w] = wr.t[0];
+  rec[WR_TY * M + w] = wr.t[1];
+  rec[WR_TZ * M + w] = wr.t[2];
+  rec[WR_UTAN * M + w] = wr.utan;
+  rec[WR_G * M + w] = wr.G;
+  rec[WR_TAU * M + w] = wr.tau;
+  rec[WR_UTAU * M + w] = wr.utau;
 }
 
-template <int Q, typename S, bool ODD>
+template <int Q, typename S, bool ODD, bool SLIP>
 __global__ __launch_bounds__(256) void k_wall_prepass(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                       const int *__restrict__ wcell, const int *__restrict__ wref,
                                                       const int *__restrict__ list, int nlist,
@@ -662,13 +618,13 @@ __global__ __launch_bounds__(256) void k_wall_prepass(const S *__restrict__ pop,
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nlist) return;
   const int w = list[j];
-  wall_record<Q, S, ODD>(pop, flags, w, wcell[w], wref[w], rec, nwall, k, errflag);
+  wall_record<Q, S, ODD, SLIP>(pop, flags, w, wcell[w], wref[w], rec, nwall, k, errflag);
 }
 
 // ---------------------------------------------------------------------------
 // K3: wall reconstruction (sigma = 0, solid velocity = modeled velocity).
 // ---------------------------------------------------------------------------
-template <int Q, typename S, bool ODD>
+template <int Q, typename S, bool ODD, bool SLIP>
 __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                               const int *__restrict__ wcell, const int *__restrict__ wref,
                                               const uint8_t *__restrict__ refwall, double *__restrict__ rec,
@@ -680,13 +636,13 @@ __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t
   int x, y, z;
   cell_xyz(b, k, x, y, z);
   const Nb n = make_nb(x, y, z, k);
-  const unsigned sm = ODD ? solid_mask<Q>(n, flags) : 0u;
+  const LinkMask sm = ODD ? solid_mask<Q, SLIP>(n, flags) : 0u;
   const size_t N = (size_t)k.N;
   R g[Q];
   R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, N));
+    g[i] = Store<S>::ld(pop + read_slot<Q, ODD, SLIP>(n, sm, i, N));
     drho += g[i];
     acc(jx, Lat<Q>::c(i, 0), g[i]);
     acc(jy, Lat<Q>::c(i, 1), g[i]);
@@ -696,7 +652,7 @@ __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t
   // here (no other thread of this launch writes that reference); the others
   // were computed by k_wall_prepass before this launch.  It comes after the
   // loads above, so that their latency overlaps the Newton solves.
-  if (!refwall[w]) wall_record<Q, S, ODD>(pop, flags, w, b, wref[w], rec, nwall, k, errflag);
+  if (!refwall[w]) wall_record<Q, S, ODD, SLIP>(pop, flags, w, b, wref[w], rec, nwall, k, errflag);
   const R rho = R(1) + drho;
   if (!finite_pos(rho)) atomicOr(errflag, 1);
   const R Fx = R(k.F[0]), Fy = R(k.F[1]), Fz = R(k.F[2]);
@@ -771,7 +727,7 @@ __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t
   }
   fringe_blend<Q, R>(g, x, z, k);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) Store<S>::st(pop + write_slot<Q, ODD>(n, sm, i, N), g[i]);
+  for (int i = 0; i < Q; ++i) Store<S>::st(pop + write_slot<Q, ODD, SLIP>(n, sm, i, N), g[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -809,21 +765,21 @@ __global__ __launch_bounds__(BLOCK) void k_init_eq(S *__restrict__ pop, const ui
   }
 }
 
-template <int Q, typename S, bool ODD, bool SOLID>
+template <int Q, typename S, bool ODD, int SOLID>
 __device__ __forceinline__ bool gather_state(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                              const KArgs &k, int x, int y, int z, Nb &n,
                                              typename Store<S>::R g[Q]) {
   n = make_nb(x, y, z, k);
   const uint8_t fl = flags[n.cell];
   if (!(fl & FL_FLUID)) return false;
-  unsigned sm = 0;
-  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  LinkMask sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q, SOLID == 2>(n, flags);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD>(n, sm, i, (size_t)k.N));
+  for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD, SOLID == 2>(n, sm, i, (size_t)k.N));
   return true;
 }
 
-template <int Q, typename S, bool ODD, bool SOLID>
+template <int Q, typename S, bool ODD, int SOLID>
 __global__ __launch_bounds__(BLOCK) void k_moments(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                    typename Store<S>::R *__restrict__ rho_out,
                                                    typename Store<S>::R *__restrict__ u_out, KArgs k, Tiles t) {
@@ -856,7 +812,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const S *__restrict__ pop, co
   }
 }
 
-template <int Q, typename S, bool ODD, bool SOLID>
+template <int Q, typename S, bool ODD, int SOLID>
 __global__ __launch_bounds__(BLOCK) void k_export(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                   typename Store<S>::R *__restrict__ f, KArgs k, Tiles t) {
   using R = typename Store<S>::R;
@@ -870,7 +826,7 @@ __global__ __launch_bounds__(BLOCK) void k_export(const S *__restrict__ pop, con
   for (int i = 0; i < Q; ++i) f[(size_t)i * N + n.cell] = fluid ? R(Lat<Q>::w(i)) + g[i] : R(0);
 }
 
-template <int Q, typename S, bool ODD, bool SOLID>
+template <int Q, typename S, bool ODD, int SOLID>
 __global__ __launch_bounds__(BLOCK) void k_import(S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                   const typename Store<S>::R *__restrict__ f, KArgs k, Tiles t) {
   using R = typename Store<S>::R;
@@ -879,12 +835,12 @@ __global__ __launch_bounds__(BLOCK) void k_import(S *__restrict__ pop, const uin
   const Nb n = make_nb(x, y, z, k);
   const uint8_t fl = flags[n.cell];
   if (!(fl & FL_FLUID)) return;
-  unsigned sm = 0;
-  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q>(n, flags);
+  LinkMask sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q, SOLID == 2>(n, flags);
   const size_t N = (size_t)k.N;
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    Store<S>::st(pop + read_slot<Q, ODD>(n, sm, i, N), f[(size_t)i * N + n.cell] - R(Lat<Q>::w(i)));
+    Store<S>::st(pop + read_slot<Q, ODD, SOLID == 2>(n, sm, i, N), f[(size_t)i * N + n.cell] - R(Lat<Q>::w(i)));
 }
 
 // ---------------------------------------------------------------------------
@@ -925,7 +881,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double *__restr
 // mode 0: {sum drho, sum jx, sum jy, sum jz, fluid cells} over fluid cells.
 // mode 1: {sum rho at x = p0, sum rho at x = p1, sum rho|u|^2/2, cells at
 //          x = p0, cells at x = p1, fluid cells}.
-template <int Q, typename S, bool ODD, bool SOLID>
+template <int Q, typename S, bool ODD, int SOLID>
 __global__ __launch_bounds__(BLOCK) void k_reduce(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                   KArgs k, Tiles t, int mode, int p0, int p1,
                                                   double *__restrict__ partial) {
@@ -1063,12 +1019,12 @@ static void launch_bulk(lbm_ctx *ctx, Tiles t) {
   auto go = [&](auto kern) {
     kern<<<t.nblocks, BLOCK, lds_cap, ctx->stream>>>(pop, ctx->flags, phi, ctx->ka, t, ctx->errflag);
   };
-  auto by_model = [&]<bool POROUS, bool SOLID>() {
+  auto by_model = [&]<bool POROUS, int SOLID>() {
     // open x faces make x non-periodic, so their domains always have solid links
     if constexpr (SOLID) {
       if (ctx->has_open) {
-        if (ctx->ka.rr) go(k_bulk<Q, S, ODD, POROUS, true, true, false, true>);
-        else go(k_bulk<Q, S, ODD, POROUS, true, false, false, true>);
+        if (ctx->ka.rr) go(k_bulk<Q, S, ODD, POROUS, SOLID, true, false, true>);
+        else go(k_bulk<Q, S, ODD, POROUS, SOLID, false, false, true>);
         return;
       }
     }
@@ -1077,12 +1033,69 @@ static void launch_bulk(lbm_ctx *ctx, Tiles t) {
     else go(k_bulk<Q, S, ODD, POROUS, SOLID, false, false>);
   };
   if (ctx->porous) {
-    if (ctx->has_solid) by_model.template operator()<true, true>();
-    else by_model.template operator()<true, false>();
+    if (ctx->has_slip) by_model.template operator()<true, 2>();
+    else if (ctx->has_solid) by_model.template operator()<true, 1>();
+    else by_model.template operator()<true, 0>();
   } else {
-    if (ctx->has_solid) by_model.template operator()<false, true>();
-    else by_model.template operator()<false, false>();
+    if (ctx->has_slip) by_model.template operator()<false, 2>();
+    else if (ctx->has_solid) by_model.template operator()<false, 1>();
+    else by_model.template operator()<false, 0>();
   }
+}
+
+// Runs g.template operator()<ODD, SOLID>() for the current parity and
+// geometry: SOLID 0 without links to leave the plain map, 1 with bounce-back
+// links, 2 with full-slip faces as well.
+template <typename G>
+static int by_parity(lbm_ctx *ctx, G &&g) {
+  const bool odd = (ctx->steps & 1) != 0;
+  if (odd) {
+    if (ctx->has_slip) return g.template operator()<true, 2>();
+    return ctx->has_solid ? g.template operator()<true, 1>() : g.template operator()<true, 0>();
+  }
+  if (ctx->has_slip) return g.template operator()<false, 2>();
+  return ctx->has_solid ? g.template operator()<false, 1>() : g.template operator()<false, 0>();
+}
+
+int dev_stream_probe(lbm_ctx *ctx, int n, double *ms_per_launch) {
+  const Tiles t = tiles_of(ctx->ka);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(ctx, e, "hipEventCreate");
+  }
+  int rc = dispatch(ctx, [&]<int Q, typename S>() {
+    constexpr size_t lds_cap = sizeof(S) == 4 ? 32768 : 0;  // the bulk kernel's residency cap
+    auto launch = [&](bool odd) {
+      S *pop = (S *)ctx->pop;
+      auto go = [&](auto kern) { kern<<<t.nblocks, BLOCK, lds_cap, ctx->stream>>>(pop, ctx->flags, ctx->ka, t); };
+      if (odd) {
+        if (ctx->has_slip) go(k_stream_probe<Q, S, true, 2>);
+        else if (ctx->has_solid) go(k_stream_probe<Q, S, true, 1>);
+        else go(k_stream_probe<Q, S, true, 0>);
+      } else {
+        if (ctx->has_slip) go(k_stream_probe<Q, S, false, 2>);
+        else if (ctx->has_solid) go(k_stream_probe<Q, S, false, 1>);
+        else go(k_stream_probe<Q, S, false, 0>);
+      }
+    };
+    launch(false);  // warm-up pair
+    launch(true);
+    hipError_t er = hipEventRecord(e0, ctx->stream);
+    for (int i = 0; i < n && er == hipSuccess; ++i) launch((i & 1) != 0);
+    if (er == hipSuccess) er = hipEventRecord(e1, ctx->stream);
+    if (er == hipSuccess) er = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (er == hipSuccess) er = hipEventElapsedTime(&ms, e0, e1);
+    if (er != hipSuccess) return hip_fail(ctx, er, "stream probe timing");
+    *ms_per_launch = (double)ms / n;
+    return check_launch(ctx, "k_stream_probe");
+  });
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 int dev_step(lbm_ctx *ctx) {
@@ -1096,41 +1109,33 @@ int dev_step(lbm_ctx *ctx) {
     if (ctx->ka.fdw > 0.0) {
       using R = typename Store<S>::R;
       R *vel = (R *)ctx->vel;
-      auto go = [&]<bool ODD, bool SOLID>() {
+      by_parity(ctx, [&]<bool ODD, int SOLID>() {
         k_moments<Q, S, ODD, SOLID><<<t.nblocks, BLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, nullptr,
                                                                         vel, ctx->ka, t);
-      };
-      if (odd) {
-        if (ctx->has_solid) go.template operator()<true, true>();
-        else go.template operator()<true, false>();
-      } else {
-        if (ctx->has_solid) go.template operator()<false, true>();
-        else go.template operator()<false, false>();
-      }
+        return LBM_OK;
+      });
     }
     // wall records whose reference cell is itself a wall cell, before any wall cell is written
     if (nb > 0) {
       prof_begin(ctx, 0);
       const int lb = (nb + 255) / 256;
-      if (odd)
-        k_wall_prepass<Q, S, true><<<lb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wref,
-                                                                ctx->wlist_refwall, nb, ctx->wrec, nw, ctx->ka,
-                                                                ctx->errflag);
-      else
-        k_wall_prepass<Q, S, false><<<lb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->wcell,
-                                                                 ctx->wref, ctx->wlist_refwall, nb, ctx->wrec, nw,
-                                                                 ctx->ka, ctx->errflag);
+      auto gp = [&](auto kern) {
+        kern<<<lb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wref,
+                                          ctx->wlist_refwall, nb, ctx->wrec, nw, ctx->ka, ctx->errflag);
+      };
+      if (odd) ctx->has_slip ? gp(k_wall_prepass<Q, S, true, true>) : gp(k_wall_prepass<Q, S, true, false>);
+      else ctx->has_slip ? gp(k_wall_prepass<Q, S, false, true>) : gp(k_wall_prepass<Q, S, false, false>);
       prof_end(ctx, 0);
     }
     // wall cells (their reference cells are read before the bulk kernel writes them)
     if (nw > 0) {
       prof_begin(ctx, 2);
-      if (odd)
-        k_wall<Q, S, true><<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wref,
-                                                        ctx->wrefwall, ctx->wrec, nw, ctx->ka, ctx->errflag);
-      else
-        k_wall<Q, S, false><<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wref,
-                                                         ctx->wrefwall, ctx->wrec, nw, ctx->ka, ctx->errflag);
+      auto gw = [&](auto kern) {
+        kern<<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wref, ctx->wrefwall, ctx->wrec,
+                                          nw, ctx->ka, ctx->errflag);
+      };
+      if (odd) ctx->has_slip ? gw(k_wall<Q, S, true, true>) : gw(k_wall<Q, S, true, false>);
+      else ctx->has_slip ? gw(k_wall<Q, S, false, true>) : gw(k_wall<Q, S, false, false>);
       prof_end(ctx, 2);
     }
     prof_begin(ctx, 1);
@@ -1141,19 +1146,12 @@ int dev_step(lbm_ctx *ctx) {
   });
 }
 
-// Runs g.template operator()<ODD, SOLID>() for the current parity and geometry.
-template <typename G>
-static int by_parity(lbm_ctx *ctx, G &&g) {
-  const bool odd = (ctx->steps & 1) != 0;
-  if (odd) return ctx->has_solid ? g.template operator()<true, true>() : g.template operator()<true, false>();
-  return ctx->has_solid ? g.template operator()<false, true>() : g.template operator()<false, false>();
-}
 
 int dev_moments(lbm_ctx *ctx, void *rho, void *u) {
   const Tiles t = tiles_of(ctx->ka);
   return dispatch(ctx, [&]<int Q, typename S>() {
     using R = typename Store<S>::R;
-    return by_parity(ctx, [&]<bool ODD, bool SOLID>() {
+    return by_parity(ctx, [&]<bool ODD, int SOLID>() {
       k_moments<Q, S, ODD, SOLID><<<t.nblocks, BLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, (R *)rho,
                                                                         (R *)u, ctx->ka, t);
       return check_launch(ctx, "k_moments");
@@ -1165,7 +1163,7 @@ int dev_export(lbm_ctx *ctx, void *f) {
   const Tiles t = tiles_of(ctx->ka);
   return dispatch(ctx, [&]<int Q, typename S>() {
     using R = typename Store<S>::R;
-    return by_parity(ctx, [&]<bool ODD, bool SOLID>() {
+    return by_parity(ctx, [&]<bool ODD, int SOLID>() {
       k_export<Q, S, ODD, SOLID><<<t.nblocks, BLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, (R *)f,
                                                                        ctx->ka, t);
       return check_launch(ctx, "k_export");
@@ -1177,7 +1175,7 @@ int dev_import(lbm_ctx *ctx, const void *f) {
   const Tiles t = tiles_of(ctx->ka);
   return dispatch(ctx, [&]<int Q, typename S>() {
     using R = typename Store<S>::R;
-    return by_parity(ctx, [&]<bool ODD, bool SOLID>() {
+    return by_parity(ctx, [&]<bool ODD, int SOLID>() {
       k_import<Q, S, ODD, SOLID><<<t.nblocks, BLOCK, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, (const R *)f,
                                                                        ctx->ka, t);
       return check_launch(ctx, "k_import");
@@ -1190,7 +1188,7 @@ static int reduce(lbm_ctx *ctx, int mode, int p0, int p1, int offset, double *pa
   const Tiles t = tiles_of(ctx->ka);
   const int grid = (int)std::min<unsigned>(t.nblocks, (unsigned)std::min(RED_BLOCKS, npartial));
   return dispatch(ctx, [&]<int Q, typename S>() {
-    int rc = by_parity(ctx, [&]<bool ODD, bool SOLID>() {
+    int rc = by_parity(ctx, [&]<bool ODD, int SOLID>() {
       k_reduce<Q, S, ODD, SOLID><<<grid, BLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->ka, t, mode,
                                                                   p0, p1, partial);
       return check_launch(ctx, "k_reduce");

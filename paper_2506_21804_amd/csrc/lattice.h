@@ -139,14 +139,17 @@ struct Store<_Float16> {
 
 // Neighbour geometry of one cell: offsets (in cells) to the -1 / +1 neighbour
 // along each axis with periodic wrap, and which moves leave the domain
-// through a non-periodic face (those links count as solid).
+// through a non-periodic face (those links count as solid).  These and the
+// slot functions below also compile for the host, where lbm_slot_map
+// evaluates the same map for inspection.
 struct Nb {
   int cell;
   int d[3][2];
-  unsigned out;  // bit 2a: -1 along axis a leaves the domain; bit 2a+1: +1 does
+  unsigned out;   // bit 2a: -1 along axis a leaves the domain; bit 2a+1: +1 does
+  unsigned slip;  // the bits of out whose face is a full-slip face
 };
 
-__device__ __forceinline__ Nb make_nb(int x, int y, int z, const KArgs &k) {
+__host__ __device__ __forceinline__ Nb make_nb(int x, int y, int z, const KArgs &k) {
   Nb n;
   const int sy = k.nx, sz = k.nx * k.ny;
   n.cell = x + sy * y + sz * z;
@@ -161,10 +164,11 @@ __device__ __forceinline__ Nb make_nb(int x, int y, int z, const KArgs &k) {
   if (!k.per[1]) o |= (y == 0 ? 4u : 0u) | (y == k.ny - 1 ? 8u : 0u);
   if (!k.per[2]) o |= (z == 0 ? 16u : 0u) | (z == k.nz - 1 ? 32u : 0u);
   n.out = o;
+  n.slip = o & (unsigned)k.slip;
   return n;
 }
 
-__device__ __forceinline__ void cell_xyz(int c, const KArgs &k, int &x, int &y, int &z) {
+__host__ __device__ __forceinline__ void cell_xyz(int c, const KArgs &k, int &x, int &y, int &z) {
   x = c % k.nx;
   int t = c / k.nx;
   y = t % k.ny;
@@ -173,7 +177,7 @@ __device__ __forceinline__ void cell_xyz(int c, const KArgs &k, int &x, int &y, 
 
 // Offset of the cell at + sgn * c_i.
 template <int Q>
-__device__ __forceinline__ int nb_off(const Nb &n, int i, int sgn) {
+__host__ __device__ __forceinline__ int nb_off(const Nb &n, int i, int sgn) {
   int o = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -184,7 +188,7 @@ __device__ __forceinline__ int nb_off(const Nb &n, int i, int sgn) {
   return o;
 }
 template <int Q>
-__device__ __forceinline__ bool nb_out(const Nb &n, int i, int sgn) {
+__host__ __device__ __forceinline__ bool nb_out(const Nb &n, int i, int sgn) {
   bool r = false;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -195,16 +199,97 @@ __device__ __forceinline__ bool nb_out(const Nb &n, int i, int sgn) {
   return r;
 }
 
-// Bit i set when the upstream cell (cell - c_i) is solid or outside.
+// Face bits (2a: low face of axis a, 2a+1: high face) crossed by the move
+// + sgn * c_i, and the axes they belong to.
 template <int Q>
-__device__ __forceinline__ unsigned solid_mask(const Nb &n, const uint8_t *__restrict__ flags) {
-  unsigned m = 0;
+__host__ __device__ __forceinline__ unsigned cross_faces(const Nb &n, int i, int sgn) {
+  unsigned r = 0;
 #pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const bool s = nb_out<Q>(n, i, -1) || !(flags[n.cell + nb_off<Q>(n, i, -1)] & FL_FLUID);
-    m |= (s ? 1u : 0u) << i;
+  for (int a = 0; a < 3; ++a) {
+    const int c = sgn * Lat<Q>::c(i, a);
+    if (c < 0) r |= n.out & (1u << (2 * a));
+    else if (c > 0) r |= n.out & (1u << (2 * a + 1));
   }
-  return m;
+  return r;
+}
+__host__ __device__ __forceinline__ unsigned face_axes(unsigned faces) {
+  return ((faces | (faces >> 1)) & 1u) | (((faces >> 2) | (faces >> 3)) & 1u) << 1 |
+         (((faces >> 4) | (faces >> 5)) & 1u) << 2;
+}
+// Specular reflection at full-slip faces: the offset of the move + sgn * c_i
+// with its components along `axes` set to zero, and the direction of c_i
+// with those components negated.
+template <int Q>
+__host__ __device__ __forceinline__ int reflect_off(const Nb &n, int i, int sgn, unsigned axes) {
+  int o = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if ((axes >> a) & 1u) continue;
+    const int c = sgn * Lat<Q>::c(i, a);
+    if (c < 0) o += n.d[a][0];
+    else if (c > 0) o += n.d[a][1];
+  }
+  return o;
+}
+template <int Q>
+__host__ __device__ constexpr int dir_of(int cx, int cy, int cz) {
+  for (int j = 0; j < Q; ++j)
+    if (Lat<Q>::c(j, 0) == cx && Lat<Q>::c(j, 1) == cy && Lat<Q>::c(j, 2) == cz) return j;
+  return -1;
+}
+template <int Q>
+__host__ __device__ constexpr int reflect_dir_const(int i, unsigned axes) {
+  return dir_of<Q>((axes & 1u) ? -Lat<Q>::c(i, 0) : Lat<Q>::c(i, 0), (axes & 2u) ? -Lat<Q>::c(i, 1) : Lat<Q>::c(i, 1),
+                   (axes & 4u) ? -Lat<Q>::c(i, 2) : Lat<Q>::c(i, 2));
+}
+// i is a compile-time constant after unrolling; axes (1..7) is not.
+template <int Q>
+__host__ __device__ __forceinline__ int reflect_dir(int i, unsigned axes) {
+  int j = i;
+#pragma unroll
+  for (unsigned m = 1; m < 8; ++m)
+    if (axes == m) j = reflect_dir_const<Q>(i, m);
+  return j;
+}
+
+// Link mask of a cell.  Bit i (0..31): the upstream cell (cell - c_i) is
+// solid or outside, so f_i arrives by halfway bounce-back.  Bit 32 + i: the
+// upstream move leaves the box through full-slip faces only and the
+// specularly reflected source (that move with the crossed components set to
+// zero) is fluid, so f_i arrives by specular reflection.
+// SLIP = false (no full-slip faces: every link leaving the box is solid)
+// compiles without any of the reflection code; kernels take SLIP = true only
+// for domains with full-slip faces.
+using LinkMask = uint64_t;
+template <int Q, bool SLIP = false>
+__host__ __device__ __forceinline__ LinkMask solid_mask(const Nb &n, const uint8_t *__restrict__ flags) {
+  if constexpr (!SLIP) {
+    unsigned m = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const bool s = nb_out<Q>(n, i, -1) || !(flags[n.cell + nb_off<Q>(n, i, -1)] & FL_FLUID);
+      m |= (s ? 1u : 0u) << i;
+    }
+    return (LinkMask)m;
+  } else {
+    LinkMask m = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const unsigned cf = cross_faces<Q>(n, i, -1);
+      bool s, sl = false;
+      if (cf == 0u) {
+        s = !(flags[n.cell + nb_off<Q>(n, i, -1)] & FL_FLUID);
+      } else if ((cf & ~n.slip) == 0u) {
+        sl = (flags[n.cell + reflect_off<Q>(n, i, -1, face_axes(cf))] & FL_FLUID) != 0;
+        s = !sl;
+      } else {
+        s = true;
+      }
+      m |= (LinkMask)(s ? 1u : 0u) << i;
+      m |= (LinkMask)(sl ? 1u : 0u) << (32 + i);
+    }
+    return m;
+  }
 }
 
 // AA pattern (in-place, one buffer A[i][cell]).
@@ -213,18 +298,33 @@ __device__ __forceinline__ unsigned solid_mask(const Nb &n, const uint8_t *__res
 // Odd parity: the state f_i(x) is A[opp i][x - c_i] if that cell is fluid,
 //   else A[i][x] (halfway bounce-back); f*_i(x) goes to A[i][x + c_i] if that
 //   cell is fluid, else to A[opp i][x].
+// Across full-slip faces (specular reflection, c_j = c_i with the crossed
+//   components negated): at odd parity f_i(x) is A[opp j][x - c_i with the
+//   crossed components zeroed], where the even step left f*_j of that cell,
+//   and f*_i(x) goes to A[j][x + c_i with the crossed components zeroed],
+//   where the next even step reads f_j of that cell.
 // Each cell reads and writes the same set of slots, and the sets of two cells
-// are disjoint, so every cell can be updated concurrently in place.
-template <int Q, bool ODD>
-__device__ __forceinline__ size_t read_slot(const Nb &n, unsigned sm, int i, size_t N) {
+// are disjoint, so every cell can be updated concurrently in place (the
+// reflected slots of a face row form the same kind of bijection as the
+// bounce-back slots they replace).
+template <int Q, bool ODD, bool SLIP = false>
+__host__ __device__ __forceinline__ size_t read_slot(const Nb &n, LinkMask sm, int i, size_t N) {
   if (!ODD) return (size_t)i * N + (size_t)n.cell;
   if ((sm >> i) & 1u) return (size_t)i * N + (size_t)n.cell;
+  if (SLIP && ((sm >> (32 + i)) & 1u)) {
+    const unsigned ax = face_axes(cross_faces<Q>(n, i, -1));
+    return (size_t)Lat<Q>::opp(reflect_dir<Q>(i, ax)) * N + (size_t)(n.cell + reflect_off<Q>(n, i, -1, ax));
+  }
   return (size_t)Lat<Q>::opp(i) * N + (size_t)(n.cell + nb_off<Q>(n, i, -1));
 }
-template <int Q, bool ODD>
-__device__ __forceinline__ size_t write_slot(const Nb &n, unsigned sm, int i, size_t N) {
+template <int Q, bool ODD, bool SLIP = false>
+__host__ __device__ __forceinline__ size_t write_slot(const Nb &n, LinkMask sm, int i, size_t N) {
   if (!ODD) return (size_t)Lat<Q>::opp(i) * N + (size_t)n.cell;
   if ((sm >> Lat<Q>::opp(i)) & 1u) return (size_t)Lat<Q>::opp(i) * N + (size_t)n.cell;
+  if (SLIP && ((sm >> (32 + Lat<Q>::opp(i))) & 1u)) {
+    const unsigned ax = face_axes(cross_faces<Q>(n, i, +1));
+    return (size_t)reflect_dir<Q>(i, ax) * N + (size_t)(n.cell + reflect_off<Q>(n, i, +1, ax));
+  }
   return (size_t)i * N + (size_t)(n.cell + nb_off<Q>(n, i, +1));
 }
 
@@ -233,12 +333,12 @@ __device__ __forceinline__ size_t write_slot(const Nb &n, unsigned sm, int i, si
 // index is a 32-bit offset from a per-direction base that is uniform across
 // the wavefront, which keeps the address arithmetic in 32 bits.
 template <int Q, bool ODD>
-__device__ __forceinline__ int plain_read(const Nb &n, int i, int &dir) {
+__host__ __device__ __forceinline__ int plain_read(const Nb &n, int i, int &dir) {
   dir = ODD ? Lat<Q>::opp(i) : i;
   return ODD ? n.cell + nb_off<Q>(n, i, -1) : n.cell;
 }
 template <int Q, bool ODD>
-__device__ __forceinline__ int plain_write(const Nb &n, int i, int &dir) {
+__host__ __device__ __forceinline__ int plain_write(const Nb &n, int i, int &dir) {
   dir = ODD ? i : Lat<Q>::opp(i);
   return ODD ? n.cell + nb_off<Q>(n, i, +1) : n.cell;
 }

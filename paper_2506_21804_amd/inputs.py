@@ -213,14 +213,16 @@ def urban(nx: int = 768, ny: int = 768, nz: int = 256, q: int = 27, seed_offset:
           u_ref: float = 0.08, tau0: float = 0.5003, cs_smag: float = 0.2, fringe_len: int = 64,
           with_wall_dist: bool = True, x_lo: int = 64, x_hi: int | None = None,
           h_mean: float = 40.0, h_max: int = 192, fp_lo: int = 8, fp_hi: int = 40,
-          host_fields: bool = True, open_x: bool = False) -> Case:
+          host_fields: bool = True, open_x: bool = False, slip_walls: bool = False) -> Case:
     """Synthetic urban canopy: random buildings on a wall-modeled ground,
     periodic x with a fringe over the last ``fringe_len`` planes, periodic y,
     lid layer on top (with ``open_x``: a velocity inlet at x = 0 and a
     pressure outlet at x = nx - 1 instead of the periodic x axis, the fringe
     kept before the outlet; the wall distance still treats x as unbounded);
     initial velocity u_ref ln(1 + z_c/z0)/ln(1 + z_top/z0)
-    in x (z_c = z + 1/2, z_top = nz - 1/2, z0 = 1) in fluid cells.
+    in x (z_c = z + 1/2, z_top = nz - 1/2, z0 = 1) in fluid cells.  With
+    ``slip_walls`` the outer walls are full-slip faces, as in the street-canyon
+    setup: the two y faces and the top face (no lid, y not periodic).
 
     C_S defaults to 0.2: with the BGK collision, nu = 1e-4 and wall-modeled
     building faces, C_S = 0.1 lets the flow between buildings accelerate past
@@ -237,11 +239,13 @@ def urban(nx: int = 768, ny: int = 768, nz: int = 256, q: int = 27, seed_offset:
     if host_fields:
         u = np.zeros((3, N))
         u[0] = np.repeat(log_profile(nz, u_ref, z0), nx * ny) * mask
-    wd = voxel_wall_distance(mask, (nx, ny, nz), (1, 1, 0)) if with_wall_dist else None
-    return Case(name=f"urban{nx}x{ny}x{nz}" + ("_open" if open_x else ""), q=q, shape=(nx, ny, nz),
-                periodic=(0, 1, 0) if open_x else (1, 1, 0), tau0=tau0, cs_smag=cs_smag, wall_model=1,
-                fringe_len=fringe_len, u_ref=u_ref, z0=z0, lid=1, open_x=int(open_x), mask=mask, wall_dist=wd,
-                rho0=None, u0=u)
+    periodic = (0 if open_x else 1, 0 if slip_walls else 1, 0)
+    slip = 0b101100 if slip_walls else 0
+    wd = voxel_wall_distance(mask, (nx, ny, nz), (1, periodic[1], 0), slip=slip) if with_wall_dist else None
+    return Case(name=f"urban{nx}x{ny}x{nz}" + ("_open" if open_x else "") + ("_slip" if slip_walls else ""), q=q,
+                shape=(nx, ny, nz), periodic=periodic, tau0=tau0, cs_smag=cs_smag, wall_model=1,
+                fringe_len=fringe_len, u_ref=u_ref, z0=z0, lid=0 if slip_walls else 1, open_x=int(open_x),
+                slip=slip, mask=mask, wall_dist=wd, rho0=None, u0=u)
 
 
 def log_profile(nz: int, u_ref: float, z0: float = 1.0) -> np.ndarray:
