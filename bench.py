@@ -16,9 +16,11 @@ against FP32 storage.
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 Workloads: channel (default), channel16, urban, urban16, big, big16 (1024^3
-urban-style domain, the largest that fits one GPU), tgv, adjoint (reverse /
+urban-style domain, the largest that fits one GPU), urban_slip, urban_slip16
+(full-slip side and top faces), cavity, cavity16, tgv, adjoint (reverse /
 forward step time), precision (FP32 and FP16 storage against FP64 on the
-same GPU).
+same GPU), wall_balance (the channel's mean modeled wall stress against the
+body force at statistical steady state; --spinup, --steps, --sample-every).
 """
 from __future__ import annotations
 
@@ -60,6 +62,9 @@ def make_case(name):
     if name in ("urban_open", "urban_open16"):
         return I.urban(768, 768, 256, q=27, with_wall_dist=False, open_x=True), \
             ("f16" if name.endswith("16") else "f32"), "urban768x768x256_d3q27_smag_wallmodel_inlet_outlet_fringe_lid"
+    if name in ("urban_slip", "urban_slip16"):
+        return I.urban(768, 768, 256, q=27, with_wall_dist=False, slip_walls=True), \
+            ("f16" if name.endswith("16") else "f32"), "urban768x768x256_d3q27_smag_wallmodel_fringe_fullslip_sides_top"
     if name in ("big", "big16"):
         case = I.urban(1024, 1024, 1024, q=27, with_wall_dist=False, x_lo=64, x_hi=896, host_fields=False)
         case.u0 = I.urban_u0_device(case)
@@ -111,9 +116,11 @@ def cpu_baseline(name, budget_s=12.0, collision=0, fd_weight=0.0):
         sample = "channel crop 384x192x24 (walls at z), D3Q27 FP64"
     elif name.startswith("urban") or name.startswith("big"):
         open_x = name.startswith("urban_open")
-        case = I.urban(192, 192, 64, q=27, fringe_len=32, x_lo=16, x_hi=144, h_mean=20.0, h_max=48, open_x=open_x)
-        sample = "urban crop 192x192x64 (buildings, fringe, lid{}), D3Q27 FP64".format(
-            ", inlet and outlet" if open_x else "")
+        slip = name.startswith("urban_slip")
+        case = I.urban(192, 192, 64, q=27, fringe_len=32, x_lo=16, x_hi=144, h_mean=20.0, h_max=48, open_x=open_x,
+                       slip_walls=slip)
+        sample = "urban crop 192x192x64 (buildings, fringe, {}{}), D3Q27 FP64".format(
+            "full-slip sides and top" if slip else "lid", ", inlet and outlet" if open_x else "")
     elif name == "tgv":
         case = I.taylor_green(32, q=19)
         sample = "tgv 32^3 D3Q19 FP64 (full)"
@@ -191,6 +198,8 @@ def main():
                          "size 4 cells); the time of one inlet-field update is reported")
     ap.add_argument("--fd-weight", type=float, default=0.0,
                     help="with --collision rr3: weight 1 - sigma of the finite-difference strain (hybrid)")
+    ap.add_argument("--spinup", type=int, default=60000, help="wall_balance workload: steps before sampling")
+    ap.add_argument("--sample-every", type=int, default=200, help="wall_balance workload: steps between samples")
     ap.add_argument("--profile-steps", type=int, default=2000,
                     help="precision workload: second horizon, with mean-profile errors")
     args = ap.parse_args()
@@ -207,6 +216,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "precision":
         return bench_precision(args, torch, lbm)
+    if args.workload == "wall_balance":
+        return bench_wall_balance(args, torch, lbm)
     case, storage, wname = make_case(args.workload)
     if args.collision == "rr3":
         case.collision = 1
@@ -260,14 +271,17 @@ def main():
     mlups = N * args.steps / (ms_total * 1e-3) / 1e6
     print(f"[bench] timed {args.steps} steps: {ms_step:.4f} ms/step, {mlups:.1f} MLUPS (host {wall_s:.3f} s)",
           file=sys.stderr, flush=True)
-    # five more repeats of the same K steps, for the spread of the step time
+    # five more timed runs of K/5 steps each, for the spread of the step time
+    # (K more steps in all: the urban canopy with BGK, which turns unstable
+    # after some 1 800 steps, stays within that)
     reps = []
+    kr = max(1, args.steps // 5)
     for _ in range(5):
         ev0.record(stream)
-        lat.step(args.steps)
+        lat.step(kr)
         ev1.record(stream)
         lat.sync()
-        reps.append(ev0.elapsed_time(ev1) / args.steps)
+        reps.append(ev0.elapsed_time(ev1) / kr)
     print(f"[bench] 5 repeats: median {np.median(reps):.4f} ms/step", file=sys.stderr, flush=True)
 
     # per-kernel times over the same number of steps, events on the library's stream
@@ -320,7 +334,7 @@ def main():
                      "kernel": "k_bulk", "avg_launch_ms": round(k2_ms, 5), "alg_bytes_per_launch": k2_bytes},
         "mflups": round(nfluid * args.steps / (ms_total * 1e-3) / 1e6, 2),
         "repeat_ms_per_step": {"median": round(float(np.median(reps)), 5), "min": round(min(reps), 5),
-                               "max": round(max(reps), 5), "repeats": 5},
+                               "max": round(max(reps), 5), "repeats": 5, "steps_each": kr},
         "step_alg_gbs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
         "kernel_ms_per_step": {"wall_prepass_refwall": round(kms[0] / max(kcount[0], 1), 5),
                                "wall": round(kms[2] / max(kcount[2], 1), 5), "bulk": round(k2_ms, 5)},
@@ -426,6 +440,52 @@ def bench_precision(args, torch, lbm):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32 compute", "data": "synthetic",
            "config": {"workload": "channel384x192x192 (BGK) and urban768x768x256 (recursive regularized), D3Q27"},
            "errors": rows}
+    print(json.dumps(out), flush=True)
+
+
+def bench_wall_balance(args, torch, lbm):
+    """Momentum balance of the wall-modeled channel at statistical steady
+    state: the body force on the fluid, F per unit volume over the half
+    height h, is carried by the two walls, so the mean modeled wall stress
+    <rho u_tau^2> approaches F h.  Runs --spinup steps, then samples the wall
+    records every --sample-every steps for --steps steps; reports the ratio
+    <rho u_tau^2> / (F h) over the whole sample and over its two halves."""
+    from paper_2506_21804_amd import inputs as I
+    case = I.channel(384, 192, 192, q=27)
+    F, h = case.force[0], case.extra["h"]
+    lat = lbm.Lattice(case, storage="f32")
+    nwall = lbm.lbm_wall_count(lat.ctx)
+    rec_cells = lbm.lbm_wall_records(lat.ctx)["cells"]
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.spinup:
+        k = min(5000, args.spinup - done)
+        lat.step(k)
+        lat.sync()
+        done += k
+        print(f"[bench] wall balance spin-up {done}/{args.spinup} steps ({time.perf_counter() - t0:.0f} s)",
+              file=sys.stderr, flush=True)
+    samples = []
+    for s in range(0, args.steps, args.sample_every):
+        lat.step(args.sample_every)
+        rho, _ = lat.moments()
+        r = lbm.lbm_wall_records(lat.ctx)
+        rw = rho.double().reshape(-1)[torch.as_tensor(rec_cells.astype(np.int64), device="cuda")].cpu().numpy()
+        samples.append(float((rw * r["utau"] ** 2).mean()))
+        if (s // args.sample_every) % 20 == 0:
+            print(f"[bench] wall balance sample {len(samples)}: <rho u_tau^2>/(F h) = {samples[-1] / (F * h):.4f} "
+                  f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    sm = np.array(samples) / (F * h)
+    half = len(sm) // 2
+    out = {"metric": "wall-law momentum balance <rho u_tau^2> / (F h) at statistical steady state",
+           "value": round(float(sm.mean()), 4), "unit": "ratio", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.spinup, "ms_per_step": None, "higher_is_better": None, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 (fp32 deviation storage)", "data": "synthetic",
+           "config": {"workload": "channel384x192x192_d3q27_smag_wallmodel", "wall_cells": nwall,
+                      "sample_every": args.sample_every},
+           "halves": [round(float(sm[:half].mean()), 4), round(float(sm[half:].mean()), 4)],
+           "min": round(float(sm.min()), 4), "max": round(float(sm.max()), 4), "samples": len(sm),
+           "mass": float(lat.diagnostics()[0])}
     print(json.dumps(out), flush=True)
 
 

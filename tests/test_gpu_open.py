@@ -286,3 +286,57 @@ def test_open_gradient_matches_tangent(gpu, collision):
         _, dJ = t.objective(planes)
         announce(f"open gradient cell {cell} (x={cell % nx}): gpu {g[cell]:.12e} tangent {dJ:.12e}")
         assert abs(g[cell] - dJ) <= 1e-10 * max(abs(dJ), 1e-3 * np.abs(g).max())
+
+
+@pytest.mark.parametrize("collision", [0, 1])
+def test_open_gradient_mean_with_lid(gpu, collision):
+    """The time-averaged objective's gradient with open x faces and a lid
+    (the reverse kernel's seeded open-face and seeded lid branches), against
+    the oracle's tangent summed over the steps, FP64."""
+    case = dataclasses.replace(_open_porous(collision, 4), lid=1)
+    planes = (2, 17)
+    T, nsnap = 11, 3
+    N, nx = case.ncells, case.shape[0]
+    lat = gpu.Lattice(case, storage="f64")
+    grad = torch.zeros(N, dtype=torch.float64, device="cuda")
+    J, _ = gpu.lbm_gradient_mean(lat.ctx, T, planes, lat.new_state_buffer(nsnap), nsnap, lat.new_adjoint(), grad)
+    g = grad.cpu().numpy()
+    nz_ = case.shape[2]
+    lid_cell = 9 + nx * (3 + case.shape[1] * (nz_ - 1))
+    for cell in (0 + nx * 5, nx - 1 + nx * 30, 7 + nx * 17, lid_cell - nx * case.shape[1]):
+        t = oracle_for(case, tangent=True)
+        e = np.zeros(N)
+        e[cell] = 1.0
+        t.set_phi_tangent(e)
+        dJ = 0.0
+        for _ in range(T):
+            t.step(1)
+            dJ += t.objective(planes)[1]
+        dJ /= T
+        announce(f"open mean gradient (lid) cell {cell}: gpu {g[cell]:.12e} tangent {dJ:.12e}")
+        assert abs(g[cell] - dJ) <= 1e-10 * max(abs(dJ), 1e-3 * np.abs(g).max())
+
+
+def test_open_gradient_fp32(gpu):
+    """FP32 storage with open x faces (the rebuild's transpose in FP32, its
+    common part in FP64): the gradient against the oracle's tangent, per cell
+    relative to max(|dJ|, 1e-3 max|g|)."""
+    case = _open_porous(1, 4)
+    planes = (2, 17)
+    T, nsnap = 15, 3
+    N, nx = case.ncells, case.shape[0]
+    lat = gpu.Lattice(case, storage="f32")
+    grad = lat.new_gradient()
+    gpu.lbm_gradient(lat.ctx, T, planes, lat.new_state_buffer(nsnap), nsnap, lat.new_adjoint(), grad)
+    g = grad.cpu().numpy()
+    errs = []
+    for cell in (0 + nx * 5, nx - 1 + nx * 30, 7 + nx * 17):
+        t = oracle_for(case, tangent=True)
+        e = np.zeros(N)
+        e[cell] = 1.0
+        t.set_phi_tangent(e)
+        t.step(T)
+        _, dJ = t.objective(planes)
+        errs.append(abs(g[cell] - dJ) / max(abs(dJ), 1e-3 * np.abs(g).max()))
+    announce(f"open gradient fp32: per-cell errors {['%.2e' % x for x in errs]}")
+    assert max(errs) <= 1e-4, errs

@@ -212,6 +212,19 @@ def test_error_paths(gpu):
     with pytest.raises(gpu.LbmError) as e:
         gpu.Lattice(c2, storage="f32")
     assert e.value.code == gpu.EINVAL
+    # a friction Reynolds number far outside the wall law's range: the
+    # laminar start already needs exp(kappa U / u_tau) beyond exp(700), so
+    # the Newton solve refuses; the oracle refuses the same step
+    c3 = I.channel(16, 4, 6, q=19, utau=0.01, nu=1e-9, tau0=0.5 + 3e-9, cs_smag=0.1, amp=0.0)
+    c3.u0[0] = 0.1
+    lat = gpu.Lattice(c3, storage="f64")
+    lat.step(1)
+    with pytest.raises(gpu.LbmError) as e:
+        lat.sync()
+    assert e.value.code == gpu.ENEWTON
+    with pytest.raises(O.OracleError) as e:
+        oracle_for(c3, 1)
+    assert e.value.code == O.ENEWTON
 
 
 @pytest.mark.parametrize("q,storage,tol", [(19, "f64", 1e-12), (27, "f64", 1e-12), (19, "f32", 1e-5)])
