@@ -84,6 +84,7 @@ def lib():
         L.orc_collide_wall.argtypes = [C.c_int, C.c_double, C.c_double, vp, vp, vp, vp, C.c_double,
                                        C.c_double, C.c_double, vp]
         L.orc_set_phi_tangent.argtypes = [vp, vp]
+        L.orc_set_smagorinsky.argtypes = [vp, vp, vp]
         L.orc_objective.argtypes = [vp, vp, vp, vp]
         L.orc_num_wall.restype = C.c_long
         L.orc_num_wall.argtypes = [vp]
@@ -210,6 +211,14 @@ class Oracle:
         yz = np.ascontiguousarray(np.asarray(yz, dtype=np.float64).reshape(-1, 2))
         sign = np.ascontiguousarray(np.asarray(sign, dtype=np.int32).reshape(-1))
         self._check(lib().orc_set_vortices(self.h, len(sign), _ptr(yz), _ptr(sign), intensity, sigma))
+
+    def set_smagorinsky(self, cs, dcs=None):
+        """Per-cell Smagorinsky constants [N] (None: the scalar of the
+        parameters everywhere); dcs: their tangent direction (tangent mode)."""
+        a = None if cs is None else np.ascontiguousarray(cs, dtype=np.float64)
+        d = None if dcs is None else np.ascontiguousarray(dcs, dtype=np.float64)
+        self._keep_cs = (a, d)
+        self._check(lib().orc_set_smagorinsky(self.h, _ptr(a), _ptr(d)))
 
     def set_phi_tangent(self, dphi):
         dphi = np.ascontiguousarray(dphi, dtype=np.float64).reshape(-1)

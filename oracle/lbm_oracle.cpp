@@ -311,8 +311,8 @@ T guo_term(const VelSet& vs, int i, const T v[3], const double F[3]) {
 
 /* Effective relaxation time of the Smagorinsky BGK model (Eqs. (3),(4),(14)):
  * the positive root of tau^2 - tau0 tau - 9 C_S^2 |Pi| / (sqrt(2) rho) = 0. */
-template <class T>
-T tau_effective(double tau0, double cs, const T& pinorm, const T& rho) {
+template <class T, class C>
+T tau_effective(double tau0, const C& cs, const T& pinorm, const T& rho) {
   return 0.5 * (tau0 + sqrt(tau0 * tau0 + 18.0 * std::sqrt(2.0) * cs * cs * pinorm / rho));
 }
 
@@ -404,6 +404,7 @@ struct SimBase {
   virtual int get_populations(double* f, double* df) = 0;
   virtual int set_populations(const double* f, const double* df) = 0;
   virtual int set_phi_tangent(const double* dphi) = 0;
+  virtual int set_smagorinsky(const double* cs, const double* dcs) = 0;
   virtual int objective(const int planes[2], double* J, double* dJ) = 0;
   virtual int wall_info(long* cells, long* refs, double* normal, double* utau, double* G, double* tau) = 0;
   virtual int wall_velocity(double* tangent, double* utan) = 0;
@@ -420,6 +421,10 @@ struct Sim : SimBase {
   long N = 0;
   std::vector<uint8_t> fluid, kind;
   std::vector<T> phi;
+  /* per-cell Smagorinsky constant (the dynamics take C_S from the cell,
+   * Sec. 2.3); empty: the scalar cs_smag everywhere */
+  std::vector<T> csf;
+  T cs_at(long c) const { return csf.empty() ? T(p.cs_smag) : csf[c]; }
   std::vector<T> f, fs; /* [q][N]: state f^n and post-collision f* */
   /* wall-model geometry (fixed at creation) */
   std::vector<long> wcell, wref;
@@ -742,7 +747,8 @@ struct Sim : SimBase {
       }
       for (int a = 0; a < 3; ++a) wt[3 * k + a] = ut[a] / U;
       wutan[k] = utau * uplus_b;
-      double cs2 = p.cs_smag * p.cs_smag;
+      const T csb = cs_at(wcell[k]);
+      T cs2 = csb * csb;
       T G = 2.0 * utau * utau / (nu + sqrt(nu * nu + 4.0 * cs2 * utau * utau));
       wG[k] = G;
       wutau[k] = utau;
@@ -814,7 +820,7 @@ struct Sim : SimBase {
     T pi2(0.0);
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) pi2 += Pi[a][b] * Pi[a][b];
-    T tau = tau_effective(p.tau0, p.cs_smag, sqrt(pi2), rho);
+    T tau = tau_effective(p.tau0, cs_at(c), sqrt(pi2), rho);
     T uh[3];
     for (int a = 0; a < 3; ++a) uh[a] = phi[c] * u[a];
     T feqh[27];
@@ -1114,6 +1120,24 @@ struct Sim : SimBase {
 
   int set_populations(const double* fi, const double* dfi) override;
   int set_phi_tangent(const double* dphi) override;
+  /* per-cell Smagorinsky constants (and, in tangent mode, their direction) */
+  int set_smagorinsky(const double* cs, const double* dcs) override {
+    if (!cs) {
+      csf.clear();
+      return ORC_OK;
+    }
+    for (long c = 0; c < N; ++c)
+      if (!(cs[c] >= 0.0) || !std::isfinite(cs[c])) {
+        err = "Smagorinsky constants must be finite and >= 0";
+        return ORC_EINVAL;
+      }
+    csf.assign(N, T(0.0));
+    for (long c = 0; c < N; ++c) {
+      if constexpr (std::is_same<T, Dual>::value) csf[c] = Dual(cs[c], dcs ? dcs[c] : 0.0);
+      else csf[c] = T(cs[c]);
+    }
+    return ORC_OK;
+  }
 
   /* Terminal objective of the porosity-gradient study: pressure drop between
    * two x-planes plus mean kinetic energy (both over fluid cells). */
@@ -1241,6 +1265,9 @@ int orc_set_populations(void* h, const double* f, const double* df) {
   return static_cast<SimBase*>(h)->set_populations(f, df);
 }
 int orc_set_phi_tangent(void* h, const double* dphi) { return static_cast<SimBase*>(h)->set_phi_tangent(dphi); }
+int orc_set_smagorinsky(void* h, const double* cs, const double* dcs) {
+  return static_cast<SimBase*>(h)->set_smagorinsky(cs, dcs);
+}
 int orc_objective(void* h, const int* planes, double* J, double* dJ) {
   return static_cast<SimBase*>(h)->objective(planes, J, dJ);
 }

@@ -103,6 +103,9 @@ MUTATIONS = [
     ("slip links counted as wall links",
      "if (!is_fluid(nb) && !slip_cross(bx, by, bz, vs.c[i][0], vs.c[i][1], vs.c[i][2])) {",
      "if (!is_fluid(nb)) {"),
+    ("per-cell C_S ignored in the bulk", "T tau = tau_effective(p.tau0, cs_at(c), sqrt(pi2), rho);",
+     "T tau = tau_effective(p.tau0, T(p.cs_smag), sqrt(pi2), rho);"),
+    ("per-cell C_S ignored in the wall records", "const T csb = cs_at(wcell[k]);", "const T csb = T(p.cs_smag);"),
 ]
 
 PIN_TESTS = [
@@ -138,6 +141,9 @@ PIN_TESTS = [
     (pins_slip.test_slip_top_over_bounce_back_ground_with_buildings, [()]),
     (pins_slip.test_slip_faces_are_not_wall_modeled, [()]),
     (pins_wall.test_tangent_through_wall_model_matches_central_differences, [()]),
+    (pins_wall.test_smagorinsky_field_relation_per_cell, [(19,)]),
+    (pins_wall.test_smagorinsky_field_in_wall_records, [()]),
+    (pins_wall.test_tangent_in_smagorinsky_field, [()]),
 ]
 
 

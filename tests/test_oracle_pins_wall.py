@@ -269,3 +269,97 @@ def test_tangent_wall_records():
     fd_state = (fps[0] - fps[1]) / (2 * h)
     assert abs(fd) > 0.0
     np.testing.assert_allclose(df1, fd_state, rtol=0, atol=1e-7 * np.abs(fd_state).max())
+
+
+# ---------------------------------------------------------------------------
+# Per-cell Smagorinsky constant (the dynamics take C_S from the cell, Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+def test_smagorinsky_field_uniform_equals_scalar():
+    """A field holding the scalar C_S everywhere reproduces the scalar run
+    bit for bit (bulk, walls and wall model)."""
+    case = I.channel(12, 8, 10, q=27)
+    a = oracle_for(case, 5)
+    b = oracle_for(case)
+    b.set_smagorinsky(np.full(case.ncells, case.cs_smag))
+    b.step(5)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_smagorinsky_field_relation_per_cell(q):
+    """Random C_S per cell on a random state: each cell's relaxed stress
+    Pi* = (1 - 1/tau) Pi gives a tau that solves tau^2 - tau0 tau =
+    9 sqrt(2)/2 C_c^2 |Pi| / rho with that cell's own C_c (F = 0, phi = 1)."""
+    shape = (6, 5, 4)
+    N = int(np.prod(shape))
+    c, w, _ = O.velocity_set(q)
+    f0 = I.random_state(w, N, seed_offset=101, amp=0.05)
+    cs = np.random.default_rng(102).uniform(0.0, 0.3, N)
+    tau0 = 0.57
+    p = O.make_params(q, shape, tau0=tau0, cs_smag=0.1)
+    s = O.Oracle(p)
+    s.set_populations(f0)
+    s.set_smagorinsky(cs)
+    s.step(1)
+    fs = s.post_collision()
+    cc = c.astype(float)
+    for cell in range(N):
+        f = f0[:, cell]
+        rho = f.sum()
+        u = cc.T @ f / rho
+        feq = O.equilibrium(q, rho, u)
+        Pi = np.einsum("ia,ib,i->ab", cc, cc, f - feq)
+        Pis = np.einsum("ia,ib,i->ab", cc, cc, fs[:, cell] - feq)
+        tau = 1.0 / (1.0 - (Pis * Pi).sum() / (Pi * Pi).sum())
+        rhs = 4.5 * np.sqrt(2.0) * cs[cell] ** 2 * np.sqrt((Pi * Pi).sum()) / rho
+        # tau comes back through 1/(1 - ratio): rounding of a few 1e-16 in tau^2
+        assert abs(tau * tau - tau0 * tau - rhs) <= 1e-9 * rhs + 1e-14, cell
+
+
+def test_smagorinsky_field_in_wall_records():
+    """The wall records take the wall cell's own C_S: G (nu + C_b^2 G) =
+    u_tau^2 and tau_b = 3 (nu + C_b^2 G) + 1/2 with C_b from the field."""
+    case = I.channel(12, 8, 10, q=27)
+    cs = np.random.default_rng(103).uniform(0.05, 0.3, case.ncells)
+    s = oracle_for(case)
+    s.set_smagorinsky(cs)
+    s.step(3)
+    info = s.wall_info()
+    nu = (case.tau0 - 0.5) / 3.0
+    cb = cs[info["cells"]]
+    np.testing.assert_allclose(info["G"] * (nu + cb ** 2 * info["G"]), info["utau"] ** 2, rtol=1e-12)
+    np.testing.assert_allclose(info["tau"], 3.0 * (nu + cb ** 2 * info["G"]) + 0.5, rtol=1e-14)
+
+
+def test_tangent_in_smagorinsky_field():
+    """dJ/dC_S at a wall cell, a reference cell and a bulk cell from the
+    tangent oracle against central differences (wall-modeled porous
+    channel)."""
+    case = _wall_porous_case()
+    planes = (1, 9)
+    steps = 10
+    nx, ny, nz = case.shape
+    p = O.make_params(19, case.shape, periodic=case.periodic, tau0=case.tau0, cs_smag=case.cs_smag,
+                      force=case.force, wall_model=1)
+    kw = dict(mask=case.mask, wall_dist=case.wall_dist, porosity=case.porosity, rho0=case.rho0, u0=case.u0)
+    cs = np.random.default_rng(104).uniform(0.05, 0.2, case.ncells)
+    for cell in (3 + nx * 4, 3 + nx * (4 + ny), 6 + nx * (2 + ny * 4)):
+        e = np.zeros(case.ncells)
+        e[cell] = 1.0
+        s = O.Oracle(p, tangent=True, **kw)
+        s.set_smagorinsky(cs, e)
+        s.step(steps)
+        _, dJ = s.objective(planes)
+        # C_S ~ 0.1: h = 1e-4 keeps the O(h^2) truncation near 1e-8 relative
+        # and the rounding of J (about 1e-16 absolute) below 1e-12 after / 2h
+        h = 1e-4
+        Js = []
+        for sgn in (1, -1):
+            t = O.Oracle(p, **kw)
+            t.set_smagorinsky(cs + sgn * h * e)
+            t.step(steps)
+            Js.append(t.objective(planes)[0])
+        fd = (Js[0] - Js[1]) / (2 * h)
+        assert abs(dJ) > 0.0
+        assert abs(dJ - fd) <= 1e-5 * abs(fd) + 1e-14, (cell, dJ, fd)
