@@ -109,6 +109,8 @@ typedef struct {
                        * is solid).  These links are not walls of the wall model;
                        * the voxel wall distance mirrors the geometry across them.
                        * 0 = none (outside a non-periodic axis is a no-slip wall). */
+  int cs_field;       /* 1 reserves workspace for a per-cell Smagorinsky constant
+                       * (lbm_set_smagorinsky); 0 = the scalar cs_smag only */
   void *stream;       /* hipStream_t for all device work (NULL = null stream) */
 } lbm_params;
 
@@ -229,8 +231,8 @@ int lbm_adjoint_from_natural(lbm_ctx *ctx, const void *natural, void *lambda);
  * checkpoint to T-1.  *J receives the objective at step T and *nforward the
  * forward steps taken (lbm_revolve_cost(T, nsnap) + 1 + that re-advance; T
  * exactly when nsnap > T).  On return the context holds the state of step 0
- * again.  Synchronises.  Not available with the wall model or the hybrid
- * collision. */
+ * again.  Synchronises.  Not available with the hybrid collision (the
+ * finite-difference strain is not differentiated). */
 int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
                  void *grad_phi, double *J, long long *nforward);
 
@@ -245,6 +247,29 @@ int lbm_gradient_mean(lbm_ctx *ctx, int T, const int planes[2], void *snapshots,
 /* The forward-step count of the optimal binomial schedule for T steps and
  * nsnap snapshot slots (host only; the starting state occupies one slot). */
 long long lbm_revolve_cost(int T, int nsnap);
+
+/* Per-cell Smagorinsky constant (Sec. 2.3: the dynamics take C_S from the
+ * cell).  cs: DEVICE double [N], C_S >= 0 and finite at every cell (solid
+ * cells included; their value is unused), copied into the workspace in the
+ * compute type (FP64 for FP64 storage, FP32 otherwise); NULL returns to the
+ * scalar lbm_params.cs_smag.  Needs lbm_params.cs_field = 1 at lbm_init
+ * (LBM_EINVAL otherwise).  From the next step on, the bulk collision takes
+ * tau_eff with the cell's own C_S, and each wall record's G and tau_b the
+ * wall cell's.  A rejected field (negative, NaN or infinite entry) gives
+ * LBM_EINVAL and leaves the previous C_S in force.  Synchronises. */
+int lbm_set_smagorinsky(lbm_ctx *ctx, const double *cs);
+
+/* Gradients with respect to the per-cell Smagorinsky constant as well.
+ *  lbm_adjoint_step_cs: lbm_adjoint_step that also adds dJ/dC_S of step n
+ *    to grad_cs [N] (double, device).  The derivative is taken at the C_S in
+ *    force: the field, or the scalar cs_smag at every cell.
+ *  lbm_gradient_cs: the checkpointed sweep of lbm_gradient (mean = 0) or
+ *    lbm_gradient_mean (mean = 1) with grad_cs [N] overwritten by dJ/dC_S
+ *    next to grad_phi.  Same conditions and synchronisation; solid cells
+ *    read 0. */
+int lbm_adjoint_step_cs(lbm_ctx *ctx, void *lambda, void *grad_phi, void *grad_cs);
+int lbm_gradient_cs(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
+                    void *grad_phi, void *grad_cs, int mean, double *J, long long *nforward);
 
 /* Number of wall-modeled cells, and their records (host arrays of that
  * length; any pointer may be NULL): cell, reference cell, normal [n][3],

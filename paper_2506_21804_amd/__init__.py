@@ -21,6 +21,7 @@ __all__ = [
     "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural",
     "lbm_gradient", "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
     "lbm_set_inflow_vortices", "lbm_gradient_mean", "lbm_stream_probe", "lbm_slot_map", "lbm_last_error",
+    "lbm_set_smagorinsky", "lbm_adjoint_step_cs", "lbm_gradient_cs",
     "lbm_free", "params_for", "Lattice", "D3Q19", "D3Q27", "F64", "F32DEV", "F16DEV",
 ]
 
@@ -52,6 +53,7 @@ class Params(C.Structure):
         ("open_x", C.c_int),
         ("rho_out", C.c_double),
         ("slip", C.c_int),
+        ("cs_field", C.c_int),
         ("stream", C.c_void_p),
     ]
 
@@ -108,6 +110,9 @@ def load():
         "lbm_gradient_mean": (i, [vp, i, vp, vp, i, vp, vp, C.POINTER(d), C.POINTER(ll)]),
         "lbm_stream_probe": (i, [vp, i, C.POINTER(d)]),
         "lbm_slot_map": (i, [C.POINTER(Params), vp, i, vp, vp]),
+        "lbm_set_smagorinsky": (i, [vp, vp]),
+        "lbm_adjoint_step_cs": (i, [vp, vp, vp, vp]),
+        "lbm_gradient_cs": (i, [vp, i, vp, vp, i, vp, vp, vp, i, C.POINTER(d), C.POINTER(ll)]),
         "lbm_last_error": (C.c_char_p, [vp]),
         "lbm_free": (None, [vp]),
     }
@@ -127,7 +132,7 @@ def exported_symbols():
             "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural", "lbm_gradient",
             "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
             "lbm_set_inflow_vortices", "lbm_gradient_mean", "lbm_stream_probe", "lbm_slot_map",
-            "lbm_last_error", "lbm_free"]
+            "lbm_set_smagorinsky", "lbm_adjoint_step_cs", "lbm_gradient_cs", "lbm_last_error", "lbm_free"]
 
 
 def _dptr(t):
@@ -177,7 +182,7 @@ def _check(ctx, rc):
 
 def make_params(q, shape, periodic=(1, 1, 1), storage=F64, tau0=0.6, cs_smag=0.0, force=(0.0, 0.0, 0.0),
                 wall_model=0, kappa=0.41, E=9.0, fringe_len=0, u_ref=0.0, z0=1.0, lid=0, collision=0,
-                fd_weight=0.0, open_x=0, rho_out=1.0, slip=0, stream=None) -> Params:
+                fd_weight=0.0, open_x=0, rho_out=1.0, slip=0, cs_field=0, stream=None) -> Params:
     p = Params()
     p.lattice = q
     p.nx, p.ny, p.nz = shape
@@ -191,6 +196,7 @@ def make_params(q, shape, periodic=(1, 1, 1), storage=F64, tau0=0.6, cs_smag=0.0
     p.fd_weight = fd_weight
     p.open_x, p.rho_out = int(open_x), rho_out
     p.slip = int(slip)
+    p.cs_field = int(cs_field)
     p.stream = stream
     return p
 
@@ -315,6 +321,17 @@ def lbm_adjoint_step(ctx, lam, grad):
     _check(ctx, load().lbm_adjoint_step(ctx, _lam(ctx, lam), _grad(ctx, grad)))
 
 
+def lbm_adjoint_step_cs(ctx, lam, grad, grad_cs):
+    _check(ctx, load().lbm_adjoint_step_cs(ctx, _lam(ctx, lam), _grad(ctx, grad), _grad(ctx, grad_cs)))
+
+
+def lbm_set_smagorinsky(ctx, cs):
+    """cs: float64 device tensor of N values, or None (back to the scalar)."""
+    import torch
+    q, N, dt, cb = _sizes(ctx)
+    _check(ctx, load().lbm_set_smagorinsky(ctx, None if cs is None else _dbuf(cs, N * 8, "C_S field", torch.float64)))
+
+
 def lbm_adjoint_to_natural(ctx, lam, nat):
     _check(ctx, load().lbm_adjoint_to_natural(ctx, _lam(ctx, lam), _nat(ctx, nat)))
 
@@ -341,6 +358,17 @@ def lbm_gradient_mean(ctx, T, planes, snapshots, nsnap, lam, grad):
     snaps = _dbuf(snapshots, int(nsnap) * lbm_state_bytes(ctx), "snapshots")
     _check(ctx, load().lbm_gradient_mean(ctx, int(T), pl, snaps, int(nsnap), _lam(ctx, lam), _grad(ctx, grad),
                                          C.byref(J), C.byref(nf)))
+    return J.value, nf.value
+
+
+def lbm_gradient_cs(ctx, T, planes, snapshots, nsnap, lam, grad, grad_cs, mean=False):
+    """lbm_gradient (or, with mean, lbm_gradient_mean) that also writes dJ/dC_S."""
+    pl = (C.c_int * 2)(*planes)
+    J = C.c_double()
+    nf = C.c_longlong()
+    snaps = _dbuf(snapshots, int(nsnap) * lbm_state_bytes(ctx), "snapshots")
+    _check(ctx, load().lbm_gradient_cs(ctx, int(T), pl, snaps, int(nsnap), _lam(ctx, lam), _grad(ctx, grad),
+                                       _grad(ctx, grad_cs), int(bool(mean)), C.byref(J), C.byref(nf)))
     return J.value, nf.value
 
 
@@ -406,14 +434,14 @@ def lbm_slot_map(p: Params, mask, parity):
     return rd, wr
 
 
-def params_for(case, storage="f64", stream=None) -> Params:
+def params_for(case, storage="f64", stream=None, cs_field=False) -> Params:
     """lbm_params of an ``inputs.Case``."""
     return make_params(case.q, case.shape, periodic=case.periodic, storage=storage, tau0=case.tau0,
                        cs_smag=case.cs_smag, force=case.force, wall_model=case.wall_model, kappa=case.kappa,
                        E=case.E, fringe_len=case.fringe_len, u_ref=case.u_ref, z0=case.z0, lid=case.lid,
                        collision=getattr(case, "collision", 0), fd_weight=getattr(case, "fd_weight", 0.0),
                        open_x=getattr(case, "open_x", 0), rho_out=getattr(case, "rho_out", 1.0),
-                       slip=getattr(case, "slip", 0), stream=stream)
+                       slip=getattr(case, "slip", 0), cs_field=int(bool(cs_field)), stream=stream)
 
 
 def lbm_last_error(ctx) -> str:
@@ -433,7 +461,7 @@ class Lattice:
     ``storage`` one of "f64", "f32", "f16".  rho0/u0 of the case are uploaded
     to the device as float64 for initialisation and then released."""
 
-    def __init__(self, case, storage="f64", stream=None, wall_dist="case"):
+    def __init__(self, case, storage="f64", stream=None, wall_dist="case", cs_field=False):
         import torch
         self.torch = torch
         if stream is None:
@@ -444,7 +472,7 @@ class Lattice:
         self.N = int(np.prod(self.shape))
         self.storage = STORAGE_NAMES[storage] if isinstance(storage, str) else storage
         self.rdtype = torch.float64 if self.storage == F64 else torch.float32
-        self.p = params_for(case, storage=self.storage, stream=stream.cuda_stream)
+        self.p = params_for(case, storage=self.storage, stream=stream.cuda_stream, cs_field=cs_field)
         porous = case.porosity is not None
         nbytes = lbm_workspace_bytes(self.p, case.mask, porous)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
@@ -500,6 +528,14 @@ class Lattice:
 
     def diagnostics(self):
         return lbm_diagnostics(self.ctx)
+
+    def set_smagorinsky(self, cs):
+        """Per-cell C_S (array or tensor of N values; None = the scalar);
+        the lattice must have been made with cs_field=True."""
+        if cs is not None:
+            cs = self.torch.as_tensor(np.asarray(cs, dtype=np.float64) if not isinstance(cs, self.torch.Tensor)
+                                      else cs, dtype=self.torch.float64, device="cuda").contiguous()
+        lbm_set_smagorinsky(self.ctx, cs)
 
     def populations(self):
         f = self.torch.empty((self.q, self.N), dtype=self.rdtype, device="cuda")

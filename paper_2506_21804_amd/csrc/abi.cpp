@@ -118,7 +118,7 @@ bool params_ok(const lbm_params *p, std::string &msg) {
 }
 
 struct Layout {
-  size_t pop, flags, phi, tables, vel, inflow, vort, wcell, wref, wrefwall, wlist, wrec, rcell, roff, rrec, partial,
+  size_t pop, flags, phi, csf, tables, vel, inflow, vort, wcell, wref, wrefwall, wlist, wrec, rcell, roff, rrec, partial,
       result, errflag,
       total;
 };
@@ -134,6 +134,8 @@ Layout layout_of(const lbm_params &p, long long nwall, bool porous) {
   off += align_up(N);
   L.phi = off;
   off += porous ? align_up(N * rb) : 0;
+  L.csf = off;
+  off += p.cs_field ? align_up(N * rb) : 0;
   L.tables = off;
   off += align_up(((size_t)p.nz + p.nx) * rb);
   L.vel = off;
@@ -320,6 +322,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   ctx->pop = base + L.pop;
   ctx->flags = (uint8_t *)(base + L.flags);
   ctx->phi = ctx->porous ? base + L.phi : nullptr;
+  ctx->csf = p->cs_field ? base + L.csf : nullptr;
   ctx->tables = base + L.tables;
   ctx->vel = p->fd_weight > 0.0 ? base + L.vel : nullptr;
   ctx->inflow = p->open_x ? base + L.inflow : nullptr;
@@ -346,7 +349,9 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   k.N = (int)N;
   for (int a = 0; a < 3; ++a) k.per[a] = p->periodic[a] ? 1 : 0;
   k.tau0 = p->tau0;
+  k.cs = p->cs_smag;
   k.cs2 = p->cs_smag * p->cs_smag;
+  k.csf = nullptr;
   k.smag = 18.0 * std::sqrt(2.0) * k.cs2;
   k.nu = (p->tau0 - 0.5) / 3.0;
   for (int a = 0; a < 3; ++a) k.F[a] = p->force[a];
@@ -593,13 +598,33 @@ int lbm_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lambda) {
   return dev_adjoint_seed(ctx, planes, lambda);
 }
 
-int lbm_adjoint_step(lbm_ctx *ctx, void *lambda, void *grad_phi) {
+int lbm_adjoint_step_cs(lbm_ctx *ctx, void *lambda, void *grad_phi, void *grad_cs) {
   if (!ctx || !lambda || !grad_phi) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
   if (ctx->ka.fdw > 0.0)
     return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the finite-difference strain");
-  if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
+  if (!adj_aligned(lambda) || !adj_aligned(grad_phi) || !adj_aligned(grad_cs))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
-  return dev_adjoint_step(ctx, lambda, grad_phi);
+  return dev_adjoint_step(ctx, lambda, grad_phi, grad_cs);
+}
+
+int lbm_adjoint_step(lbm_ctx *ctx, void *lambda, void *grad_phi) {
+  return lbm_adjoint_step_cs(ctx, lambda, grad_phi, nullptr);
+}
+
+int lbm_set_smagorinsky(lbm_ctx *ctx, const double *cs) {
+  if (!ctx) return LBM_EINVAL;
+  if (!ctx->csf) return set_err(ctx, LBM_EINVAL, "no room for a C_S field: create the context with cs_field = 1");
+  if (!cs) {
+    ctx->ka.csf = nullptr;
+    return LBM_OK;
+  }
+  if (((uintptr_t)cs & 7u) != 0) return set_err(ctx, LBM_EINVAL, "C_S field not 8-byte aligned");
+  int bad = 0;
+  const int rc = dev_set_cs(ctx, cs, &bad);
+  if (rc != LBM_OK) return rc;
+  if (bad) return set_err(ctx, LBM_EINVAL, "C_S must be finite and >= 0 at every cell");
+  ctx->ka.csf = ctx->csf;
+  return LBM_OK;
 }
 
 int lbm_adjoint_to_natural(lbm_ctx *ctx, const void *lambda, void *natural) {
@@ -622,13 +647,13 @@ long long lbm_revolve_cost(int T, int nsnap) { return revolve_cost(T, nsnap); }
 // each step index is reached); its seeds enter the reverse steps t = T-1 .. 1
 // fused into the adjoint kernel, and the terminal seed is scaled by 1/T.
 static int gradient_sweep(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
-                          void *grad_phi, double *J, long long *nforward, bool mean) {
+                          void *grad_phi, void *grad_cs, double *J, long long *nforward, bool mean) {
   if (!ctx) return LBM_EINVAL;
   if (T < 1 || nsnap < 1 || !snapshots || !lambda || !grad_phi || !planes)
     return set_err(ctx, LBM_EINVAL, "gradient needs T >= 1, nsnap >= 1 and non-null buffers");
   if (ctx->ka.fdw > 0.0)
     return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the finite-difference strain");
-  if (!adj_aligned(lambda) || !adj_aligned(grad_phi))
+  if (!adj_aligned(lambda) || !adj_aligned(grad_phi) || !adj_aligned(grad_cs))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   const size_t sb = lbm_state_bytes(ctx);
   auto slot = [&](int k) { return (char *)snapshots + (size_t)k * sb; };
@@ -637,6 +662,7 @@ static int gradient_sweep(lbm_ctx *ctx, int T, const int planes[2], void *snapsh
   if (rc != LBM_OK) return rc;
   const long long step0 = ctx->steps;
   if ((rc = dev_fill(ctx, grad_phi, (size_t)ctx->N * sizeof(double))) != LBM_OK) return rc;
+  if (grad_cs && (rc = dev_fill(ctx, grad_cs, (size_t)ctx->N * sizeof(double))) != LBM_OK) return rc;
   // The binomial schedule's first descent is the forward sweep: it stores
   // its checkpoints on the way to step T-1.  There, one more step gives the
   // final state for the objective and the seed; then the last restored
@@ -699,7 +725,8 @@ static int gradient_sweep(lbm_ctx *ctx, int T, const int planes[2], void *snapsh
         }
         if (ctx->steps != step0 + a.arg) return set_err(ctx, LBM_EINVAL, "internal: schedule out of step");
         // the seed of step t (t >= 1) joins the reverse step that produces dJ/df_t
-        if ((rc = dev_adjoint_step(ctx, lambda, grad_phi, mean && a.arg >= 1 ? w : 0.0, planes)) != LBM_OK)
+        if ((rc = dev_adjoint_step(ctx, lambda, grad_phi, grad_cs, mean && a.arg >= 1 ? w : 0.0, planes)) !=
+            LBM_OK)
           return rc;
         break;
     }
@@ -713,12 +740,19 @@ static int gradient_sweep(lbm_ctx *ctx, int T, const int planes[2], void *snapsh
 
 int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
                  void *grad_phi, double *J, long long *nforward) {
-  return gradient_sweep(ctx, T, planes, snapshots, nsnap, lambda, grad_phi, J, nforward, false);
+  return gradient_sweep(ctx, T, planes, snapshots, nsnap, lambda, grad_phi, nullptr, J, nforward, false);
 }
 
 int lbm_gradient_mean(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
                       void *grad_phi, double *J, long long *nforward) {
-  return gradient_sweep(ctx, T, planes, snapshots, nsnap, lambda, grad_phi, J, nforward, true);
+  return gradient_sweep(ctx, T, planes, snapshots, nsnap, lambda, grad_phi, nullptr, J, nforward, true);
+}
+
+int lbm_gradient_cs(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
+                    void *grad_phi, void *grad_cs, int mean, double *J, long long *nforward) {
+  if (!ctx) return LBM_EINVAL;
+  if (!grad_cs) return set_err(ctx, LBM_EINVAL, "null C_S gradient buffer");
+  return gradient_sweep(ctx, T, planes, snapshots, nsnap, lambda, grad_phi, grad_cs, J, nforward, mean != 0);
 }
 
 int lbm_wall_count(const lbm_ctx *ctx) { return ctx ? ctx->nwall : -1; }

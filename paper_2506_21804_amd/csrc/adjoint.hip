@@ -62,10 +62,12 @@ __device__ __forceinline__ bool atile_xyz(const KArgs &k, ATiles t, int &x, int 
 
 // Vector-Jacobian product of the bulk collision in precision R.  g holds the
 // state deviations, mu the adjoints of the outputs; the adjoint of input
-// population i is handed to out(i, value) as soon as it is known, and the
-// porosity adjoint is returned.
+// population i is handed to out(i, value) as soon as it is known, the
+// porosity adjoint is returned and the adjoint of the cell's Smagorinsky
+// coefficient smag = 18 sqrt(2) C_S^2 goes to smagb.
 template <int Q, typename R, bool POROUS, typename OUT>
-__device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi, const KArgs &k, OUT out) {
+__device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi, R smag, const KArgs &k, OUT out,
+                                              R &smagb) {
   // ---- forward recomputation
   R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
   R mxx = R(0), myy = R(0), mzz = R(0), mxy = R(0), mxz = R(0), myz = R(0);
@@ -96,7 +98,7 @@ __device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi
   const R pxz = mxz - rho * ux * uz;
   const R pyz = myz - rho * uy * uz;
   const R pn = sqrt(pxx * pxx + pyy * pyy + pzz * pzz + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz));
-  const R tau0 = R(k.tau0), smag = R(k.smag);
+  const R tau0 = R(k.tau0);
   const R sA = sqrt(tau0 * tau0 + smag * pn * ir);
   const R tau = R(0.5) * (tau0 + sA);
   const R om = R(1) / tau;
@@ -177,6 +179,7 @@ __device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi
   const R Ab = R(0.5) * taub / (R(2) * sA);
   const R pnb = Ab * smag * ir;
   R irb = Ab * smag * pn;
+  smagb = Ab * pn * ir;
   const R q = pn > R(0) ? pnb / pn : R(0);  // d pn / d P_ab = P_ab / pn (off-diagonals twice)
   const R pxxb = q * pxx, pyyb = q * pyy, pzzb = q * pzz;
   const R pxyb = R(2) * q * pxy, pxzb = R(2) * q * pxz, pyzb = R(2) * q * pyz;
@@ -221,7 +224,8 @@ __device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi
 // M_k = sum_i mu_i w_i P_k(c_i)).  The outputs depend on g only through its
 // moments.
 template <int Q, typename R, bool POROUS, typename OUT>
-__device__ __forceinline__ R collide_bulk_rr_vjp(const R g[Q], const R mu[Q], R phi, const KArgs &k, OUT out) {
+__device__ __forceinline__ R collide_bulk_rr_vjp(const R g[Q], const R mu[Q], R phi, R smag, const KArgs &k, OUT out,
+                                                 R &smagb) {
   // ---- forward recomputation
   R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
   R mxx = R(0), myy = R(0), mzz = R(0), mxy = R(0), mxz = R(0), myz = R(0);
@@ -252,7 +256,7 @@ __device__ __forceinline__ R collide_bulk_rr_vjp(const R g[Q], const R mu[Q], R 
   const R pxz = mxz - rho * ux * uz;
   const R pyz = myz - rho * uy * uz;
   const R pn = sqrt(pxx * pxx + pyy * pyy + pzz * pzz + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz));
-  const R tau0 = R(k.tau0), smag = R(k.smag);
+  const R tau0 = R(k.tau0);
   const R sA = sqrt(tau0 * tau0 + smag * pn * ir);
   const R tau = R(0.5) * (tau0 + sA);
   const R om = R(1) / tau;
@@ -393,6 +397,7 @@ __device__ __forceinline__ R collide_bulk_rr_vjp(const R g[Q], const R mu[Q], R 
   const R Abar = R(0.5) * taub / (R(2) * sA);
   const R pnb = Abar * smag * ir;
   R irb = Abar * smag * pn;
+  smagb = Abar * pn * ir;
   const R q = pn > R(0) ? pnb / pn : R(0);
   pxxb += q * pxx;
   pyyb += q * pyy;
@@ -680,9 +685,9 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
                                                     typename Store<S>::R *__restrict__ dev,
                                                     const double *__restrict__ m_prev, double *__restrict__ m_next,
                                                     const typename Store<S>::R *__restrict__ phi,
-                                                    double *__restrict__ grad, KArgs k, ATiles t, int p0 = 0,
-                                                    int p1 = 0, const double *__restrict__ cnt = nullptr,
-                                                    double sw = 0.0) {
+                                                    double *__restrict__ grad, double *__restrict__ gcs, KArgs k,
+                                                    ATiles t, int p0 = 0, int p1 = 0,
+                                                    const double *__restrict__ cnt = nullptr, double sw = 0.0) {
   using R = typename Store<S>::R;
   int x, y, z;
   if (!atile_xyz(k, t, x, y, z)) return;
@@ -735,7 +740,12 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
     if constexpr (SEED) v += (R)cs.template kin<Q>(i);
     dev[read_slot<Q, ODD, SOLID == 2>(n, sm, i, N)] = v;
   };
-  R phib;
+  const R smag = smag_of<R>(k, n.cell);
+  R phib, smagb;
+  // dJ/dC_S of the cell (gcs != NULL): smag = 18 sqrt(2) C_S^2
+  auto add_cs = [&]() {
+    if (gcs) gcs[n.cell] += (double)smagb * (2.0 * SMAG_COEF) * cs_of<R>(k, n.cell);
+  };
   if constexpr (OPEN) {
     if (fl & (FL_INLET | FL_OUTLET)) {
       // open face: the collision acts on the rebuilt populations; the
@@ -746,8 +756,8 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
       om.forward(g, gre);
       R ob[Q], one[Q];
       auto collect = [&](int i, R v) { ob[i] = v; };
-      if constexpr (RR) phib = collide_bulk_rr_vjp<Q, R, POROUS>(gre, dmu, ph, k, collect);
-      else phib = collide_bulk_vjp<Q, R, POROUS>(gre, dmu, ph, k, collect);
+      if constexpr (RR) phib = collide_bulk_rr_vjp<Q, R, POROUS>(gre, dmu, ph, smag, k, collect, smagb);
+      else phib = collide_bulk_vjp<Q, R, POROUS>(gre, dmu, ph, smag, k, collect, smagb);
 #pragma unroll
       for (int i = 0; i < Q; ++i) one[i] = R(1);
       om.transpose(ob);
@@ -756,13 +766,15 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
       for (int i = 0; i < Q; ++i) store(i, (R)(m * ((double)one[i] - 1.0)) + ob[i]);
       m_next[n.cell] = SEED ? m + cs.base : m;
       if (POROUS) grad[n.cell] += (double)phib;
+      add_cs();
       return;
     }
   }
-  if constexpr (RR) phib = collide_bulk_rr_vjp<Q, R, POROUS>(g, dmu, ph, k, store);
-  else phib = collide_bulk_vjp<Q, R, POROUS>(g, dmu, ph, k, store);
+  if constexpr (RR) phib = collide_bulk_rr_vjp<Q, R, POROUS>(g, dmu, ph, smag, k, store, smagb);
+  else phib = collide_bulk_vjp<Q, R, POROUS>(g, dmu, ph, smag, k, store, smagb);
   m_next[n.cell] = SEED ? m + cs.base : m;
   if (POROUS) grad[n.cell] += (double)phib;
+  add_cs();
 }
 
 // ---------------------------------------------------------------------------
@@ -903,20 +915,24 @@ __device__ __forceinline__ void wall_collide_vjp(const R g[Q], const R mu[Q], co
 // through t = u_t/|u_t|, the friction velocity (the root of g(U/u_tau) =
 // y_r u_tau/nu, implicit derivative), u+_b (the root of g(u+) = y_b u_tau/nu,
 // or U/u_tau when the reference is the wall cell itself), G(u_tau) and
-// tau_b(G).  An inactive record (|u_t| at or below 1e-300, or a failed solve)
-// is constant: zero adjoint.
+// tau_b(G), and to the wall cell's C_S^2 (C2b) through G and tau_b.  An
+// inactive record (|u_t| at or below 1e-300, or a failed solve) is constant:
+// zero adjoint.
 __device__ __forceinline__ void wall_record_vjp(const WallRec &w, const double u[3], double rho, const double n[3],
-                                                double yr, double yb, bool self, const KArgs &k,
+                                                double yr, double yb, bool self, double C2, const KArgs &k,
                                                 const double tb[3], double utanb, double Gb, double taub,
-                                                double &rhob, double jb[3]) {
+                                                double &rhob, double jb[3], double &C2b) {
   rhob = 0.0;
   jb[0] = jb[1] = jb[2] = 0.0;
+  C2b = 0.0;
   if (!w.active) return;
-  const double nu = k.nu, C2 = k.cs2, inv_E = 1.0 / k.E, kap = k.kappa;
+  const double nu = k.nu, inv_E = 1.0 / k.E, kap = k.kappa;
   const double ut = w.utau, U = w.U;
   const double Gt = Gb + 3.0 * C2 * taub;
   const double sq = sqrt(nu * nu + 4.0 * C2 * ut * ut);
   const double dG = 4.0 * ut / (nu + sq) - 8.0 * C2 * ut * ut * ut / (sq * (nu + sq) * (nu + sq));
+  // G = 2 u_tau^2 / (nu + sq): dG/dC2 = -4 u_tau^4 / (sq (nu + sq)^2); tau_b = 3 (nu + C2 G) + 1/2
+  C2b = 3.0 * w.G * taub - Gt * 4.0 * ut * ut * ut * ut / (sq * (nu + sq) * (nu + sq));
   double utb = Gt * dG, Ub = 0.0;
   if (self) {
     Ub = utanb;  // u_tan = u_tau (U / u_tau) = U
@@ -949,8 +965,8 @@ __global__ __launch_bounds__(256) void k_adjoint_wall(const S *__restrict__ pop,
                                                       const double *__restrict__ m_prev, double *__restrict__ m_next,
                                                       const int *__restrict__ wcell, const int *__restrict__ wref,
                                                       const double *__restrict__ rec, int nwall,
-                                                      double *__restrict__ wadj, KArgs k, int p0, int p1,
-                                                      const double *__restrict__ cnt, double sw) {
+                                                      double *__restrict__ wadj, double *__restrict__ gcs, KArgs k,
+                                                      int p0, int p1, const double *__restrict__ cnt, double sw) {
   using R = typename Store<S>::R;
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nwall) return;
@@ -982,7 +998,8 @@ __global__ __launch_bounds__(256) void k_adjoint_wall(const S *__restrict__ pop,
   ref_velocity<Q, S, ODD, SLIP>(pop, flags, r, k, rho_r, ur);
   const double nn[3] = {rec[WR_NX * M + w], rec[WR_NY * M + w], rec[WR_NZ * M + w]};
   const double yr = rec[WR_YR * M + w], yb = rec[WR_YB * M + w];
-  const WallRec wr = wall_record_of(ur, nn, yr, yb, r == b, k);
+  const double C2 = cs2_of<R>(k, b);
+  const WallRec wr = wall_record_of(ur, nn, yr, yb, r == b, C2, k);
   CellSeed cs{};
   if constexpr (SEED) cs = cell_seed<Q, R>(g, x, p0, p1, cnt, sw, k);
   const R nv[3] = {R(nn[0]), R(nn[1]), R(nn[2])};
@@ -995,8 +1012,10 @@ __global__ __launch_bounds__(256) void k_adjoint_wall(const S *__restrict__ pop,
   wall_collide_vjp<Q, R, RR>(g, dmu, nv, tv, R(wr.utan), R(wr.G), R(wr.tau), k, store, rb);
   m_next[n.cell] = SEED ? m + cs.base : m;
   const double tb[3] = {(double)rb.t[0], (double)rb.t[1], (double)rb.t[2]};
-  double rhob, jb[3];
-  wall_record_vjp(wr, ur, rho_r, nn, yr, yb, r == b, k, tb, (double)rb.utan, (double)rb.G, (double)rb.tau, rhob, jb);
+  double rhob, jb[3], C2b;
+  wall_record_vjp(wr, ur, rho_r, nn, yr, yb, r == b, C2, k, tb, (double)rb.utan, (double)rb.G, (double)rb.tau, rhob,
+                  jb, C2b);
+  if (gcs) gcs[b] += C2b * 2.0 * cs_of<R>(k, b);
   wadj[w] = rhob;
   wadj[M + w] = jb[0];
   wadj[2 * M + w] = jb[1];
@@ -1174,20 +1193,21 @@ static AdjPtrs adj_ptrs(lbm_ctx *ctx, void *lamv) {
 // so the build compiles this file once more per (Q, S) pair with ADJ_PART set,
 // each copy instantiating one pair; the main copy dispatches to them.
 template <int Q, typename S>
-int adjoint_step_qs(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const int *planes) {
+int adjoint_step_qs(lbm_ctx *ctx, void *lamv, void *gradv, void *gcsv, double seed_w, const int *planes) {
   const ATiles t = atiles_of(ctx->ka);
   const AdjPtrs a = adj_ptrs(ctx, lamv);
   auto body = [&]<bool ODD, int SOLID>() {
     using R = typename Store<S>::R;
     R *dev = (R *)a.dev;
     double *grad = (double *)gradv;
+    double *gcs = (double *)gcsv;
     const R *phi = (const R *)ctx->phi;
     // reads the common modes of the later state (the other parity), writes this parity's
     const int p0 = planes ? planes[0] : 0, p1 = planes ? planes[1] : 0;
     const double *cnt = ctx->result + 8 + 3;  // fluid-cell counts of the last objective evaluation
     auto go = [&](auto kern) {
       kern<<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, dev, a.m_other, a.m_cur, phi,
-                                                  grad, ctx->ka, t, p0, p1, cnt, seed_w);
+                                                  grad, gcs, ctx->ka, t, p0, p1, cnt, seed_w);
     };
     auto by_seed = [&]<bool POROUS, bool RR>() {
       // open x faces make x non-periodic, so their domains always have solid links
@@ -1215,7 +1235,7 @@ int adjoint_step_qs(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const 
       const int nw = ctx->nwall, wb = (nw + 255) / 256;
       auto gow = [&](auto kern) {
         kern<<<wb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, dev, a.m_other, a.m_cur, ctx->wcell,
-                                         ctx->wref, ctx->wrec, nw, a.wadj, ctx->ka, p0, p1, cnt, seed_w);
+                                         ctx->wref, ctx->wrec, nw, a.wadj, gcs, ctx->ka, p0, p1, cnt, seed_w);
       };
       constexpr bool SLIP = SOLID == 2;
       if (ctx->ka.rr) {
@@ -1245,9 +1265,9 @@ int adjoint_step_qs(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const 
 
 #define LBM_ADJ_PAIRS(X) X(19, double) X(19, float) X(19, _Float16) X(27, double) X(27, float) X(27, _Float16)
 #define LBM_ADJ_DECL(Q, S) \
-  template int adjoint_step_qs<Q, S>(lbm_ctx *, void *, void *, double, const int *);
+  template int adjoint_step_qs<Q, S>(lbm_ctx *, void *, void *, void *, double, const int *);
 #define LBM_ADJ_EXTERN(Q, S) \
-  extern template int adjoint_step_qs<Q, S>(lbm_ctx *, void *, void *, double, const int *);
+  extern template int adjoint_step_qs<Q, S>(lbm_ctx *, void *, void *, void *, double, const int *);
 
 #if defined(ADJ_PART)
 // one (Q, S) pair per part
@@ -1267,15 +1287,15 @@ LBM_ADJ_DECL(27, _Float16)
 #else
 LBM_ADJ_PAIRS(LBM_ADJ_EXTERN)
 
-int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv, double seed_w, const int *planes) {
+int dev_adjoint_step(lbm_ctx *ctx, void *lamv, void *gradv, void *gcsv, double seed_w, const int *planes) {
   if (ctx->q == 19) {
-    if (ctx->p.storage == LBM_F64) return adjoint_step_qs<19, double>(ctx, lamv, gradv, seed_w, planes);
-    if (ctx->p.storage == LBM_F32DEV) return adjoint_step_qs<19, float>(ctx, lamv, gradv, seed_w, planes);
-    return adjoint_step_qs<19, _Float16>(ctx, lamv, gradv, seed_w, planes);
+    if (ctx->p.storage == LBM_F64) return adjoint_step_qs<19, double>(ctx, lamv, gradv, gcsv, seed_w, planes);
+    if (ctx->p.storage == LBM_F32DEV) return adjoint_step_qs<19, float>(ctx, lamv, gradv, gcsv, seed_w, planes);
+    return adjoint_step_qs<19, _Float16>(ctx, lamv, gradv, gcsv, seed_w, planes);
   }
-  if (ctx->p.storage == LBM_F64) return adjoint_step_qs<27, double>(ctx, lamv, gradv, seed_w, planes);
-  if (ctx->p.storage == LBM_F32DEV) return adjoint_step_qs<27, float>(ctx, lamv, gradv, seed_w, planes);
-  return adjoint_step_qs<27, _Float16>(ctx, lamv, gradv, seed_w, planes);
+  if (ctx->p.storage == LBM_F64) return adjoint_step_qs<27, double>(ctx, lamv, gradv, gcsv, seed_w, planes);
+  if (ctx->p.storage == LBM_F32DEV) return adjoint_step_qs<27, float>(ctx, lamv, gradv, gcsv, seed_w, planes);
+  return adjoint_step_qs<27, _Float16>(ctx, lamv, gradv, gcsv, seed_w, planes);
 }
 
 int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lamv, double w) {

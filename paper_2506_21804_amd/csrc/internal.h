@@ -42,6 +42,7 @@ struct KArgs {
   int per[3];
   double tau0;
   double smag;  // 18 sqrt(2) C_S^2: coefficient of |Pi|/rho under the root of tau_eff
+  double cs;    // C_S (scalar; the per-cell field csf replaces it when set)
   double cs2;   // C_S^2
   double nu;    // (tau0 - 1/2)/3
   double F[3];
@@ -57,6 +58,7 @@ struct KArgs {
   const void *uin;   // [nz] fringe inflow profile, compute type
   const void *lam;   // [nx] fringe blend weight, compute type (0 before the fringe)
   const void *inflow;  // [3][ny nz] inlet velocity, compute type (open_x)
+  const void *csf;     // [N] per-cell Smagorinsky constant C_S, compute type; NULL: C_S^2 = cs2 everywhere
 };
 
 // Adjoint field in caller memory (lbm_adjoint_bytes).  The value of a slot is
@@ -110,6 +112,7 @@ struct lbm_ctx {
   void *pop = nullptr;        // [q][N] stored deviations
   uint8_t *flags = nullptr;   // [N]
   void *phi = nullptr;        // [N] compute type, porous only
+  void *csf = nullptr;        // [N] per-cell C_S, compute type (cs_field only; in force when ka.csf is set)
   void *tables = nullptr;     // [nz] inflow + [nx] fringe weights, compute type
   void *vel = nullptr;        // [3][N] velocity field, compute type (hybrid collision only)
   void *inflow = nullptr;     // [3][ny nz] inlet velocity, compute type (open_x only)
@@ -191,8 +194,13 @@ int dev_layout_from_natural(lbm_ctx *ctx, const void *nat, void *lam);
 // seed of the terminal objective, times w
 int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lam, double w = 1.0);
 // one reverse step; seed_w != 0 also adds seed_w dJ/df of the state held
-// (planes and the fluid-cell counts of the last objective evaluation)
-int dev_adjoint_step(lbm_ctx *ctx, void *lam, void *grad, double seed_w = 0.0, const int *planes = nullptr);
+// (planes and the fluid-cell counts of the last objective evaluation);
+// gcs != NULL also accumulates dJ/dC_S per cell
+int dev_adjoint_step(lbm_ctx *ctx, void *lam, void *grad, void *gcs = nullptr, double seed_w = 0.0,
+                     const int *planes = nullptr);
+// copies a device double [N] C_S field into ctx->csf in the compute type;
+// *bad != 0 when an entry is negative or not finite (synchronises)
+int dev_set_cs(lbm_ctx *ctx, const double *cs, int *bad);
 int dev_fill(lbm_ctx *ctx, void *ptr, size_t bytes);  // zero fill with a kernel
 int dev_write_header(lbm_ctx *ctx, void *dst);
 

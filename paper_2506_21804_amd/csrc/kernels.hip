@@ -171,7 +171,7 @@ __device__ __forceinline__ void fd_strain(const Nb &n, const uint8_t *__restrict
 // sigma Pi^neq - (1 - sigma) 2 rho c_s^2 tau S^FD, the third-order part keeps
 // the factor sigma, the first-order part (-F/2) is kept whole.
 template <int Q, typename R, bool POROUS, bool RR, bool HYB = false>
-__device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k, const R *Sfd = nullptr) {
+__device__ __forceinline__ bool collide_bulk(R g[Q], R phi, R smag, const KArgs &k, const R *Sfd = nullptr) {
   constexpr int H = Lat<Q>::H;
   // moments from pair sums s = g_i + g_ibar (even moments) and differences d = g_i - g_ibar (odd)
   R drho = g[0], jx = R(0), jy = R(0), jz = R(0);
@@ -206,7 +206,7 @@ __device__ __forceinline__ bool collide_bulk(R g[Q], R phi, const KArgs &k, cons
   const R pyz = myz - rho * uy * uz;
   const R pn = sqrt(pxx * pxx + pyy * pyy + pzz * pzz + R(2) * (pxy * pxy + pxz * pxz + pyz * pyz));
   const R tau0 = R(k.tau0);
-  const R tau = R(0.5) * (tau0 + sqrt(tau0 * tau0 + R(k.smag) * pn * ir));
+  const R tau = R(0.5) * (tau0 + sqrt(tau0 * tau0 + smag * pn * ir));
   const R om = R(1) / tau;
   const R c1 = R(1) - om, c2 = R(1) - R(0.5) * om;
   const R uu = ux * ux + uy * uy + uz * uz;
@@ -478,7 +478,7 @@ __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename St
     const R ph = POROUS ? phi[n.cell] : R(1);
     R Sfd[6];
     if constexpr (HYB) fd_strain<R>(n, flags, k, Sfd);
-    if (!collide_bulk<Q, R, POROUS, RR, HYB>(g, ph, k, Sfd)) atomicOr(errflag, 1);
+    if (!collide_bulk<Q, R, POROUS, RR, HYB>(g, ph, smag_of<R>(k, n.cell), k, Sfd)) atomicOr(errflag, 1);
   }
   // the outlet plane is left out of the fringe
   if (!OPEN || !(fl & FL_OUTLET)) fringe_blend<Q, R>(g, x, z, k);
@@ -598,7 +598,8 @@ __device__ __forceinline__ void wall_record(const S *__restrict__ pop, const uin
   ref_velocity<Q, S, ODD, SLIP>(pop, flags, r, k, rho, u);
   const size_t M = (size_t)nwall;
   const double n[3] = {rec[WR_NX * M + w], rec[WR_NY * M + w], rec[WR_NZ * M + w]};
-  const WallRec wr = wall_record_of(u, n, rec[WR_YR * M + w], rec[WR_YB * M + w], r == b, k);
+  const WallRec wr =
+      wall_record_of(u, n, rec[WR_YR * M + w], rec[WR_YB * M + w], r == b, cs2_of<typename Store<S>::R>(k, b), k);
   if (wr.fail) atomicOr(errflag, 2);
   rec[WR_TX * M + w] = wr.t[0];
   rec[WR_TY * M + w] = wr.t[1];
@@ -950,6 +951,20 @@ __global__ void k_fill_zero(uint32_t *__restrict__ p, size_t n4) {
     p[i] = 0u;
 }
 
+// Per-cell C_S field: dst == nullptr checks the FP64 input (any negative or
+// non-finite entry sets *bad), otherwise converts it to the compute type.
+template <typename R>
+__global__ void k_set_cs(R *__restrict__ dst, const double *__restrict__ src, size_t n, int *__restrict__ bad) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double v = src[i];
+    if (!dst) {
+      if (!(v >= 0.0) || isinf(v)) atomicOr(bad, 1);
+    } else {
+      dst[i] = (R)v;
+    }
+  }
+}
+
 __global__ void k_header(long long *__restrict__ h, long long steps, long long q, long long N, long long storage) {
   if (threadIdx.x == 0) {
     h[0] = 0x4c424d5354415445LL;  // "LBMSTATE"
@@ -1265,6 +1280,33 @@ int dev_fill(lbm_ctx *ctx, void *ptr, size_t bytes) {
   const unsigned grid = (unsigned)std::min<size_t>(want, 65536);
   k_fill_zero<<<grid, 256, 0, ctx->stream>>>((uint32_t *)ptr, n4);
   return check_launch(ctx, "k_fill_zero");
+}
+
+int dev_set_cs(lbm_ctx *ctx, const double *cs, int *bad) {
+  // the flag lives in the last slot of the workspace's result block (unused by the reductions)
+  int *flag = (int *)(ctx->result + 31);
+  int rc = dev_fill(ctx, flag, sizeof(int));
+  if (rc != LBM_OK) return rc;
+  const size_t n = (size_t)ctx->N;
+  const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+  // check the whole field first, so that a rejected one leaves the field in force untouched
+  auto pass = [&](bool write) {
+    if (ctx->p.storage == LBM_F64)
+      k_set_cs<double><<<grid, 256, 0, ctx->stream>>>(write ? (double *)ctx->csf : nullptr, cs, n, flag);
+    else
+      k_set_cs<float><<<grid, 256, 0, ctx->stream>>>(write ? (float *)ctx->csf : nullptr, cs, n, flag);
+    return check_launch(ctx, "k_set_cs");
+  };
+  if ((rc = pass(false)) != LBM_OK) return rc;
+  hipError_t e = hipMemcpyAsync(bad, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reading the C_S check flag");
+  e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  if (*bad) return LBM_OK;
+  if ((rc = pass(true)) != LBM_OK) return rc;
+  e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  return LBM_OK;
 }
 
 int dev_write_header(lbm_ctx *ctx, void *dst) {

@@ -115,6 +115,33 @@ __device__ __forceinline__ R dot3(int cx, int cy, int cz, R x, R y, R z) {
   return s;
 }
 
+// Smagorinsky coefficient of the cell: 18 sqrt(2) C_S^2 multiplies |Pi|/rho
+// under the root of tau_eff (Sec. 2.3).  C_S comes from the cell's field when
+// the context holds one (the dynamics read it per cell), else the scalar.
+constexpr double SMAG_COEF = 25.455844122715710878430397035774;  // 18 sqrt(2)
+template <typename R>
+__device__ __forceinline__ R smag_of(const KArgs &k, int cell) {
+  if (k.csf) {
+    const R c = static_cast<const R *>(k.csf)[cell];
+    return R(SMAG_COEF) * c * c;
+  }
+  return R(k.smag);
+}
+// C_S of the cell in FP64 (gradients with respect to C_S).
+template <typename R>
+__device__ __forceinline__ double cs_of(const KArgs &k, int cell) {
+  return k.csf ? (double)static_cast<const R *>(k.csf)[cell] : k.cs;
+}
+// C_S^2 of the cell in FP64 (wall records).
+template <typename R>
+__device__ __forceinline__ double cs2_of(const KArgs &k, int cell) {
+  if (k.csf) {
+    const double c = (double)static_cast<const R *>(k.csf)[cell];
+    return c * c;
+  }
+  return k.cs2;
+}
+
 // Stored value type -> compute type.
 template <typename S>
 struct Store;

@@ -80,9 +80,10 @@ struct WallRec {
 
 // The record from the reference cell's velocity u and the unit normal n;
 // yr, yb the wall distances of the reference and the wall cell; self: the
-// reference cell is the wall cell itself (u+_b = U/u_tau).
+// reference cell is the wall cell itself (u+_b = U/u_tau); C2 the wall cell's
+// C_S^2.
 __device__ __forceinline__ WallRec wall_record_of(const double u[3], const double n[3], double yr, double yb,
-                                                  bool self, const KArgs &k) {
+                                                  bool self, double C2, const KArgs &k) {
   WallRec w;
   const double un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
   const double tx = u[0] - un * n[0], ty = u[1] - un * n[1], tz = u[2] - un * n[2];
@@ -163,8 +164,8 @@ __device__ __forceinline__ WallRec wall_record_of(const double u[3], const doubl
       w.t[0] = tx / U;
       w.t[1] = ty / U;
       w.t[2] = tz / U;
-      w.G = 2.0 * ut * ut / (nu + sqrt(nu * nu + 4.0 * k.cs2 * ut * ut));
-      w.tau = 3.0 * (nu + k.cs2 * w.G) + 0.5;
+      w.G = 2.0 * ut * ut / (nu + sqrt(nu * nu + 4.0 * C2 * ut * ut));
+      w.tau = 3.0 * (nu + C2 * w.G) + 0.5;
     }
   }
   return w;
