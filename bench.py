@@ -19,8 +19,10 @@ Workloads: channel (default), channel16, urban, urban16, big, big16 (1024^3
 urban-style domain, the largest that fits one GPU), urban_slip, urban_slip16
 (full-slip side and top faces), cavity, cavity16, tgv, adjoint (reverse /
 forward step time), precision (FP32 and FP16 storage against FP64 on the
-same GPU), wall_balance (the channel's mean modeled wall stress against the
-body force at statistical steady state; --spinup, --steps, --sample-every).
+same GPU), cavity_sweep (the cavity at one GPU's share of each problem of
+the strong-scaling table, 12 M to 762 M cells), wall_balance (the channel's
+mean modeled wall stress against the body force at statistical steady state;
+--spinup, --steps, --sample-every).
 """
 from __future__ import annotations
 
@@ -218,6 +220,8 @@ def main():
         return bench_precision(args, torch, lbm)
     if args.workload == "wall_balance":
         return bench_wall_balance(args, torch, lbm)
+    if args.workload == "cavity_sweep":
+        return bench_cavity_sweep(args, torch, lbm)
     case, storage, wname = make_case(args.workload)
     if args.collision == "rr3":
         case.collision = 1
@@ -465,9 +469,10 @@ def bench_wall_balance(args, torch, lbm):
         done += k
         print(f"[bench] wall balance spin-up {done}/{args.spinup} steps ({time.perf_counter() - t0:.0f} s)",
               file=sys.stderr, flush=True)
-    samples = []
+    samples, mom = [], [float(lat.diagnostics()[1])]
     for s in range(0, args.steps, args.sample_every):
         lat.step(args.sample_every)
+        mom.append(float(lat.diagnostics()[1]))
         rho, _ = lat.moments()
         r = lbm.lbm_wall_records(lat.ctx)
         rw = rho.double().reshape(-1)[torch.as_tensor(rec_cells.astype(np.int64), device="cuda")].cpu().numpy()
@@ -477,6 +482,14 @@ def bench_wall_balance(args, torch, lbm):
                   f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
     sm = np.array(samples) / (F * h)
     half = len(sm) // 2
+    # the momentum the walls actually take out: each step the forcing adds F
+    # per fluid cell to sum c f, so the walls remove F V - dP/dt; over the
+    # nwall wall cells this is a mean wall stress to compare with F h
+    V = case.ncells if case.mask is None else int(np.count_nonzero(case.mask))
+    P = np.array(mom)
+
+    def budget(a, b):
+        return (F * V - (P[b] - P[a]) / ((b - a) * args.sample_every)) / (nwall * F * h)
     out = {"metric": "wall-law momentum balance <rho u_tau^2> / (F h) at statistical steady state",
            "value": round(float(sm.mean()), 4), "unit": "ratio", "n_gpus": 1, "steps": args.steps,
            "warmup": args.spinup, "ms_per_step": None, "higher_is_better": None, "scaling": "weak",
@@ -484,8 +497,67 @@ def bench_wall_balance(args, torch, lbm):
            "config": {"workload": "channel384x192x192_d3q27_smag_wallmodel", "wall_cells": nwall,
                       "sample_every": args.sample_every},
            "halves": [round(float(sm[:half].mean()), 4), round(float(sm[half:].mean()), 4)],
+           "removed_by_walls": round(float(budget(0, len(sm))), 4),
+           "removed_by_walls_halves": [round(float(budget(0, half)), 4), round(float(budget(half, len(sm))), 4)],
+           "mean_velocity": [round(float(P[0] / V), 6), round(float(P[-1] / V), 6)],
            "min": round(float(sm.min()), 4), "max": round(float(sm.max()), 4), "samples": len(sm),
            "mass": float(lat.diagnostics()[0])}
+    print(json.dumps(out), flush=True)
+
+
+def bench_cavity_sweep(args, torch, lbm):
+    """The lid-driven cavity (D3Q19, FP32 storage, BGK, C_S = 0.1) at one
+    GPU's share of each problem of the paper's strong-scaling table (Sec. 3.1:
+    575^3 to 1449^3 on 4 to 16 GPUs), taken as an n x n x ceil(n/G) slab of
+    the cube: 12 M to 762 M cells per GPU.  Each shape runs on its own as a
+    closed box (walls on all faces, lid on top; the halo exchange of a
+    multi-GPU run is not part of it) for about half a second of steps.
+    Reports MLUPS and the bulk kernel's fraction of the HBM peak per shape;
+    value is the median MLUPS over the shapes."""
+    from paper_2506_21804_amd import inputs as I
+    import numpy as np
+    rows = []
+    for n in (575, 725, 913, 1150, 1449):
+        for G in (4, 8, 16):
+            shape = (n, n, -(-n // G))
+            case = I.cavity(shape, q=19)
+            N = case.ncells
+            t0 = time.perf_counter()
+            lat = lbm.Lattice(case, storage="f32")
+            t_init = time.perf_counter() - t0
+            steps = int(min(300, max(20, round(0.5 / (N / 3.0e10)))))
+            lat.step(10)
+            lat.sync()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(lat.stream)
+            lat.step(steps)
+            ev1.record(lat.stream)
+            lat.sync()
+            ms = ev0.elapsed_time(ev1) / steps
+            lbm.lbm_profile(lat.ctx, True)
+            lat.step(10)
+            lbm.lbm_profile(lat.ctx, False)
+            kms, kcount = lbm.lbm_profile_read(lat.ctx)
+            lat.sync()
+            k2_ms = kms[1] / max(kcount[1], 1)
+            k2_bytes = N * 1 + N * 2 * 19 * 4
+            frac = k2_bytes / (k2_ms * 1e-3) / 1e9 / PEAK_HBM_GBS
+            finite = bool(np.isfinite(lat.diagnostics()[0]))
+            del lat
+            torch.cuda.empty_cache()
+            rows.append({"cube": n, "gpus": G, "shape": list(shape), "cells": N, "steps": steps,
+                         "ms_per_step": round(ms, 4), "mlups": round(N / (ms * 1e-3) / 1e6, 1),
+                         "bulk_hbm_frac": round(frac, 4), "finite": finite})
+            print(f"[bench] cavity {n}^3 / {G}: {shape} {N / 1e6:.1f} M cells, {ms:.3f} ms/step, "
+                  f"{rows[-1]['mlups']:.0f} MLUPS, bulk {frac:.3f} of peak (init {t_init:.1f} s)",
+                  file=sys.stderr, flush=True)
+    m = [r["mlups"] for r in rows]
+    out = {"metric": "MLUPS (million lattice-cell updates per second) per GPU", "value": round(float(np.median(m)), 1),
+           "unit": "MLUPS", "n_gpus": 1, "steps": None, "warmup": 10, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "strong", "vs_baseline": None, "dtype": "f32 (fp32 deviation storage)", "data": "synthetic",
+           "config": {"workload": "cavity_strong_scaling_shares_d3q19_smag_lid", "lattice": "D3Q19",
+                      "storage": "f32", "collision": "bgk"},
+           "min": min(m), "max": max(m), "shapes": rows}
     print(json.dumps(out), flush=True)
 
 

@@ -8,10 +8,13 @@ Per-cell error e = |g - g_ref| / max(|g_ref|, 1e-3 max_k |g_ref,k|).
  - GPU FP64 storage against the oracle's exact derivative: e <= 1e-9;
  - GPU FP32 storage against the exact derivative: e <= 1e-4 (the target);
  - both are also reported against the central differences.  These differ
-   from the exact derivative by the O(h^2) truncation of the 400-step map at
-   h = 1e-3: 3e-4 per cell at the median, 4.2e-3 at the smallest derivative
-   of the sixteen (2e-10 against 3.3e-9 at the largest), 2.5e-4 of the
-   largest |dJ/dphi| at worst; the file check bounds the latter by 1e-3.
+   from the exact derivative by about 1e-13 in absolute terms: 3e-4 per cell
+   at the median, 4.2e-3 at the smallest derivative of the sixteen (2e-10
+   against 3.3e-9 at the largest), 2.5e-4 of the largest |dJ/dphi| at worst;
+   the file check bounds the latter by 1e-3.  At that smallest one the
+   difference is 8.3e-13 at h = 1e-3, 1.1e-13 at 2e-3 and 3.2e-13 at 4e-3:
+   below 2e-3 the rounding of J (a few 1e-16) over 2h dominates, above it
+   the O(h^2) truncation.
 """
 import json
 import os
