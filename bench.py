@@ -202,6 +202,9 @@ def main():
                     help="with --collision rr3: weight 1 - sigma of the finite-difference strain (hybrid)")
     ap.add_argument("--spinup", type=int, default=60000, help="wall_balance workload: steps before sampling")
     ap.add_argument("--sample-every", type=int, default=200, help="wall_balance workload: steps between samples")
+    ap.add_argument("--no-spread", action="store_true",
+                    help="allocate the workspace and adjoint buffers as one plain allocation each instead of with "
+                         "their arrays spread in physical memory (lbm_workspace_alloc / lbm_adjoint_alloc)")
     ap.add_argument("--profile-steps", type=int, default=2000,
                     help="precision workload: second horizon, with mean-profile errors")
     args = ap.parse_args()
@@ -233,7 +236,8 @@ def main():
     if args.workload == "adjoint":
         return bench_adjoint(args, torch, lbm, case, storage, wname)
 
-    lat = lbm.Lattice(case, storage=storage, wall_dist=None if case.wall_dist is None else "case")
+    spread = not args.no_spread
+    lat = lbm.Lattice(case, storage=storage, wall_dist=None if case.wall_dist is None else "case", spread=spread)
     N = case.ncells
     nfluid = case.nfluid()
     nwall = lbm.lbm_wall_count(lat.ctx)
@@ -332,7 +336,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "cells": N, "fluid_cells": nfluid, "wall_cells": nwall, "lattice": f"D3Q{q}",
                    "storage": storage, "collision": args.collision,
-                   "fd_weight": fdw},
+                   "fd_weight": fdw, "workspace": "spread" if spread else "plain"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": "k_bulk", "avg_launch_ms": round(k2_ms, 5), "alg_bytes_per_launch": k2_bytes},
@@ -359,7 +363,7 @@ def main():
         # step-time ratio on the porosity workload, and the FP16-storage
         # moment error against FP32 storage on this channel
         print("[bench] adjoint/forward ratio (porous channel 128^3, FP32)", file=sys.stderr, flush=True)
-        out["adjoint"] = adjoint_ratio(torch, lbm, make_case("adjoint")[0], "f32", 300, 20)
+        out["adjoint"] = adjoint_ratio(torch, lbm, make_case("adjoint")[0], "f32", 300, 20, spread=spread)
         print("[bench] FP16 vs FP32 storage (channel, 100 steps)", file=sys.stderr, flush=True)
         out["fp16_vs_fp32"] = fp16_vs_fp32(torch, lbm)
     if not args.no_cpu_baseline:
@@ -523,7 +527,7 @@ def bench_cavity_sweep(args, torch, lbm):
             case = I.cavity(shape, q=19)
             N = case.ncells
             t0 = time.perf_counter()
-            lat = lbm.Lattice(case, storage="f32")
+            lat = lbm.Lattice(case, storage="f32", spread=not args.no_spread)
             t_init = time.perf_counter() - t0
             steps = int(min(300, max(20, round(0.5 / (N / 3.0e10)))))
             lat.step(10)
@@ -556,7 +560,7 @@ def bench_cavity_sweep(args, torch, lbm):
            "unit": "MLUPS", "n_gpus": 1, "steps": None, "warmup": 10, "ms_per_step": None, "higher_is_better": True,
            "scaling": "strong", "vs_baseline": None, "dtype": "f32 (fp32 deviation storage)", "data": "synthetic",
            "config": {"workload": "cavity_strong_scaling_shares_d3q19_smag_lid", "lattice": "D3Q19",
-                      "storage": "f32", "collision": "bgk"},
+                      "storage": "f32", "collision": "bgk", "workspace": "plain" if args.no_spread else "spread"},
            "min": min(m), "max": max(m), "shapes": rows}
     print(json.dumps(out), flush=True)
 
@@ -564,7 +568,7 @@ def bench_cavity_sweep(args, torch, lbm):
 def bench_adjoint(args, torch, lbm, case, storage, wname):
     """Forward step vs hand-written reverse step on the porosity workload,
     and one full checkpointed gradient."""
-    r = adjoint_ratio(torch, lbm, case, storage, args.steps, args.warmup)
+    r = adjoint_ratio(torch, lbm, case, storage, args.steps, args.warmup, spread=not args.no_spread)
     out = {
         "metric": "adjoint/forward step time ratio",
         "value": r["ratio"],
@@ -578,12 +582,12 @@ def bench_adjoint(args, torch, lbm, case, storage, wname):
     print(json.dumps(out), flush=True)
 
 
-def adjoint_ratio(torch, lbm, case, storage, K, warmup):
+def adjoint_ratio(torch, lbm, case, storage, K, warmup, spread=True):
     """Median of 5 repeats of K forward steps and of K reverse steps (half at
     each parity) on the porosity workload, their ratio, and one full
     checkpointed gradient (terminal and time-averaged objective, T = 400,
     20 snapshots)."""
-    lat = lbm.Lattice(case, storage=storage)
+    lat = lbm.Lattice(case, storage=storage, spread=spread)
     N = case.ncells
     planes = case.extra["planes"]
     lat.step(warmup)
@@ -592,7 +596,7 @@ def adjoint_ratio(torch, lbm, case, storage, K, warmup):
     e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     torch.cuda.synchronize()
     fwd, adj = [], []
-    lam = lat.new_adjoint()
+    lam = lat.new_adjoint(spread=spread)
     grad = lat.new_gradient()
     for _ in range(5):
         e[0].record(stream)
@@ -630,6 +634,7 @@ def adjoint_ratio(torch, lbm, case, storage, K, warmup):
         "ratio": round(adj_ms / fwd_ms, 3),
         "workload": "porous_channel128_d3q19_adjoint",
         "storage": storage,
+        "buffers": "spread" if spread else "plain",
         "forward_ms_per_step": round(fwd_ms, 5),
         "forward_mlups": round(N / (fwd_ms * 1e-3) / 1e6, 1),
         "adjoint_ms_per_step": round(adj_ms, 5),

@@ -326,6 +326,34 @@ int lbm_stream_probe(lbm_ctx *ctx, int n, double *ms_per_launch);
 int lbm_slot_map(const lbm_params *p, const uint8_t *mask, int parity, long long *read, long long *write);
 
 const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* Buffers whose streamed arrays lie far apart in physical memory (for
+ * callers that can allocate; any buffer of the right size also works).  The
+ * step streams q direction arrays at once; on MI355X that pattern runs at
+ * about 65 % of the HBM peak when the arrays are physically adjacent, as one
+ * plain allocation places them, and at 75-80 % once they are 3-4 GiB or more
+ * apart physically.  These calls cut the buffer into pieces about one array
+ * long (whole 2 MiB pages), create each piece as its own physical allocation
+ * (virtual memory API) with a temporary spacer allocation after it so that
+ * the next lands about 4 GiB further on, release the spacers, and map the
+ * pieces back to back into one virtual range: the buffer has the ordinary
+ * layout and holds its own size rounded up to whole pieces, but needs up to
+ * (q - 1) x 4 GiB of free device memory while it is made.  Arrays of 4 GiB
+ * or more are left in one allocation.  Spacers that cannot be made are
+ * skipped (the buffer is as correct, possibly slower).
+ *  lbm_workspace_alloc: a workspace for lbm_init with these arguments
+ *    (*bytes = lbm_workspace_bytes(p, mask, porous)), on the current device,
+ *    256-byte aligned, its population arrays spread.
+ *  lbm_adjoint_alloc: an adjoint buffer of lbm_adjoint_bytes(ctx) with its
+ *    common-mode and deviation arrays spread, zero-filled (synchronous).
+ *  lbm_spread_free: releases a buffer of either call (LBM_EINVAL for any
+ *    other pointer) after synchronising the device.  A workspace is freed
+ *    only after lbm_free of its context.
+ * Errors: LBM_EINVAL (invalid parameters, no virtual memory management on
+ * the device), LBM_ESIZE (out of device memory), LBM_EHIP. */
+int lbm_workspace_alloc(const lbm_params *p, const uint8_t *mask, int porous, void **workspace, size_t *bytes);
+int lbm_adjoint_alloc(const lbm_ctx *ctx, void **lambda, size_t *bytes);
+int lbm_spread_free(void *ptr);
 /* Releases the context (host memory only; the workspace stays the caller's). */
 void lbm_free(lbm_ctx *ctx);
 

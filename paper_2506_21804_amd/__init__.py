@@ -22,6 +22,7 @@ __all__ = [
     "lbm_gradient", "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
     "lbm_set_inflow_vortices", "lbm_gradient_mean", "lbm_stream_probe", "lbm_slot_map", "lbm_last_error",
     "lbm_set_smagorinsky", "lbm_adjoint_step_cs", "lbm_gradient_cs",
+    "lbm_workspace_alloc", "lbm_adjoint_alloc", "lbm_spread_free", "SpreadBuffer",
     "lbm_free", "params_for", "Lattice", "D3Q19", "D3Q27", "F64", "F32DEV", "F16DEV",
 ]
 
@@ -113,6 +114,9 @@ def load():
         "lbm_set_smagorinsky": (i, [vp, vp]),
         "lbm_adjoint_step_cs": (i, [vp, vp, vp, vp]),
         "lbm_gradient_cs": (i, [vp, i, vp, vp, i, vp, vp, vp, i, C.POINTER(d), C.POINTER(ll)]),
+        "lbm_workspace_alloc": (i, [C.POINTER(Params), vp, i, C.POINTER(vp), C.POINTER(sz)]),
+        "lbm_adjoint_alloc": (i, [vp, C.POINTER(vp), C.POINTER(sz)]),
+        "lbm_spread_free": (i, [vp]),
         "lbm_last_error": (C.c_char_p, [vp]),
         "lbm_free": (None, [vp]),
     }
@@ -132,7 +136,8 @@ def exported_symbols():
             "lbm_adjoint_step", "lbm_adjoint_to_natural", "lbm_adjoint_from_natural", "lbm_gradient",
             "lbm_revolve_cost", "lbm_wall_count", "lbm_wall_records", "lbm_profile", "lbm_profile_read",
             "lbm_set_inflow_vortices", "lbm_gradient_mean", "lbm_stream_probe", "lbm_slot_map",
-            "lbm_set_smagorinsky", "lbm_adjoint_step_cs", "lbm_gradient_cs", "lbm_last_error", "lbm_free"]
+            "lbm_set_smagorinsky", "lbm_adjoint_step_cs", "lbm_gradient_cs", "lbm_workspace_alloc",
+            "lbm_adjoint_alloc", "lbm_spread_free", "lbm_last_error", "lbm_free"]
 
 
 def _dptr(t):
@@ -444,6 +449,66 @@ def params_for(case, storage="f64", stream=None, cs_field=False) -> Params:
                        slip=getattr(case, "slip", 0), cs_field=int(bool(cs_field)), stream=stream)
 
 
+class SpreadBuffer:
+    """Device buffer of lbm_workspace_alloc / lbm_adjoint_alloc: its arrays
+    lie far apart in physical memory.  Offers the parts of a torch tensor the
+    wrappers here use (data_ptr, numel, ...); released by free() or when
+    collected."""
+    is_cuda = True
+
+    def __init__(self, ptr: int, nbytes: int):
+        import torch
+        self._ptr, self._n, self.dtype = int(ptr), int(nbytes), torch.uint8
+
+    def data_ptr(self):
+        if not self._ptr:
+            raise ValueError("buffer already freed")
+        return self._ptr
+
+    def is_contiguous(self):
+        return True
+
+    def numel(self):
+        return self._n
+
+    def element_size(self):
+        return 1
+
+    def free(self):
+        if self._ptr:
+            ptr, self._ptr = self._ptr, 0
+            rc = load().lbm_spread_free(C.c_void_p(ptr))
+            if rc != OK:
+                raise LbmError(rc, load().lbm_last_error(None).decode())
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def lbm_workspace_alloc(p: Params, mask=None, porous=False) -> SpreadBuffer:
+    keep = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    ptr, nb = C.c_void_p(), C.c_size_t()
+    rc = load().lbm_workspace_alloc(C.byref(p), _hptr(keep), int(bool(porous)), C.byref(ptr), C.byref(nb))
+    if rc != OK:
+        raise LbmError(rc, load().lbm_last_error(None).decode())
+    return SpreadBuffer(ptr.value, nb.value)
+
+
+def lbm_adjoint_alloc(ctx) -> SpreadBuffer:
+    ptr, nb = C.c_void_p(), C.c_size_t()
+    rc = load().lbm_adjoint_alloc(ctx, C.byref(ptr), C.byref(nb))
+    if rc != OK:
+        raise LbmError(rc, load().lbm_last_error(None).decode())
+    return SpreadBuffer(ptr.value, nb.value)
+
+
+def lbm_spread_free(buf: SpreadBuffer):
+    buf.free()
+
+
 def lbm_last_error(ctx) -> str:
     return load().lbm_last_error(ctx).decode()
 
@@ -461,7 +526,7 @@ class Lattice:
     ``storage`` one of "f64", "f32", "f16".  rho0/u0 of the case are uploaded
     to the device as float64 for initialisation and then released."""
 
-    def __init__(self, case, storage="f64", stream=None, wall_dist="case", cs_field=False):
+    def __init__(self, case, storage="f64", stream=None, wall_dist="case", cs_field=False, spread=False):
         import torch
         self.torch = torch
         if stream is None:
@@ -474,10 +539,16 @@ class Lattice:
         self.rdtype = torch.float64 if self.storage == F64 else torch.float32
         self.p = params_for(case, storage=self.storage, stream=stream.cuda_stream, cs_field=cs_field)
         porous = case.porosity is not None
-        nbytes = lbm_workspace_bytes(self.p, case.mask, porous)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
-        off = (-self.workspace.data_ptr()) % 256
-        self.ws = self.workspace[off:off + nbytes]
+        self.spread = bool(spread)
+        if self.spread:
+            # population arrays spread in physical memory (lbm_workspace_alloc)
+            self.workspace = lbm_workspace_alloc(self.p, case.mask, porous)
+            self.ws = self.workspace
+        else:
+            nbytes = lbm_workspace_bytes(self.p, case.mask, porous)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            off = (-self.workspace.data_ptr()) % 256
+            self.ws = self.workspace[off:off + nbytes]
         dev = torch.device("cuda")
 
         def to_dev(a):
@@ -560,9 +631,12 @@ class Lattice:
     def objective(self, planes):
         return lbm_objective(self.ctx, planes)
 
-    def new_adjoint(self):
+    def new_adjoint(self, spread=False):
         """Buffer for an adjoint field in the library's in-memory form
-        (read it in natural order with lbm_adjoint_to_natural)."""
+        (read it in natural order with lbm_adjoint_to_natural); spread=True
+        places its arrays apart in physical memory (lbm_adjoint_alloc)."""
+        if spread:
+            return lbm_adjoint_alloc(self.ctx)
         return self.torch.zeros(lbm_adjoint_bytes(self.ctx), dtype=self.torch.uint8, device="cuda")
 
     def new_natural(self):

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm_hip.so")
-SOURCES = ["abi.cpp", "geometry.cpp", "revolve.cpp", "kernels.hip", "adjoint.hip"]
+SOURCES = ["abi.cpp", "geometry.cpp", "revolve.cpp", "spread.cpp", "kernels.hip", "adjoint.hip"]
 # adjoint.hip is compiled once more per (lattice, storage) pair, each copy
 # holding that pair's adjoint kernels (ADJ_PART), so that they build in parallel
 ADJOINT_PARTS = 6

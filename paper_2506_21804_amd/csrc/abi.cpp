@@ -814,6 +814,44 @@ int lbm_wall_records(lbm_ctx *ctx, int *cell, int *ref, double *normal, double *
 
 const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err.c_str() : g_static_error.c_str(); }
 
+int lbm_workspace_alloc(const lbm_params *p, const uint8_t *mask, int porous, void **workspace, size_t *bytes) {
+  if (!workspace || !bytes) return set_err(nullptr, LBM_EINVAL, "null output pointer");
+  *workspace = nullptr;
+  *bytes = 0;
+  const size_t need = lbm_workspace_bytes(p, mask, porous);
+  if (need == 0) return LBM_EINVAL;  // lbm_workspace_bytes left the message
+  const size_t N = (size_t)p->nx * p->ny * p->nz;
+  std::string msg;
+  const int rc = spread_alloc(need, 0, N * storage_bytes(p->storage), p->lattice, workspace, msg);
+  if (rc != LBM_OK) return set_err(nullptr, rc, msg);
+  *bytes = need;
+  return LBM_OK;
+}
+
+int lbm_adjoint_alloc(const lbm_ctx *ctx, void **lambda, size_t *bytes) {
+  if (!ctx || !lambda || !bytes) return set_err(nullptr, LBM_EINVAL, "null argument");
+  *lambda = nullptr;
+  *bytes = 0;
+  const size_t db = ctx->p.storage == LBM_F64 ? 8 : 4;
+  const AdjLayout L = adj_layout(ctx->N, ctx->q, db, ctx->nwall);
+  std::string msg;
+  const int rc = spread_alloc(L.bytes, L.d_off, (size_t)ctx->N * db, ctx->q, lambda, msg);
+  if (rc != LBM_OK) return set_err(nullptr, rc, msg);
+  const hipError_t e = hipMemset(*lambda, 0, L.bytes);
+  if (e != hipSuccess) {
+    (void)spread_free(*lambda);
+    *lambda = nullptr;
+    return set_err(nullptr, LBM_EHIP, std::string("hipMemset of the adjoint buffer: ") + hipGetErrorString(e));
+  }
+  *bytes = L.bytes;
+  return LBM_OK;
+}
+
+int lbm_spread_free(void *ptr) {
+  if (spread_free(ptr) != LBM_OK) return set_err(nullptr, LBM_EINVAL, "not a buffer of lbm_workspace_alloc / lbm_adjoint_alloc");
+  return LBM_OK;
+}
+
 int lbm_profile(lbm_ctx *ctx, int enable) {
   if (!ctx) return LBM_EINVAL;
   if (enable && !ctx->timers) {

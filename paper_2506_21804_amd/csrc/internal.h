@@ -198,6 +198,10 @@ int dev_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lam, double w = 1.
 // gcs != NULL also accumulates dJ/dC_S per cell
 int dev_adjoint_step(lbm_ctx *ctx, void *lam, void *grad, void *gcs = nullptr, double seed_w = 0.0,
                      const int *planes = nullptr);
+// device buffer of `bytes` whose count arrays [offset + k stride, + stride)
+// lie far apart in physical memory, mapped back to back (spread.cpp)
+int spread_alloc(size_t bytes, size_t offset, size_t stride, int count, void **out, std::string &msg);
+int spread_free(void *ptr);
 // copies a device double [N] C_S field into ctx->csf in the compute type;
 // *bad != 0 when an entry is negative or not finite (synchronises)
 int dev_set_cs(lbm_ctx *ctx, const double *cs, int *bad);
