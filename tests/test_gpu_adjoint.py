@@ -180,11 +180,17 @@ def _fd_gradient(case, planes, T, cells, h=1e-3):
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_gradient_vs_central_differences(gpu, storage):
-    """GPU gradient after 100 steps vs FP64 central differences of the oracle.
-    FP64 storage: every sampled cell within 1e-4 of its own derivative (floor
-    1e-3 of the largest).  FP32 storage: within 1e-4 of the gradient's
-    max-norm; per cell it is reported (FP32 rounding of the trajectory moves
-    the smallest sampled derivatives by about 1e-4 of themselves)."""
+    """GPU gradient after 100 steps vs the oracle's exact (dual-number)
+    derivative and its FP64 central differences, per sampled cell relative to
+    max(|dJ/dphi|, 1e-3 of the largest).  FP64 storage: within 1e-10 of the
+    exact derivative and 1e-4 of the central differences.  FP32 storage:
+    within 1e-5 of the exact derivatives' max-norm, and per cell within
+    2e-4.  The FP32 run's smallest sampled derivative (1.6 % of the largest)
+    is off by 1.35e-4 of itself: the exact derivative along the FP32
+    trajectory already differs from the FP64 one by about that much there,
+    and the FP32 adjoint arithmetic adds a similar amount (measured split);
+    at the full porous-channel size every sampled cell meets 1e-4
+    (test_gpu_c4_gradient.py)."""
     case = _case((32, 24, 16))
     planes = (4, 28)
     T = 100
@@ -200,11 +206,24 @@ def test_gradient_vs_central_differences(gpu, storage):
     scale = np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
     err_cell = (np.abs(g[cells] - fd) / scale).max()
     err_norm = np.abs(g[cells] - fd).max() / np.abs(fd).max()
-    announce(f"{storage} gradient vs FD: per-cell {err_cell:.3e}, max-norm {err_norm:.3e}")
+    tan = []
+    for cell in cells:
+        t = oracle_for(case, tangent=True)
+        e = np.zeros(N)
+        e[cell] = 1.0
+        t.set_phi_tangent(e)
+        t.step(T)
+        tan.append(t.objective(planes)[1])
+    tan = np.array(tan)
+    err_tan = (np.abs(g[cells] - tan) / np.maximum(np.abs(tan), 1e-3 * np.abs(tan).max())).max()
+    fd_tan = (np.abs(fd - tan) / np.maximum(np.abs(tan), 1e-3 * np.abs(tan).max())).max()
+    announce(f"{storage} gradient: per-cell vs exact {err_tan:.3e}; vs FD per-cell {err_cell:.3e}, max-norm "
+             f"{err_norm:.3e}; FD vs exact per-cell {fd_tan:.3e}")
     if storage == "f64":
-        assert err_cell <= 1e-4, err_cell
+        assert err_tan <= 1e-10 and err_cell <= 1e-4, (err_tan, err_cell)
     else:
-        assert err_norm <= 1e-4 and err_cell <= 1e-3, (err_norm, err_cell)
+        err_tan_norm = np.abs(g[cells] - tan).max() / np.abs(tan).max()
+        assert err_tan <= 2e-4 and err_tan_norm <= 1e-5 and err_norm <= 1e-4, (err_tan, err_tan_norm, err_norm)
 
 
 def test_autograd_function(gpu):
@@ -242,3 +261,53 @@ def test_autograd_function_mean(gpu):
     grad = torch.zeros(case.ncells, dtype=torch.float64, device="cuda")
     gpu.lbm_gradient_mean(lat.ctx, 9, planes, lat.new_state_buffer(3), 3, lat.new_adjoint(), grad)
     np.testing.assert_array_equal(phi.grad.numpy(), grad.cpu().numpy())
+
+
+def test_fp32_gradient_error_split(gpu):
+    """Where the FP32 gradient's error comes from, on the case above: the
+    oracle's exact derivative taken along the GPU's FP32 trajectory (its
+    states exported every step as FP32 full populations and loaded into the
+    tangent run, the tangent carried over) against the FP64 derivative (the
+    trajectory part, an upper bound: the export rounds full populations), and
+    the GPU's FP32 gradient against the derivative along its own trajectory
+    (the adjoint arithmetic part).  Both are reported per cell; each stays
+    within 5e-4 of the derivative (floor 1e-3 of the largest), and the total
+    within 2e-4."""
+    case = _case((32, 24, 16))
+    planes = (4, 28)
+    T = 100
+    N = case.ncells
+    cells = I.sample_cells(N, 8, seed_offset=5)
+    lat = gpu.Lattice(case, storage="f32")
+    traj = [lat.populations().double().cpu().numpy()]
+    for _ in range(T):
+        lat.step(1)
+        traj.append(lat.populations().double().cpu().numpy())
+    run = gpu.Lattice(case, storage="f32")
+    g = run.new_gradient()
+    gpu.lbm_gradient(run.ctx, T, planes, run.new_state_buffer(11), 11, run.new_adjoint(), g)
+    g = g.cpu().numpy()[cells]
+    exact, along = [], []
+    for cell in cells:
+        e = np.zeros(N)
+        e[cell] = 1.0
+        t = oracle_for(case, tangent=True)
+        t.set_phi_tangent(e)
+        t.step(T)
+        exact.append(t.objective(planes)[1])
+        o = oracle_for(case, tangent=True)
+        o.set_phi_tangent(e)
+        v = np.zeros_like(traj[0])
+        for s in range(T):
+            o.set_populations(traj[s], v)
+            o.step(1)
+            v = o.populations(with_tangent=True)[1]
+        o.set_populations(traj[T], v)
+        along.append(o.objective(planes)[1])
+    exact, along = np.array(exact), np.array(along)
+    sc = np.maximum(np.abs(exact), 1e-3 * np.abs(exact).max())
+    tot, traj_part, adj_part = np.abs(g - exact) / sc, np.abs(along - exact) / sc, np.abs(g - along) / sc
+    for k, c in enumerate(cells):
+        announce(f"cell {c}: dJ/dphi {exact[k]: .4e}  total {tot[k]:.2e}  trajectory {traj_part[k]:.2e}  "
+                 f"adjoint {adj_part[k]:.2e}")
+    assert tot.max() <= 2e-4 and traj_part.max() <= 5e-4 and adj_part.max() <= 5e-4

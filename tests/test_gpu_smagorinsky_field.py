@@ -252,3 +252,25 @@ def test_adjoint_step_cs_transpose(gpu):
     rhs = float((v * nat.cpu().numpy()).sum()) + float((dc * gcs.cpu().numpy()).sum())
     announce(f"C_S transpose: <Lv,w> {lhs:.15e} <v,L^T w> {rhs:.15e}")
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+
+
+def test_autograd_with_cs_field(gpu):
+    """autograd.objective(phi, ..., cs=...): backward gives lbm_gradient_cs's
+    dJ/dphi and dJ/dC_S; the value matches a run without gradients."""
+    from paper_2506_21804_amd.autograd import objective
+    case = _wall_porous(collision=1)
+    planes = (2, 13)
+    N = case.ncells
+    cs0 = _field(N, 331)
+    phi = torch.tensor(case.porosity, dtype=torch.float64, requires_grad=True)
+    cs = torch.tensor(cs0, dtype=torch.float64, requires_grad=True)
+    J = objective(phi, case, storage="f64", T=10, planes=planes, nsnap=3, cs=cs)
+    J.backward()
+    J0 = objective(phi.detach(), case, storage="f64", T=10, planes=planes, nsnap=3, cs=cs.detach())
+    assert abs(J.item() - J0.item()) <= 1e-13 * abs(J.item())
+    lat = gpu.Lattice(case, storage="f64", cs_field=True)
+    lat.set_smagorinsky(cs0)
+    gphi, gcs = lat.new_gradient(), lat.new_gradient()
+    gpu.lbm_gradient_cs(lat.ctx, 10, planes, lat.new_state_buffer(3), 3, lat.new_adjoint(), gphi, gcs)
+    np.testing.assert_array_equal(phi.grad.numpy(), gphi.cpu().numpy())
+    np.testing.assert_array_equal(cs.grad.numpy(), gcs.cpu().numpy())
