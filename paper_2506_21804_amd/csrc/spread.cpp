@@ -29,7 +29,7 @@ namespace lbmk {
 
 namespace {
 
-constexpr size_t SPREAD = (size_t)4 << 30;
+constexpr size_t SPREAD = (size_t)6 << 30;
 
 struct Mapping {
   size_t offset, bytes;
