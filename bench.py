@@ -304,13 +304,13 @@ def main():
     fdw = args.fd_weight if args.collision == "rr3" else 0.0
     # algorithmic bytes of one bulk launch: every cell's flag byte, q loads and
     # q stores for each fluid cell it updates (all fluid cells but the wall
-    # cells and the open-face cells); the hybrid collision also reads the velocity field once (three
+    # cells and the open-face cells); the hybrid collision also reads the velocity field once (four
     # compute-type values per fluid cell), which a pre-pass over the q loads
     # of every fluid cell wrote
     rb = 8 if storage == "f64" else 4
-    k2_bytes = N * 1 + (nfluid - nwall - n_open) * 2 * q * sb + (nfluid * 3 * rb if fdw > 0 else 0)
+    k2_bytes = N * 1 + (nfluid - nwall - n_open) * 2 * q * sb + (nfluid * 4 * rb if fdw > 0 else 0)
     achieved = k2_bytes / (k2_ms * 1e-3) / 1e9
-    step_bytes = nfluid * (2 * q * sb + 1) + (nfluid * (q * sb + 6 * rb) if fdw > 0 else 0)
+    step_bytes = nfluid * (2 * q * sb + 1) + (nfluid * (q * sb + 8 * rb) if fdw > 0 else 0)
     traffic = measured_traffic(args.workload, args.collision, fdw)
     diag = lat.diagnostics()
     ceiling = None

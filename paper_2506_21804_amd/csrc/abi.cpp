@@ -139,7 +139,7 @@ Layout layout_of(const lbm_params &p, long long nwall, bool porous) {
   L.tables = off;
   off += align_up(((size_t)p.nz + p.nx) * rb);
   L.vel = off;
-  off += p.fd_weight > 0.0 ? align_up(3 * N * rb) : 0;
+  off += p.fd_weight > 0.0 ? align_up(4 * N * rb) : 0;
   L.inflow = off;
   off += p.open_x ? align_up(3 * (size_t)p.ny * p.nz * rb) : 0;
   L.vort = off;

@@ -54,7 +54,7 @@ struct KArgs {
   int slip;          // full-slip box faces (lbm_params.slip bits)
   int open_x;        // 1: inlet / outlet on the x faces
   double rho_out;    // outlet density
-  const void *vel;   // [3][N] velocity field of the current step, compute type (fdw > 0)
+  const void *vel;   // [N] (u_x, u_y, u_z, fluid 1/0) of the current step, compute type (fdw > 0)
   const void *uin;   // [nz] fringe inflow profile, compute type
   const void *lam;   // [nx] fringe blend weight, compute type (0 before the fringe)
   const void *inflow;  // [3][ny nz] inlet velocity, compute type (open_x)
@@ -114,7 +114,7 @@ struct lbm_ctx {
   void *phi = nullptr;        // [N] compute type, porous only
   void *csf = nullptr;        // [N] per-cell C_S, compute type (cs_field only; in force when ka.csf is set)
   void *tables = nullptr;     // [nz] inflow + [nx] fringe weights, compute type
-  void *vel = nullptr;        // [3][N] velocity field, compute type (hybrid collision only)
+  void *vel = nullptr;        // [N] (u, fluid) vectors, compute type (hybrid collision only)
   void *inflow = nullptr;     // [3][ny nz] inlet velocity, compute type (open_x only)
   double *vort = nullptr;     // [LBM_MAX_VORTICES][3] vortex y, z, circulation (open_x only)
   int nwall = 0;

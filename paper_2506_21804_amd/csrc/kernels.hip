@@ -124,22 +124,31 @@ __device__ __forceinline__ void lid_equilibrium(R g[Q], const KArgs &k) {
 // D_ab = d_a u_b by central differences; one-sided where one neighbour along
 // the axis is solid or outside a non-periodic axis, zero where both are
 // (hybrid collision, Sec. 2.2, Eq. (10)).  S[0..5] = xx, yy, zz, xy, xz, yz.
+// The velocity field of the hybrid is one vector per cell, (u_x, u_y, u_z,
+// 1 for a fluid cell / 0 otherwise): a neighbour's velocity and whether it is
+// fluid come in one vector load.
 template <typename R>
-__device__ __forceinline__ void fd_strain(const Nb &n, const uint8_t *__restrict__ flags, const KArgs &k, R S[6]) {
-  const R *v = static_cast<const R *>(k.vel);
-  const size_t N = (size_t)k.N;
+struct alignas(4 * sizeof(R)) V4 {
+  R x, y, z, w;
+};
+
+template <typename R>
+__device__ __forceinline__ void fd_strain(const Nb &n, const KArgs &k, R S[6]) {
+  const V4<R> *v = static_cast<const V4<R> *>(k.vel);
+  const V4<R> c = v[n.cell];
   R D[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int cp = n.cell + n.d[a][1], cm = n.cell + n.d[a][0];
-    const bool fp = !((n.out >> (2 * a + 1)) & 1u) && (flags[cp] & FL_FLUID);
-    const bool fm = !((n.out >> (2 * a)) & 1u) && (flags[cm] & FL_FLUID);
+    const V4<R> zero = {R(0), R(0), R(0), R(0)};
+    const V4<R> P = ((n.out >> (2 * a + 1)) & 1u) ? zero : v[n.cell + n.d[a][1]];
+    const V4<R> M = ((n.out >> (2 * a)) & 1u) ? zero : v[n.cell + n.d[a][0]];
+    const bool fp = P.w > R(0.5), fm = M.w > R(0.5);
+    const R up[3] = {P.x, P.y, P.z}, um[3] = {M.x, M.y, M.z}, uc[3] = {c.x, c.y, c.z};
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const R uc = v[(size_t)b * N + n.cell];
-      if (fp && fm) D[a][b] = R(0.5) * (v[(size_t)b * N + cp] - v[(size_t)b * N + cm]);
-      else if (fp) D[a][b] = v[(size_t)b * N + cp] - uc;
-      else if (fm) D[a][b] = uc - v[(size_t)b * N + cm];
+      if (fp && fm) D[a][b] = R(0.5) * (up[b] - um[b]);
+      else if (fp) D[a][b] = up[b] - uc[b];
+      else if (fm) D[a][b] = uc[b] - um[b];
       else D[a][b] = R(0);
     }
   }
@@ -477,7 +486,7 @@ __device__ __forceinline__ void bulk_cell(S *__restrict__ pop, const typename St
     }
     const R ph = POROUS ? phi[n.cell] : R(1);
     R Sfd[6];
-    if constexpr (HYB) fd_strain<R>(n, flags, k, Sfd);
+    if constexpr (HYB) fd_strain<R>(n, k, Sfd);
     if (!collide_bulk<Q, R, POROUS, RR, HYB>(g, ph, smag_of<R>(k, n.cell), k, Sfd)) atomicOr(errflag, 1);
   }
   // the outlet plane is left out of the fringe
@@ -678,7 +687,7 @@ __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t
   R Sw[6] = {};
   const bool full = k.fdw > 0.0;
   if (full) {
-    fd_strain<R>(n, flags, k, Sw);
+    fd_strain<R>(n, k, Sw);
     const R snx = Sw[0] * nx + Sw[3] * ny + Sw[4] * nz;
     const R sny = Sw[3] * nx + Sw[1] * ny + Sw[5] * nz;
     const R snz = Sw[4] * nx + Sw[5] * ny + Sw[2] * nz;
@@ -778,6 +787,32 @@ __device__ __forceinline__ bool gather_state(const S *__restrict__ pop, const ui
 #pragma unroll
   for (int i = 0; i < Q; ++i) g[i] = Store<S>::ld(pop + read_slot<Q, ODD, SOLID == 2>(n, sm, i, (size_t)k.N));
   return true;
+}
+
+// The hybrid's velocity field: (Guo velocity, 1) at fluid cells, 0 elsewhere.
+template <int Q, typename S, bool ODD, int SOLID>
+__global__ __launch_bounds__(BLOCK) void k_velocity4(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
+                                                     V4<typename Store<S>::R> *__restrict__ out, KArgs k, Tiles t) {
+  using R = typename Store<S>::R;
+  int x, y, z;
+  if (!tile_xyz(k, t, blockIdx.x, x, y, z)) return;
+  Nb n;
+  R g[Q];
+  if (!gather_state<Q, S, ODD, SOLID>(pop, flags, k, x, y, z, n, g)) {
+    out[x + k.nx * (y + k.ny * z)] = V4<R>{R(0), R(0), R(0), R(0)};
+    return;
+  }
+  R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += g[i];
+    acc(jx, Lat<Q>::c(i, 0), g[i]);
+    acc(jy, Lat<Q>::c(i, 1), g[i]);
+    acc(jz, Lat<Q>::c(i, 2), g[i]);
+  }
+  const R rho = R(1) + drho;
+  out[n.cell] = V4<R>{(jx + R(0.5) * R(k.F[0])) / rho, (jy + R(0.5) * R(k.F[1])) / rho,
+                      (jz + R(0.5) * R(k.F[2])) / rho, R(1)};
 }
 
 template <int Q, typename S, bool ODD, int SOLID>
@@ -1123,10 +1158,10 @@ int dev_step(lbm_ctx *ctx) {
     // hybrid collision: the step's velocity field first (read by K2 and K3 at neighbours)
     if (ctx->ka.fdw > 0.0) {
       using R = typename Store<S>::R;
-      R *vel = (R *)ctx->vel;
+      V4<R> *vel = (V4<R> *)ctx->vel;
       by_parity(ctx, [&]<bool ODD, int SOLID>() {
-        k_moments<Q, S, ODD, SOLID><<<t.nblocks, BLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, nullptr,
-                                                                        vel, ctx->ka, t);
+        k_velocity4<Q, S, ODD, SOLID><<<t.nblocks, BLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, vel,
+                                                                          ctx->ka, t);
         return LBM_OK;
       });
     }
