@@ -118,7 +118,7 @@ bool params_ok(const lbm_params *p, std::string &msg) {
 }
 
 struct Layout {
-  size_t pop, flags, phi, csf, tables, vel, inflow, vort, wcell, wref, wrefwall, wlist, wrec, rcell, roff, rrec, partial,
+  size_t pop, flags, phi, csf, tables, vel, inflow, vort, wcell, wref, wrefwall, wlist, wrec, wmask, rcell, roff, rrec, partial,
       result, errflag,
       total;
 };
@@ -154,6 +154,8 @@ Layout layout_of(const lbm_params &p, long long nwall, bool porous) {
   off += align_up((size_t)nwall * sizeof(int));
   L.wrec = off;
   off += align_up((size_t)nwall * WR_COUNT * sizeof(double));
+  L.wmask = off;
+  off += align_up((size_t)nwall * 2 * sizeof(uint64_t));
   // the records grouped by reference cell (reverse step)
   L.rcell = off;
   off += align_up((size_t)nwall * sizeof(int));
@@ -227,6 +229,25 @@ void prof_end(lbm_ctx *ctx, int k) {
 }  // namespace lbmk
 
 namespace {
+// Link masks of the wall cells (wm[w]) and of their reference cells
+// (wm[nwall + w], 0 unless the reference cell has a solid link), as the
+// kernels' solid_mask gives them; the geometry is static, so the wall kernels
+// read them instead of gathering the neighbours' flags every odd step.
+template <int Q, bool SLIP>
+void wall_masks(const KArgs &k, const uint8_t *flags, const std::vector<int> &wcell, const std::vector<int> &wref,
+                std::vector<uint64_t> &wm) {
+  const size_t M = wcell.size();
+  auto mask_of = [&](int c) {
+    int x, y, z;
+    cell_xyz(c, k, x, y, z);
+    return (uint64_t)solid_mask<Q, SLIP>(make_nb(x, y, z, k), flags);
+  };
+  for (size_t w = 0; w < M; ++w) {
+    wm[w] = mask_of(wcell[w]);
+    wm[M + w] = (flags[wref[w]] & FL_NEAR) ? mask_of(wref[w]) : 0u;
+  }
+}
+
 // Slots of every fluid cell at one parity, by the kernels' own slot
 // functions: the plain path for cells without solid links (every cell at
 // even parity), the bounce-back map for the others.
@@ -336,6 +357,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
   ctx->wref_off = (int *)(base + L.roff);
   ctx->wref_rec = (int *)(base + L.rrec);
   ctx->wrec = (double *)(base + L.wrec);
+  ctx->wmask = (uint64_t *)(base + L.wmask);
   ctx->partial = (double *)(base + L.partial);
   ctx->npartial = PARTIAL_SLOTS;
   ctx->result = (double *)(base + L.result);
@@ -423,6 +445,17 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, const uint8_t *mask, const doub
       return fail(e, "upload wall references");
     if ((e = hipMemcpy(ctx->wrec, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
       return fail(e, "upload wall records");
+    // link masks of each wall cell and of its reference cell (static geometry)
+    std::vector<uint64_t> wm((size_t)2 * nwall);
+    if (ctx->q == 19) {
+      if (ctx->has_slip) wall_masks<19, true>(k, g.flags.data(), g.wcell, g.wref, wm);
+      else wall_masks<19, false>(k, g.flags.data(), g.wcell, g.wref, wm);
+    } else {
+      if (ctx->has_slip) wall_masks<27, true>(k, g.flags.data(), g.wcell, g.wref, wm);
+      else wall_masks<27, false>(k, g.flags.data(), g.wcell, g.wref, wm);
+    }
+    if ((e = hipMemcpy(ctx->wmask, wm.data(), wm.size() * sizeof(uint64_t), hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e, "upload wall link masks");
     // records grouped by reference cell, in increasing cell and record order
     std::vector<int> order((size_t)nwall);
     for (long long k = 0; k < nwall; ++k) order[(size_t)k] = (int)k;

@@ -965,8 +965,9 @@ __global__ __launch_bounds__(256) void k_adjoint_wall(const S *__restrict__ pop,
                                                       const double *__restrict__ m_prev, double *__restrict__ m_next,
                                                       const int *__restrict__ wcell, const int *__restrict__ wref,
                                                       const double *__restrict__ rec, int nwall,
-                                                      double *__restrict__ wadj, double *__restrict__ gcs, KArgs k,
-                                                      int p0, int p1, const double *__restrict__ cnt, double sw) {
+                                                      const uint64_t *__restrict__ wmask, double *__restrict__ wadj,
+                                                      double *__restrict__ gcs, KArgs k, int p0, int p1,
+                                                      const double *__restrict__ cnt, double sw) {
   using R = typename Store<S>::R;
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nwall) return;
@@ -974,7 +975,7 @@ __global__ __launch_bounds__(256) void k_adjoint_wall(const S *__restrict__ pop,
   int x, y, z;
   cell_xyz(b, k, x, y, z);
   const Nb n = make_nb(x, y, z, k);
-  const LinkMask sm = solid_mask<Q, SLIP>(n, flags);
+  const LinkMask sm = wmask[w];  // precomputed from the static geometry
   const size_t N = (size_t)k.N;
   double scale = 1.0;
   if (x >= k.fringe_start) scale = 1.0 - (double)static_cast<const R *>(k.lam)[x];
@@ -995,7 +996,7 @@ __global__ __launch_bounds__(256) void k_adjoint_wall(const S *__restrict__ pop,
   // the record, from the reference cell's state (the forward step's inputs)
   const size_t M = (size_t)nwall;
   double rho_r, ur[3];
-  ref_velocity<Q, S, ODD, SLIP>(pop, flags, r, k, rho_r, ur);
+  ref_velocity<Q, S, ODD, SLIP>(pop, wmask[M + w], r, k, rho_r, ur);
   const double nn[3] = {rec[WR_NX * M + w], rec[WR_NY * M + w], rec[WR_NZ * M + w]};
   const double yr = rec[WR_YR * M + w], yb = rec[WR_YB * M + w];
   const double C2 = cs2_of<R>(k, b);
@@ -1235,7 +1236,8 @@ int adjoint_step_qs(lbm_ctx *ctx, void *lamv, void *gradv, void *gcsv, double se
       const int nw = ctx->nwall, wb = (nw + 255) / 256;
       auto gow = [&](auto kern) {
         kern<<<wb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, dev, a.m_other, a.m_cur, ctx->wcell,
-                                         ctx->wref, ctx->wrec, nw, a.wadj, gcs, ctx->ka, p0, p1, cnt, seed_w);
+                                         ctx->wref, ctx->wrec, nw, ctx->wmask, a.wadj, gcs, ctx->ka, p0, p1, cnt,
+                                         seed_w);
       };
       constexpr bool SLIP = SOLID == 2;
       if (ctx->ka.rr) {

@@ -119,6 +119,7 @@ struct lbm_ctx {
   double *vort = nullptr;     // [LBM_MAX_VORTICES][3] vortex y, z, circulation (open_x only)
   int nwall = 0;
   int *wcell = nullptr;       // [nwall]
+  uint64_t *wmask = nullptr;  // [2][nwall] link masks of the wall cells and of their reference cells
   int *wref = nullptr;        // [nwall]
   uint8_t *wrefwall = nullptr;   // [nwall] 1 when the reference cell is itself a wall cell
   int *wlist_refwall = nullptr;  // [nwall_refwall] indices of those records

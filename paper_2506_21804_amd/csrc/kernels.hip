@@ -600,11 +600,11 @@ __global__ __launch_bounds__(BLOCK) void k_stream_probe(S *__restrict__ pop_, co
 // (the computation itself is wall_record_of in wall.h).
 // ---------------------------------------------------------------------------
 template <int Q, typename S, bool ODD, bool SLIP>
-__device__ __forceinline__ void wall_record(const S *__restrict__ pop, const uint8_t *__restrict__ flags, int w, int b,
-                                            int r, double *__restrict__ rec, int nwall, const KArgs &k,
+__device__ __forceinline__ void wall_record(const S *__restrict__ pop, const uint64_t *__restrict__ wmask, int w,
+                                            int b, int r, double *__restrict__ rec, int nwall, const KArgs &k,
                                             int *__restrict__ errflag) {
   double rho, u[3];
-  ref_velocity<Q, S, ODD, SLIP>(pop, flags, r, k, rho, u);
+  ref_velocity<Q, S, ODD, SLIP>(pop, wmask[(size_t)nwall + w], r, k, rho, u);
   const size_t M = (size_t)nwall;
   const double n[3] = {rec[WR_NX * M + w], rec[WR_NY * M + w], rec[WR_NZ * M + w]};
   const WallRec wr =
@@ -620,7 +620,7 @@ __device__ __forceinline__ void wall_record(const S *__restrict__ pop, const uin
 }
 
 template <int Q, typename S, bool ODD, bool SLIP>
-__global__ __launch_bounds__(256) void k_wall_prepass(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
+__global__ __launch_bounds__(256) void k_wall_prepass(const S *__restrict__ pop, const uint64_t *__restrict__ wmask,
                                                       const int *__restrict__ wcell, const int *__restrict__ wref,
                                                       const int *__restrict__ list, int nlist,
                                                       double *__restrict__ rec, int nwall, KArgs k,
@@ -628,14 +628,14 @@ __global__ __launch_bounds__(256) void k_wall_prepass(const S *__restrict__ pop,
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nlist) return;
   const int w = list[j];
-  wall_record<Q, S, ODD, SLIP>(pop, flags, w, wcell[w], wref[w], rec, nwall, k, errflag);
+  wall_record<Q, S, ODD, SLIP>(pop, wmask, w, wcell[w], wref[w], rec, nwall, k, errflag);
 }
 
 // ---------------------------------------------------------------------------
 // K3: wall reconstruction (sigma = 0, solid velocity = modeled velocity).
 // ---------------------------------------------------------------------------
 template <int Q, typename S, bool ODD, bool SLIP>
-__global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t *__restrict__ flags,
+__global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint64_t *__restrict__ wmask,
                                               const int *__restrict__ wcell, const int *__restrict__ wref,
                                               const uint8_t *__restrict__ refwall, double *__restrict__ rec,
                                               int nwall, KArgs k, int *__restrict__ errflag) {
@@ -646,7 +646,8 @@ __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t
   int x, y, z;
   cell_xyz(b, k, x, y, z);
   const Nb n = make_nb(x, y, z, k);
-  const LinkMask sm = ODD ? solid_mask<Q, SLIP>(n, flags) : 0u;
+  // the cell's link mask, precomputed from the static geometry
+  const LinkMask sm = ODD ? wmask[w] : 0u;
   const size_t N = (size_t)k.N;
   R g[Q];
   R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
@@ -662,7 +663,7 @@ __global__ __launch_bounds__(256) void k_wall(S *__restrict__ pop, const uint8_t
   // here (no other thread of this launch writes that reference); the others
   // were computed by k_wall_prepass before this launch.  It comes after the
   // loads above, so that their latency overlaps the Newton solves.
-  if (!refwall[w]) wall_record<Q, S, ODD, SLIP>(pop, flags, w, b, wref[w], rec, nwall, k, errflag);
+  if (!refwall[w]) wall_record<Q, S, ODD, SLIP>(pop, wmask, w, b, wref[w], rec, nwall, k, errflag);
   const R rho = R(1) + drho;
   if (!finite_pos(rho)) atomicOr(errflag, 1);
   const R Fx = R(k.F[0]), Fy = R(k.F[1]), Fz = R(k.F[2]);
@@ -1170,7 +1171,7 @@ int dev_step(lbm_ctx *ctx) {
       prof_begin(ctx, 0);
       const int lb = (nb + 255) / 256;
       auto gp = [&](auto kern) {
-        kern<<<lb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wref,
+        kern<<<lb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->wmask, ctx->wcell, ctx->wref,
                                           ctx->wlist_refwall, nb, ctx->wrec, nw, ctx->ka, ctx->errflag);
       };
       if (odd) ctx->has_slip ? gp(k_wall_prepass<Q, S, true, true>) : gp(k_wall_prepass<Q, S, true, false>);
@@ -1181,7 +1182,7 @@ int dev_step(lbm_ctx *ctx) {
     if (nw > 0) {
       prof_begin(ctx, 2);
       auto gw = [&](auto kern) {
-        kern<<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->flags, ctx->wcell, ctx->wref, ctx->wrefwall, ctx->wrec,
+        kern<<<wb, 256, 0, ctx->stream>>>((S *)ctx->pop, ctx->wmask, ctx->wcell, ctx->wref, ctx->wrefwall, ctx->wrec,
                                           nw, ctx->ka, ctx->errflag);
       };
       if (odd) ctx->has_slip ? gw(k_wall<Q, S, true, true>) : gw(k_wall<Q, S, true, false>);

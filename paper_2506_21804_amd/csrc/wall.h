@@ -47,14 +47,14 @@ __device__ __forceinline__ void spalding_gd(double up, double kappa, double inv_
 }
 
 // Density and Guo velocity u = (j + F/2)/rho of cell r's current state, FP64.
+// rmask: the cell's link mask, precomputed (0 unless it has a solid link).
 template <int Q, typename S, bool ODD, bool SLIP>
-__device__ __forceinline__ void ref_velocity(const S *__restrict__ pop, const uint8_t *__restrict__ flags, int r,
-                                             const KArgs &k, double &rho, double u[3]) {
+__device__ __forceinline__ void ref_velocity(const S *__restrict__ pop, LinkMask rmask, int r, const KArgs &k,
+                                             double &rho, double u[3]) {
   int x, y, z;
   cell_xyz(r, k, x, y, z);
   const Nb n = make_nb(x, y, z, k);
-  LinkMask sm = 0;
-  if (ODD && (flags[r] & FL_NEAR)) sm = solid_mask<Q, SLIP>(n, flags);
+  const LinkMask sm = ODD ? rmask : 0u;
   const size_t N = (size_t)k.N;
   double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
