@@ -237,7 +237,15 @@ def main():
         return bench_adjoint(args, torch, lbm, case, storage, wname)
 
     spread = not args.no_spread
-    lat = lbm.Lattice(case, storage=storage, wall_dist=None if case.wall_dist is None else "case", spread=spread)
+    try:
+        lat = lbm.Lattice(case, storage=storage, wall_dist=None if case.wall_dist is None else "case", spread=spread)
+    except lbm.LbmError as e:
+        if not spread:
+            raise
+        # too little free device memory for the spread pieces: the plain layout
+        print(f"[bench] spread workspace unavailable ({e}); plain allocation", file=sys.stderr, flush=True)
+        spread = False
+        lat = lbm.Lattice(case, storage=storage, wall_dist=None if case.wall_dist is None else "case")
     N = case.ncells
     nfluid = case.nfluid()
     nwall = lbm.lbm_wall_count(lat.ctx)
