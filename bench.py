@@ -119,9 +119,9 @@ def cpu_baseline(name, budget_s=12.0, collision=0, fd_weight=0.0):
     elif name.startswith("urban") or name.startswith("big"):
         open_x = name.startswith("urban_open")
         slip = name.startswith("urban_slip")
-        case = I.urban(192, 192, 64, q=27, fringe_len=32, x_lo=16, x_hi=144, h_mean=20.0, h_max=48, open_x=open_x,
+        case = I.urban(192, 192, 128, q=27, fringe_len=32, x_lo=16, x_hi=144, h_mean=20.0, h_max=48, open_x=open_x,
                        slip_walls=slip)
-        sample = "urban crop 192x192x64 (buildings, fringe, {}{}), D3Q27 FP64".format(
+        sample = "urban crop 192x192x128 (buildings, fringe, {}{}), D3Q27 FP64".format(
             "full-slip sides and top" if slip else "lid", ", inlet and outlet" if open_x else "")
     elif name == "tgv":
         case = I.taylor_green(32, q=19)
