@@ -183,3 +183,58 @@ def test_fd_weight_checked():
         O.Oracle(O.make_params(19, (4, 4, 4), tau0=0.6, collision=0, fd_weight=0.5))
     with pytest.raises(O.OracleError):
         O.Oracle(O.make_params(19, (4, 4, 4), tau0=0.6, collision=1, fd_weight=1.5))
+
+
+def test_tangent_through_the_hybrid_matches_central_differences():
+    """The tangent oracle differentiates the hybrid collision (the
+    finite-difference strain of the neighbours' velocities, the blend, and at
+    wall cells the full strain with the law's wall-normal shear): dJ/dphi at
+    a wall cell, a reference cell and a bulk cell, and along a random
+    population direction, against central differences of the FP64 oracle.
+    (The wall cell's own porosity does not enter its reconstruction: there
+    both are exactly 0.)"""
+    from paper_2506_21804_amd import inputs as I
+    case = I.porous_channel(shape=(12, 10, 8))
+    case.wall_model = 1
+    case.wall_dist = I.voxel_wall_distance(case.mask, case.shape, case.periodic)
+    planes = (1, 9)
+    steps = 10
+    nx, ny, nz = case.shape
+    p = O.make_params(19, case.shape, periodic=case.periodic, tau0=case.tau0, cs_smag=case.cs_smag,
+                      force=case.force, wall_model=1, collision=1, fd_weight=0.3)
+    kw = dict(mask=case.mask, wall_dist=case.wall_dist, rho0=case.rho0, u0=case.u0)
+    for cell in (3 + nx * 4, 3 + nx * (4 + ny), 6 + nx * (2 + ny * 4)):
+        s = O.Oracle(p, porosity=case.porosity, tangent=True, **kw)
+        e = np.zeros(case.ncells)
+        e[cell] = 1.0
+        s.set_phi_tangent(e)
+        s.step(steps)
+        _, dJ = s.objective(planes)
+        h = 1e-5
+        Js = []
+        for sgn in (1, -1):
+            ph = case.porosity.copy()
+            ph[cell] += sgn * h
+            t = O.Oracle(p, porosity=ph, **kw)
+            t.step(steps)
+            Js.append(t.objective(planes)[0])
+        fd = (Js[0] - Js[1]) / (2 * h)
+        assert cell == 3 + nx * 4 or abs(dJ) > 0.0
+        assert abs(dJ - fd) <= 2e-5 * abs(fd) + 1e-13, (cell, dJ, fd)
+    # a random direction in the populations
+    c, w, _ = O.velocity_set(19)
+    f0 = I.random_state(w, case.ncells, seed_offset=61, amp=0.02) * case.mask
+    v = np.random.default_rng(62).standard_normal(f0.shape) * case.mask
+    s = O.Oracle(p, porosity=case.porosity, tangent=True, **kw)
+    s.set_populations(f0, v)
+    s.step(steps)
+    _, dJ = s.objective(planes)
+    h = 1e-6
+    Js = []
+    for sgn in (1, -1):
+        t = O.Oracle(p, porosity=case.porosity, **kw)
+        t.set_populations(f0 + sgn * h * v)
+        t.step(steps)
+        Js.append(t.objective(planes)[0])
+    fd = (Js[0] - Js[1]) / (2 * h)
+    assert abs(dJ - fd) <= 1e-5 * abs(fd) + 1e-13, (dJ, fd)
