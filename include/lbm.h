@@ -205,8 +205,13 @@ int lbm_objective(lbm_ctx *ctx, const int planes[2], double *J);
  * step parity.  Its values are read and written in natural order through
  * lbm_adjoint_to_natural / _from_natural.  The common mode is handled in
  * FP64 and the deviations pass through the collision's vector-Jacobian
- * product in the compute precision; grad_phi is FP64.  Misaligned buffers
- * give LBM_EINVAL.
+ * product in the compute precision; grad_phi is FP64.  With the hybrid
+ * collision (fd_weight > 0, Eqs. (7), (10)) the buffer also holds the
+ * adjoint of each cell's finite-difference strain (six values per cell in
+ * the compute type, scratch of the reverse step), and the reverse step
+ * carries it back through the strain's central and one-sided differences
+ * to the neighbours' velocities and populations.  Misaligned buffers give
+ * LBM_EINVAL.
  *  lbm_adjoint_seed: lambda = dJ/df of the current state (async).
  *  lbm_adjoint_step: given lambda = dJ/df^{n+1} and the state f^n currently
  *    held by the context (step counter n), overwrites lambda with dJ/df^n
@@ -231,8 +236,7 @@ int lbm_adjoint_from_natural(lbm_ctx *ctx, const void *natural, void *lambda);
  * checkpoint to T-1.  *J receives the objective at step T and *nforward the
  * forward steps taken (lbm_revolve_cost(T, nsnap) + 1 + that re-advance; T
  * exactly when nsnap > T).  On return the context holds the state of step 0
- * again.  Synchronises.  Not available with the hybrid collision (the
- * finite-difference strain is not differentiated). */
+ * again.  Synchronises. */
 int lbm_gradient(lbm_ctx *ctx, int T, const int planes[2], void *snapshots, int nsnap, void *lambda,
                  void *grad_phi, double *J, long long *nforward);
 

@@ -618,7 +618,7 @@ int lbm_objective(lbm_ctx *ctx, const int planes[2], double *J) {
 
 size_t lbm_adjoint_bytes(const lbm_ctx *ctx) {
   if (!ctx) return 0;
-  return adj_layout(ctx->N, ctx->q, ctx->p.storage == LBM_F64 ? 8 : 4, ctx->nwall).bytes;
+  return adj_layout(ctx->N, ctx->q, ctx->p.storage == LBM_F64 ? 8 : 4, ctx->nwall, ctx->ka.fdw > 0.0).bytes;
 }
 
 static bool adj_aligned(const void *p) { return ((uintptr_t)p & 7u) == 0; }
@@ -633,8 +633,6 @@ int lbm_adjoint_seed(lbm_ctx *ctx, const int planes[2], void *lambda) {
 
 int lbm_adjoint_step_cs(lbm_ctx *ctx, void *lambda, void *grad_phi, void *grad_cs) {
   if (!ctx || !lambda || !grad_phi) return ctx ? set_err(ctx, LBM_EINVAL, "null argument") : LBM_EINVAL;
-  if (ctx->ka.fdw > 0.0)
-    return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the finite-difference strain");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi) || !adj_aligned(grad_cs))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   return dev_adjoint_step(ctx, lambda, grad_phi, grad_cs);
@@ -684,8 +682,6 @@ static int gradient_sweep(lbm_ctx *ctx, int T, const int planes[2], void *snapsh
   if (!ctx) return LBM_EINVAL;
   if (T < 1 || nsnap < 1 || !snapshots || !lambda || !grad_phi || !planes)
     return set_err(ctx, LBM_EINVAL, "gradient needs T >= 1, nsnap >= 1 and non-null buffers");
-  if (ctx->ka.fdw > 0.0)
-    return set_err(ctx, LBM_EINVAL, "the adjoint does not differentiate the finite-difference strain");
   if (!adj_aligned(lambda) || !adj_aligned(grad_phi) || !adj_aligned(grad_cs))
     return set_err(ctx, LBM_EINVAL, "adjoint or gradient buffer not 8-byte aligned");
   const size_t sb = lbm_state_bytes(ctx);
@@ -866,7 +862,7 @@ int lbm_adjoint_alloc(const lbm_ctx *ctx, void **lambda, size_t *bytes) {
   *lambda = nullptr;
   *bytes = 0;
   const size_t db = ctx->p.storage == LBM_F64 ? 8 : 4;
-  const AdjLayout L = adj_layout(ctx->N, ctx->q, db, ctx->nwall);
+  const AdjLayout L = adj_layout(ctx->N, ctx->q, db, ctx->nwall, ctx->ka.fdw > 0.0);
   std::string msg;
   const int rc = spread_alloc(L.bytes, L.d_off, (size_t)ctx->N * db, ctx->q, lambda, msg);
   if (rc != LBM_OK) return set_err(nullptr, rc, msg);

@@ -223,9 +223,15 @@ __device__ __forceinline__ R collide_bulk_vjp(const R g[Q], const R mu[Q], R phi
 // tensor argument: sum_i mu_i w_i T3(A)_i = sum_k <A, P_k> M_k / |P_k|^2 with
 // M_k = sum_i mu_i w_i P_k(c_i)).  The outputs depend on g only through its
 // moments.
-template <int Q, typename R, bool POROUS, typename OUT>
+//
+// HYB = true: the hybrid of Eq. (7) with the finite-difference strain Sfd of
+// the step's velocity field: the second-order coefficient is
+// h = sigma Pi - fs Sfd, fs = (1 - sigma) 2 rho c_s^2 tau, and the third-order
+// part keeps the factor sigma; the adjoint of Sfd (its six components) goes
+// to Sb.
+template <int Q, typename R, bool POROUS, bool HYB = false, typename OUT>
 __device__ __forceinline__ R collide_bulk_rr_vjp(const R g[Q], const R mu[Q], R phi, R smag, const KArgs &k, OUT out,
-                                                 R &smagb) {
+                                                 R &smagb, const R *Sfd = nullptr, R *Sb = nullptr) {
   // ---- forward recomputation
   R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
   R mxx = R(0), myy = R(0), mzz = R(0), mxy = R(0), mxz = R(0), myz = R(0);
@@ -264,7 +270,20 @@ __device__ __forceinline__ R collide_bulk_rr_vjp(const R g[Q], const R mu[Q], R 
   const R vx = POROUS ? phi * ux : ux, vy = POROUS ? phi * uy : uy, vz = POROUS ? phi * uz : uz;
   const R vv = vx * vx + vy * vy + vz * vz;
   const R uF = ux * Fx + uy * Fy + uz * Fz;
-  const R tr3 = (pxx + pyy + pzz) * cs2;
+  R sig = R(1), fs = R(0);
+  R hxx = pxx, hyy = pyy, hzz = pzz, hxy = pxy, hxz = pxz, hyz = pyz;  // second-order coefficient
+  if constexpr (HYB) {
+    const R fw = R(k.fdw);
+    sig = R(1) - fw;
+    fs = fw * R(2.0 / 3.0) * rho * tau;
+    hxx = sig * pxx - fs * Sfd[0];
+    hyy = sig * pyy - fs * Sfd[1];
+    hzz = sig * pzz - fs * Sfd[2];
+    hxy = sig * pxy - fs * Sfd[3];
+    hxz = sig * pxz - fs * Sfd[4];
+    hyz = sig * pyz - fs * Sfd[5];
+  }
+  const R tr3 = (hxx + hyy + hzz) * cs2;
   R A1[7], K1[7];
   A1[0] = R(2) * ux * pxy + uy * pxx;
   A1[1] = R(2) * ux * pxz + uz * pxx;
@@ -294,14 +313,14 @@ __device__ __forceinline__ R collide_bulk_rr_vjp(const R g[Q], const R mu[Q], R 
     const R cv = dot3(cx, cy, cz, vx, vy, vz);
     const R cF = dot3(cx, cy, cz, Fx, Fy, Fz);
     R cPc = R(0);
-    acc(cPc, cx * cx, pxx);
-    acc(cPc, cy * cy, pyy);
-    acc(cPc, cz * cz, pzz);
-    acc(cPc, cx * cy, R(2) * pxy);
-    acc(cPc, cx * cz, R(2) * pxz);
-    acc(cPc, cy * cz, R(2) * pyz);
+    acc(cPc, cx * cx, hxx);
+    acc(cPc, cy * cy, hyy);
+    acc(cPc, cz * cz, hzz);
+    acc(cPc, cx * cy, R(2) * hxy);
+    acc(cPc, cx * cz, R(2) * hxz);
+    acc(cPc, cy * cz, R(2) * hyz);
     const R t1 = third_term<Q, R>(i, K1);
-    c1b += mw * (R(-1.5) * cF + R(4.5) * (cPc - tr3) + t1);
+    c1b += mw * (R(-1.5) * cF + R(4.5) * (cPc - tr3) + sig * t1);
     c2b += mw * (R(3) * (cF - uF) + R(9) * cu * cF);
     s0 += mw;
     s1 += mw * (R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv);
@@ -353,15 +372,35 @@ __device__ __forceinline__ R collide_bulk_rr_vjp(const R g[Q], const R mu[Q], R 
   vxb += rho * (Ab[0] * R(2) * vx * vy + Ab[1] * R(2) * vx * vz + Ab[2] * vy * vy + Ab[4] * vz * vz + Ab[6] * vy * vz);
   vyb += rho * (Ab[0] * vx * vx + Ab[2] * R(2) * vx * vy + Ab[3] * R(2) * vy * vz + Ab[5] * vz * vz + Ab[6] * vx * vz);
   vzb += rho * (Ab[1] * vx * vx + Ab[3] * vy * vy + Ab[4] * R(2) * vx * vz + Ab[5] * R(2) * vy * vz + Ab[6] * vx * vy);
-  // regularized f^(1), times c1: Pi directly, and Pi and u through A1
+  // regularized f^(1), times c1: the second-order coefficient directly, and Pi and u through A1
   R pxxb = c1 * R(4.5) * (pbxx - cs2 * pbtr), pyyb = c1 * R(4.5) * (pbyy - cs2 * pbtr),
     pzzb = c1 * R(4.5) * (pbzz - cs2 * pbtr);
   R pxyb = c1 * R(9) * pbxy, pxzb = c1 * R(9) * pbxz, pyzb = c1 * R(9) * pbyz;
+  R tau_h = R(0);  // adjoint of tau through fs (hybrid)
+  if constexpr (HYB) {
+    // h = sigma Pi - fs Sfd: to Sfd, to fs (then rho and tau), and sigma to Pi
+    const R fsb = -(pxxb * Sfd[0] + pyyb * Sfd[1] + pzzb * Sfd[2] + pxyb * Sfd[3] + pxzb * Sfd[4] + pyzb * Sfd[5]);
+    Sb[0] = -fs * pxxb;
+    Sb[1] = -fs * pyyb;
+    Sb[2] = -fs * pzzb;
+    Sb[3] = -fs * pxyb;
+    Sb[4] = -fs * pxzb;
+    Sb[5] = -fs * pyzb;
+    pxxb *= sig;
+    pyyb *= sig;
+    pzzb *= sig;
+    pxyb *= sig;
+    pxzb *= sig;
+    pyzb *= sig;
+    const R fw = R(k.fdw);
+    rhob += fsb * fw * R(2.0 / 3.0) * tau;
+    tau_h = fsb * fw * R(2.0 / 3.0) * rho;
+  }
   R uxb = R(0), uyb = R(0), uzb = R(0);
   {
     R B[7];
 #pragma unroll
-    for (int m = 0; m < 7; ++m) B[m] = c1 * Ab[m];
+    for (int m = 0; m < 7; ++m) B[m] = c1 * sig * Ab[m];
     // A1: xxy = 2 ux pxy + uy pxx; xxz = 2 ux pxz + uz pxx; xyy = 2 uy pxy + ux pyy;
     //     yyz = 2 uy pyz + uz pyy; xzz = 2 uz pxz + ux pzz; yzz = 2 uz pyz + uy pzz;
     //     xyz = ux pyz + uy pxz + uz pxy
@@ -393,7 +432,7 @@ __device__ __forceinline__ R collide_bulk_rr_vjp(const R g[Q], const R mu[Q], R 
   }
   // relaxation rate: om = 1/tau, tau = (tau0 + sqrt(A))/2, A = tau0^2 + smag pn / rho
   const R omb = -c1b - R(0.5) * c2b;
-  const R taub = -omb * om * om;
+  const R taub = -omb * om * om + tau_h;
   const R Abar = R(0.5) * taub / (R(2) * sA);
   const R pnb = Abar * smag * ir;
   R irb = Abar * smag * pn;
@@ -680,15 +719,21 @@ __device__ __forceinline__ CellSeed cell_seed(const R g[Q], int x, int p0, int p
 
 // SEED = true (time-averaged objectives): the step also adds w dJ/df of the
 // state it reads (the objective's seed at that step), after the transpose.
-template <int Q, typename S, bool ODD, bool POROUS, int SOLID, bool RR, bool SEED = false, bool OPEN = false>
+// HYB = true (hybrid collision, with RR): the finite-difference strain of the
+// step's velocity field (k.vel) is held fixed here and its adjoint written to
+// sbar[6][N]; k_adjoint_fd then carries it to the velocities it came from.
+template <int Q, typename S, bool ODD, bool POROUS, int SOLID, bool RR, bool SEED = false, bool OPEN = false,
+          bool HYB = false>
 __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                     typename Store<S>::R *__restrict__ dev,
                                                     const double *__restrict__ m_prev, double *__restrict__ m_next,
                                                     const typename Store<S>::R *__restrict__ phi,
                                                     double *__restrict__ grad, double *__restrict__ gcs, KArgs k,
                                                     ATiles t, int p0 = 0, int p1 = 0,
-                                                    const double *__restrict__ cnt = nullptr, double sw = 0.0) {
+                                                    const double *__restrict__ cnt = nullptr, double sw = 0.0,
+                                                    typename Store<S>::R *__restrict__ sbar = nullptr) {
   using R = typename Store<S>::R;
+  static_assert(!HYB || (RR && !OPEN), "the hybrid collision comes with RR and without open faces");
   int x, y, z;
   if (!atile_xyz(k, t, x, y, z)) return;
   const Nb n = make_nb(x, y, z, k);
@@ -770,8 +815,17 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint(const S *__restrict__ pop, c
       return;
     }
   }
-  if constexpr (RR) phib = collide_bulk_rr_vjp<Q, R, POROUS>(g, dmu, ph, smag, k, store, smagb);
-  else phib = collide_bulk_vjp<Q, R, POROUS>(g, dmu, ph, smag, k, store, smagb);
+  if constexpr (HYB) {
+    R Sfd[6], Sb[6];
+    fd_strain<R>(n, k, Sfd);
+    phib = collide_bulk_rr_vjp<Q, R, POROUS, true>(g, dmu, ph, smag, k, store, smagb, Sfd, Sb);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) sbar[(size_t)m * N + n.cell] = Sb[m];
+  } else if constexpr (RR) {
+    phib = collide_bulk_rr_vjp<Q, R, POROUS>(g, dmu, ph, smag, k, store, smagb);
+  } else {
+    phib = collide_bulk_vjp<Q, R, POROUS>(g, dmu, ph, smag, k, store, smagb);
+  }
   m_next[n.cell] = SEED ? m + cs.base : m;
   if (POROUS) grad[n.cell] += (double)phib;
   add_cs();
@@ -797,9 +851,14 @@ struct WallBar {
 // (c.t)(c.n), Guo source at v; third-order equilibrium with RR) in precision
 // R, for the record held fixed: the adjoint of input population i goes to
 // out(i, value); the adjoints of the record's values to rb.
+// With Sfd (hybrid collision) the non-equilibrium is the full one,
+// -3 w rho tau (c.S'.c - c_s^2 tr S') with S' = S + (e n^T + n e^T),
+// e = (G/2) t - (S n - (n.S.n) n), and the adjoint of the finite-difference
+// strain S goes to Sb.
 template <int Q, typename R, bool RR, typename OUT>
 __device__ __forceinline__ void wall_collide_vjp(const R g[Q], const R mu[Q], const R nv[3], const R tv[3], R utan,
-                                                 R G, R tau, const KArgs &k, OUT out, WallBar<R> &rb) {
+                                                 R G, R tau, const KArgs &k, OUT out, WallBar<R> &rb,
+                                                 const R *Sfd = nullptr, R *Sb = nullptr) {
   // ---- forward recomputation (as in the wall kernel)
   R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
 #pragma unroll
@@ -821,8 +880,25 @@ __device__ __forceinline__ void wall_collide_vjp(const R g[Q], const R mu[Q], co
   const R om = R(1) / tau;
   const R c1 = R(1) - om, c2 = R(1) - R(0.5) * om;
   const R fd = R(-3) * rho * tau * G;
+  const bool full = Sfd != nullptr;
+  const R hg = R(0.5) * G;
+  R Sw[6] = {};
+  if (full) {
+    const R snx = Sfd[0] * nx + Sfd[3] * ny + Sfd[4] * nz;
+    const R sny = Sfd[3] * nx + Sfd[1] * ny + Sfd[5] * nz;
+    const R snz = Sfd[4] * nx + Sfd[5] * ny + Sfd[2] * nz;
+    const R nSn = nx * snx + ny * sny + nz * snz;
+    const R ex = hg * tx - (snx - nSn * nx), ey = hg * ty - (sny - nSn * ny), ez = hg * tz - (snz - nSn * nz);
+    Sw[0] = Sfd[0] + R(2) * ex * nx;
+    Sw[1] = Sfd[1] + R(2) * ey * ny;
+    Sw[2] = Sfd[2] + R(2) * ez * nz;
+    Sw[3] = Sfd[3] + ex * ny + nx * ey;
+    Sw[4] = Sfd[4] + ex * nz + nx * ez;
+    Sw[5] = Sfd[5] + ey * nz + ny * ez;
+  }
   // ---- reverse through the outputs
   R s0 = R(0), s1 = R(0), stn = R(0), sg = R(0);
+  R qxx = R(0), qyy = R(0), qzz = R(0), qxy = R(0), qxz = R(0), qyz = R(0);  // sum mu w c c
   R evx = R(0), evy = R(0), evz = R(0);  // sum mu w (3 + 9 c.v) c
   R gux = R(0), guy = R(0), guz = R(0);  // sum mu w 9 (c.F) c
   R snx = R(0), sny = R(0), snz = R(0);  // sum mu w (c.n) c
@@ -853,6 +929,12 @@ __device__ __forceinline__ void wall_collide_vjp(const R g[Q], const R mu[Q], co
     acc(snx, cx, tn);
     acc(sny, cy, tn);
     acc(snz, cz, tn);
+    acc(qxx, cx * cx, mw);
+    acc(qyy, cy * cy, mw);
+    acc(qzz, cz * cz, mw);
+    acc(qxy, cx * cy, mw);
+    acc(qxz, cx * cz, mw);
+    acc(qyz, cy * cz, mw);
     if constexpr (RR) {
 #pragma unroll
       for (int kk = 0; kk < H3Basis<Q>::n; ++kk) {
@@ -861,9 +943,24 @@ __device__ __forceinline__ void wall_collide_vjp(const R g[Q], const R mu[Q], co
       }
     }
   }
+  // full strain: sum_i mu_i w_i (c.S'.c - c_s^2 tr S') = W . S' (Z), with
+  // W the derivative in the six components xx, yy, zz, xy, xz, yz
+  R W[6] = {}, Z = R(0);
+  if (full) {
+    W[0] = qxx - s0 * R(1.0 / 3.0);
+    W[1] = qyy - s0 * R(1.0 / 3.0);
+    W[2] = qzz - s0 * R(1.0 / 3.0);
+    W[3] = R(2) * qxy;
+    W[4] = R(2) * qxz;
+    W[5] = R(2) * qyz;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) Z += W[m] * Sw[m];
+  }
+  // the non-equilibrium's sum: sum_i mu_i f^(1,FD)_i / (-3 rho tau)
+  const R zs = full ? Z : G * stn;
   // equilibrium and Guo source: drho directly, rho, and v
   R drhob = s0;
-  R rhob = s1 + c1 * R(-3) * tau * G * stn;
+  R rhob = s1 + c1 * R(-3) * tau * zs;
   R vxb = rho * (evx - R(3) * vx * s0) + c2 * (gux - R(3) * Fx * s0);
   R vyb = rho * (evy - R(3) * vy * s0) + c2 * (guy - R(3) * Fy * s0);
   R vzb = rho * (evz - R(3) * vz * s0) + c2 * (guz - R(3) * Fz * s0);
@@ -887,13 +984,36 @@ __device__ __forceinline__ void wall_collide_vjp(const R g[Q], const R mu[Q], co
     vyb += rho * (Ab[0] * vx * vx + Ab[2] * R(2) * vx * vy + Ab[3] * R(2) * vy * vz + Ab[5] * vz * vz + Ab[6] * vx * vz);
     vzb += rho * (Ab[1] * vx * vx + Ab[3] * vy * vy + Ab[4] * R(2) * vx * vz + Ab[5] * R(2) * vy * vz + Ab[6] * vx * vy);
   }
-  // the record: c1 fd w (c.t)(c.n) and v = u_tan t + un n
-  rb.tau = stn * (fd * om * om + c1 * R(-3) * rho * G) + sg * R(0.5) * om * om;
-  rb.G = stn * c1 * R(-3) * rho * tau;
+  // the record: c1 f^(1,FD) (with tau, and G and t through it) and v = u_tan t + un n
+  rb.tau = zs * (R(-3) * rho * tau * om * om + c1 * R(-3) * rho) + sg * R(0.5) * om * om;
   rb.utan = vxb * tx + vyb * ty + vzb * tz;
-  rb.t[0] = c1 * fd * snx + utan * vxb;
-  rb.t[1] = c1 * fd * sny + utan * vyb;
-  rb.t[2] = c1 * fd * snz + utan * vzb;
+  if (full) {
+    // S' = S + e n^T + n e^T: to S directly and to e; e = (G/2) t - P S n, P = I - n n^T
+    R Swb[6];
+    const R cz = c1 * R(-3) * rho * tau;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) Swb[m] = cz * W[m];
+    const R ebx = R(2) * nx * Swb[0] + ny * Swb[3] + nz * Swb[4];
+    const R eby = R(2) * ny * Swb[1] + nx * Swb[3] + nz * Swb[5];
+    const R ebz = R(2) * nz * Swb[2] + nx * Swb[4] + ny * Swb[5];
+    rb.G = R(0.5) * (tx * ebx + ty * eby + tz * ebz);
+    rb.t[0] = hg * ebx + utan * vxb;
+    rb.t[1] = hg * eby + utan * vyb;
+    rb.t[2] = hg * ebz + utan * vzb;
+    const R ne = nx * ebx + ny * eby + nz * ebz;
+    const R sbx = -(ebx - ne * nx), sby = -(eby - ne * ny), sbz = -(ebz - ne * nz);  // adjoint of S n
+    Sb[0] = Swb[0] + sbx * nx;
+    Sb[1] = Swb[1] + sby * ny;
+    Sb[2] = Swb[2] + sbz * nz;
+    Sb[3] = Swb[3] + sbx * ny + sby * nx;
+    Sb[4] = Swb[4] + sbx * nz + sbz * nx;
+    Sb[5] = Swb[5] + sby * nz + sbz * ny;
+  } else {
+    rb.G = stn * c1 * R(-3) * rho * tau;
+    rb.t[0] = c1 * fd * snx + utan * vxb;
+    rb.t[1] = c1 * fd * sny + utan * vyb;
+    rb.t[2] = c1 * fd * snz + utan * vzb;
+  }
   // the cell's own velocity enters through un = u.n; u = (j + F/2)/rho
   const R unb = vxb * nx + vyb * ny + vzb * nz;
   const R uxb = unb * nx, uyb = unb * ny, uzb = unb * nz;
@@ -967,7 +1087,8 @@ __global__ __launch_bounds__(256) void k_adjoint_wall(const S *__restrict__ pop,
                                                       const double *__restrict__ rec, int nwall,
                                                       const uint64_t *__restrict__ wmask, double *__restrict__ wadj,
                                                       double *__restrict__ gcs, KArgs k, int p0, int p1,
-                                                      const double *__restrict__ cnt, double sw) {
+                                                      const double *__restrict__ cnt, double sw,
+                                                      typename Store<S>::R *__restrict__ sbar) {
   using R = typename Store<S>::R;
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nwall) return;
@@ -1010,7 +1131,16 @@ __global__ __launch_bounds__(256) void k_adjoint_wall(const S *__restrict__ pop,
     if constexpr (SEED) v += (R)cs.template kin<Q>(i);
     dev[read_slot<Q, ODD, SLIP>(n, sm, i, N)] = v;
   };
-  wall_collide_vjp<Q, R, RR>(g, dmu, nv, tv, R(wr.utan), R(wr.G), R(wr.tau), k, store, rb);
+  if (k.fdw > 0.0) {
+    // hybrid collision: the full finite-difference strain (adjoint to sbar, for k_adjoint_fd)
+    R Sfd[6], Sb[6];
+    fd_strain<R>(n, k, Sfd);
+    wall_collide_vjp<Q, R, RR>(g, dmu, nv, tv, R(wr.utan), R(wr.G), R(wr.tau), k, store, rb, Sfd, Sb);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) sbar[(size_t)m * N + n.cell] = Sb[m];
+  } else {
+    wall_collide_vjp<Q, R, RR>(g, dmu, nv, tv, R(wr.utan), R(wr.G), R(wr.tau), k, store, rb);
+  }
   m_next[n.cell] = SEED ? m + cs.base : m;
   const double tb[3] = {(double)rb.t[0], (double)rb.t[1], (double)rb.t[2]};
   double rhob, jb[3], C2b;
@@ -1059,6 +1189,89 @@ __global__ __launch_bounds__(256) void k_adjoint_ref(const uint8_t *__restrict__
     acc(v, Lat<Q>::c(i, 2), az);
     R *p = dev + read_slot<Q, ODD, SLIP>(n, sm, i, N);
     *p = (R)((double)*p + v);
+  }
+}
+
+// Hybrid collision, second pass of the reverse step: the adjoints of the
+// cells' finite-difference strains (sbar, written by the first pass) go back
+// to the velocities their stencils read, and from the velocity
+// u = (j + F/2)/rho of each cell to its populations, d u_b / d f_i =
+// (c_ib - u_b) / rho.  One thread per fluid cell, gathering from the cell
+// itself and its six axis neighbours: along axis a, a central difference
+// 0.5 (u(z + e_a) - u(z - e_a)) sends +/- 0.5 of row a of the gradient's
+// adjoint to the two neighbours, a one-sided one sends +/- 1 to the
+// neighbour and to z.  Every fluid cell but the lid's took a strain.
+template <int Q, typename S, bool ODD, int SOLID>
+__global__ __launch_bounds__(ABLOCK) void k_adjoint_fd(const uint8_t *__restrict__ flags,
+                                                       typename Store<S>::R *__restrict__ dev,
+                                                       const typename Store<S>::R *__restrict__ sbar, KArgs k,
+                                                       ATiles t) {
+  using R = typename Store<S>::R;
+  int x, y, z;
+  if (!atile_xyz(k, t, x, y, z)) return;
+  const Nb n = make_nb(x, y, z, k);
+  const uint8_t fl = flags[n.cell];
+  if (!(fl & FL_FLUID)) return;
+  const size_t N = (size_t)k.N;
+  auto fluid = [&](int c) { return (flags[c] & FL_FLUID) != 0; };
+  auto strained = [&](int c) { return (flags[c] & (FL_FLUID | FL_LID)) == FL_FLUID; };
+  // row a of the adjoint of D (D_ab = d_a u_b): S_aa = D_aa, S_ab = (D_ab + D_ba) / 2
+  auto row = [&](int c, int a, R r[3]) {
+    constexpr int idx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+#pragma unroll
+    for (int b = 0; b < 3; ++b) r[b] = (a == b ? R(1) : R(0.5)) * sbar[(size_t)idx[a][b] * N + (size_t)c];
+  };
+  const int pos[3] = {x, y, z}, ext[3] = {k.nx, k.ny, k.nz};
+  R ub[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R r[3];
+    const bool hm = !((n.out >> (2 * a)) & 1u), hp = !((n.out >> (2 * a + 1)) & 1u);
+    const int cm = n.cell + n.d[a][0], cp = n.cell + n.d[a][1];
+    const bool fm = hm && fluid(cm), fp = hp && fluid(cp);
+    // the cell's own strain: a one-sided difference reads its velocity
+    if (fp != fm && strained(n.cell)) {
+      row(n.cell, a, r);
+      const R sg = fp ? R(-1) : R(1);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) ub[b] += sg * r[b];
+    }
+    // the neighbour below along a (this cell is its upper neighbour)
+    if (fm && strained(cm)) {
+      int q[3] = {pos[0], pos[1], pos[2]};
+      q[a] = pos[a] == 0 ? ext[a] - 1 : pos[a] - 1;
+      const Nb nm = make_nb(q[0], q[1], q[2], k);
+      const bool both = !((nm.out >> (2 * a)) & 1u) && fluid(cm + nm.d[a][0]);
+      row(cm, a, r);
+      const R wgt = both ? R(0.5) : R(1);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) ub[b] += wgt * r[b];
+    }
+    // the neighbour above along a (this cell is its lower neighbour)
+    if (fp && strained(cp)) {
+      int q[3] = {pos[0], pos[1], pos[2]};
+      q[a] = pos[a] == ext[a] - 1 ? 0 : pos[a] + 1;
+      const Nb np = make_nb(q[0], q[1], q[2], k);
+      const bool both = !((np.out >> (2 * a + 1)) & 1u) && fluid(cp + np.d[a][1]);
+      row(cp, a, r);
+      const R wgt = both ? R(0.5) : R(1);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) ub[b] -= wgt * r[b];
+    }
+  }
+  const V4<R> v = static_cast<const V4<R> *>(k.vel)[n.cell];
+  const R ir = R(1) / v.w;
+  const R base = -(ub[0] * v.x + ub[1] * v.y + ub[2] * v.z) * ir;
+  LinkMask sm = 0;
+  if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q, SOLID == 2>(n, flags);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    R d = base;
+    acc(d, Lat<Q>::c(i, 0), ub[0] * ir);
+    acc(d, Lat<Q>::c(i, 1), ub[1] * ir);
+    acc(d, Lat<Q>::c(i, 2), ub[2] * ir);
+    R *p = dev + read_slot<Q, ODD, SOLID == 2>(n, sm, i, N);
+    *p += d;
   }
 }
 
@@ -1180,13 +1393,16 @@ struct AdjPtrs {
   double *m_cur, *m_other;
   void *dev;
   double *wadj;  // [4][nwall] (wall model)
+  void *sbar;    // [6][N] compute type (hybrid collision)
 };
 static AdjPtrs adj_ptrs(lbm_ctx *ctx, void *lamv) {
-  const AdjLayout L = adj_layout(ctx->N, ctx->q, ctx->p.storage == LBM_F64 ? 8 : 4, ctx->nwall);
+  const bool fd = ctx->ka.fdw > 0.0;
+  const AdjLayout L = adj_layout(ctx->N, ctx->q, ctx->p.storage == LBM_F64 ? 8 : 4, ctx->nwall, fd);
   double *m0 = (double *)lamv, *m1 = m0 + ctx->N;
   const bool odd = (ctx->steps & 1) != 0;
   return {odd ? m1 : m0, odd ? m0 : m1, (char *)lamv + L.d_off,
-          ctx->nwall > 0 ? (double *)((char *)lamv + L.wadj_off) : nullptr};
+          ctx->nwall > 0 ? (double *)((char *)lamv + L.wadj_off) : nullptr,
+          fd ? (void *)((char *)lamv + L.sbar_off) : nullptr};
 }
 
 // The reverse step for one lattice and storage type.  Its kernels are many
@@ -1206,11 +1422,26 @@ int adjoint_step_qs(lbm_ctx *ctx, void *lamv, void *gradv, void *gcsv, double se
     // reads the common modes of the later state (the other parity), writes this parity's
     const int p0 = planes ? planes[0] : 0, p1 = planes ? planes[1] : 0;
     const double *cnt = ctx->result + 8 + 3;  // fluid-cell counts of the last objective evaluation
+    R *sbar = (R *)a.sbar;
+    const bool hyb = ctx->ka.fdw > 0.0;
+    if (hyb) {
+      // the hybrid's velocity field of the state this step reads
+      const int rc = dev_velocity4(ctx);
+      if (rc != LBM_OK) return rc;
+    }
     auto go = [&](auto kern) {
       kern<<<t.nblocks, ABLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, dev, a.m_other, a.m_cur, phi,
-                                                  grad, gcs, ctx->ka, t, p0, p1, cnt, seed_w);
+                                                  grad, gcs, ctx->ka, t, p0, p1, cnt, seed_w, sbar);
     };
     auto by_seed = [&]<bool POROUS, bool RR>() {
+      if constexpr (RR) {
+        // the hybrid collision (never with open faces)
+        if (hyb) {
+          if (seed_w != 0.0) go(k_adjoint<Q, S, ODD, POROUS, SOLID, true, true, false, true>);
+          else go(k_adjoint<Q, S, ODD, POROUS, SOLID, true, false, false, true>);
+          return;
+        }
+      }
       // open x faces make x non-periodic, so their domains always have solid links
       if constexpr (SOLID) {
         if (ctx->has_open) {
@@ -1230,14 +1461,21 @@ int adjoint_step_qs(lbm_ctx *ctx, void *lamv, void *gradv, void *gcsv, double se
       else by_seed.template operator()<false, false>();
     }
     int rc = check(ctx, "k_adjoint");
-    if (rc != LBM_OK || ctx->nwall == 0) return rc;
+    // the strains' adjoints to the velocities, once every cell has written its own
+    auto fd_pass = [&]() -> int {
+      if (!hyb) return LBM_OK;
+      k_adjoint_fd<Q, S, ODD, SOLID><<<t.nblocks, ABLOCK, 0, ctx->stream>>>(ctx->flags, dev, sbar, ctx->ka, t);
+      return check(ctx, "k_adjoint_fd");
+    };
+    if (rc != LBM_OK) return rc;
+    if (ctx->nwall == 0) return fd_pass();
     if constexpr (SOLID) {
       // wall cells, then their contributions to the reference cells
       const int nw = ctx->nwall, wb = (nw + 255) / 256;
       auto gow = [&](auto kern) {
         kern<<<wb, 256, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags, dev, a.m_other, a.m_cur, ctx->wcell,
                                          ctx->wref, ctx->wrec, nw, ctx->wmask, a.wadj, gcs, ctx->ka, p0, p1, cnt,
-                                         seed_w);
+                                         seed_w, sbar);
       };
       constexpr bool SLIP = SOLID == 2;
       if (ctx->ka.rr) {
@@ -1252,7 +1490,9 @@ int adjoint_step_qs(lbm_ctx *ctx, void *lamv, void *gradv, void *gcsv, double se
       const int rb = (ctx->nref + 255) / 256;
       k_adjoint_ref<Q, S, ODD, SLIP><<<rb, 256, 0, ctx->stream>>>(ctx->flags, dev, ctx->wref_cell, ctx->wref_off,
                                                           ctx->wref_rec, ctx->nref, a.wadj, nw, ctx->ka);
-      return check(ctx, "k_adjoint_ref");
+      rc = check(ctx, "k_adjoint_ref");
+      if (rc != LBM_OK) return rc;
+      return fd_pass();
     }
     return rc;
   };

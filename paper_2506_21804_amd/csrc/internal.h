@@ -54,7 +54,7 @@ struct KArgs {
   int slip;          // full-slip box faces (lbm_params.slip bits)
   int open_x;        // 1: inlet / outlet on the x faces
   double rho_out;    // outlet density
-  const void *vel;   // [N] (u_x, u_y, u_z, fluid 1/0) of the current step, compute type (fdw > 0)
+  const void *vel;   // [N] (u_x, u_y, u_z, rho) of the current step at fluid cells, 0 elsewhere, compute type (fdw > 0)
   const void *uin;   // [nz] fringe inflow profile, compute type
   const void *lam;   // [nx] fringe blend weight, compute type (0 before the fringe)
   const void *inflow;  // [3][ny nz] inlet velocity, compute type (open_x)
@@ -67,15 +67,21 @@ struct KArgs {
 // (FP64 for FP64 storage, FP32 otherwise).  Two arrays of N doubles, then q
 // arrays of N deviations from a 256-byte boundary, then (wall model) four
 // doubles per wall record from a 256-byte boundary: the reverse step's
-// adjoint of each record's reference-cell density and momentum.
+// adjoint of each record's reference-cell density and momentum; then (hybrid
+// collision) six arrays of N values in the compute type from a 256-byte
+// boundary: the adjoint of each cell's finite-difference strain.
 struct AdjLayout {
-  size_t d_off, wadj_off, bytes;
+  size_t d_off, wadj_off, sbar_off, bytes;
 };
-inline AdjLayout adj_layout(long long N, int q, size_t dev_bytes, long long nwall) {
+inline AdjLayout adj_layout(long long N, int q, size_t dev_bytes, long long nwall, bool fd) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
   AdjLayout L;
-  L.d_off = ((size_t)2 * (size_t)N * sizeof(double) + 255) & ~(size_t)255;
-  L.wadj_off = (L.d_off + (size_t)q * (size_t)N * dev_bytes + 255) & ~(size_t)255;
-  L.bytes = nwall > 0 ? L.wadj_off + (size_t)4 * (size_t)nwall * sizeof(double) : L.d_off + (size_t)q * (size_t)N * dev_bytes;
+  L.d_off = up((size_t)2 * (size_t)N * sizeof(double));
+  L.wadj_off = up(L.d_off + (size_t)q * (size_t)N * dev_bytes);
+  size_t end = nwall > 0 ? L.wadj_off + (size_t)4 * (size_t)nwall * sizeof(double) : L.d_off + (size_t)q * (size_t)N * dev_bytes;
+  L.sbar_off = up(end);
+  if (fd) end = L.sbar_off + (size_t)6 * (size_t)N * dev_bytes;
+  L.bytes = end;
   return L;
 }
 
@@ -180,6 +186,8 @@ int dev_step(lbm_ctx *ctx);  // one time step at parity ctx->steps & 1
 // the collision; mean time per launch from events.  Synchronises.
 int dev_stream_probe(lbm_ctx *ctx, int n, double *ms_per_launch);
 int dev_moments(lbm_ctx *ctx, void *rho, void *u);
+// the hybrid's velocity field (ctx->vel) of the current state (fdw > 0)
+int dev_velocity4(lbm_ctx *ctx);
 int dev_reduce_diag(lbm_ctx *ctx);  // writes result[0..3]
 // Looks up (once per device) the address of the static scratch array and
 // stores it in ctx->scratch; the current device must be the context's.

@@ -120,45 +120,6 @@ __device__ __forceinline__ void lid_equilibrium(R g[Q], const KArgs &k) {
   }
 }
 
-// Strain rate S = (D + D^T)/2 of the step's velocity field at cell n, with
-// D_ab = d_a u_b by central differences; one-sided where one neighbour along
-// the axis is solid or outside a non-periodic axis, zero where both are
-// (hybrid collision, Sec. 2.2, Eq. (10)).  S[0..5] = xx, yy, zz, xy, xz, yz.
-// The velocity field of the hybrid is one vector per cell, (u_x, u_y, u_z,
-// 1 for a fluid cell / 0 otherwise): a neighbour's velocity and whether it is
-// fluid come in one vector load.
-template <typename R>
-struct alignas(4 * sizeof(R)) V4 {
-  R x, y, z, w;
-};
-
-template <typename R>
-__device__ __forceinline__ void fd_strain(const Nb &n, const KArgs &k, R S[6]) {
-  const V4<R> *v = static_cast<const V4<R> *>(k.vel);
-  const V4<R> c = v[n.cell];
-  R D[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const V4<R> zero = {R(0), R(0), R(0), R(0)};
-    const V4<R> P = ((n.out >> (2 * a + 1)) & 1u) ? zero : v[n.cell + n.d[a][1]];
-    const V4<R> M = ((n.out >> (2 * a)) & 1u) ? zero : v[n.cell + n.d[a][0]];
-    const bool fp = P.w > R(0.5), fm = M.w > R(0.5);
-    const R up[3] = {P.x, P.y, P.z}, um[3] = {M.x, M.y, M.z}, uc[3] = {c.x, c.y, c.z};
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      if (fp && fm) D[a][b] = R(0.5) * (up[b] - um[b]);
-      else if (fp) D[a][b] = up[b] - uc[b];
-      else if (fm) D[a][b] = uc[b] - um[b];
-      else D[a][b] = R(0);
-    }
-  }
-  S[0] = D[0][0];
-  S[1] = D[1][1];
-  S[2] = D[2][2];
-  S[3] = R(0.5) * (D[0][1] + D[1][0]);
-  S[4] = R(0.5) * (D[0][2] + D[2][0]);
-  S[5] = R(0.5) * (D[1][2] + D[2][1]);
-}
 
 // Bulk collision on deviations g (sigma = 1): BGK with tau_eff from the
 // non-equilibrium stress, homogenized velocity u_hat = phi u, Guo forcing.
@@ -790,7 +751,7 @@ __device__ __forceinline__ bool gather_state(const S *__restrict__ pop, const ui
   return true;
 }
 
-// The hybrid's velocity field: (Guo velocity, 1) at fluid cells, 0 elsewhere.
+// The hybrid's velocity field: (Guo velocity, rho) at fluid cells, 0 elsewhere.
 template <int Q, typename S, bool ODD, int SOLID>
 __global__ __launch_bounds__(BLOCK) void k_velocity4(const S *__restrict__ pop, const uint8_t *__restrict__ flags,
                                                      V4<typename Store<S>::R> *__restrict__ out, KArgs k, Tiles t) {
@@ -813,7 +774,7 @@ __global__ __launch_bounds__(BLOCK) void k_velocity4(const S *__restrict__ pop, 
   }
   const R rho = R(1) + drho;
   out[n.cell] = V4<R>{(jx + R(0.5) * R(k.F[0])) / rho, (jy + R(0.5) * R(k.F[1])) / rho,
-                      (jz + R(0.5) * R(k.F[2])) / rho, R(1)};
+                      (jz + R(0.5) * R(k.F[2])) / rho, rho};
 }
 
 template <int Q, typename S, bool ODD, int SOLID>
@@ -1197,6 +1158,18 @@ int dev_step(lbm_ctx *ctx) {
   });
 }
 
+
+int dev_velocity4(lbm_ctx *ctx) {
+  const Tiles t = tiles_of(ctx->ka);
+  return dispatch(ctx, [&]<int Q, typename S>() {
+    using R = typename Store<S>::R;
+    return by_parity(ctx, [&]<bool ODD, int SOLID>() {
+      k_velocity4<Q, S, ODD, SOLID><<<t.nblocks, BLOCK, 0, ctx->stream>>>((const S *)ctx->pop, ctx->flags,
+                                                                        (V4<R> *)ctx->vel, ctx->ka, t);
+      return check_launch(ctx, "k_velocity4");
+    });
+  });
+}
 
 int dev_moments(lbm_ctx *ctx, void *rho, void *u) {
   const Tiles t = tiles_of(ctx->ka);

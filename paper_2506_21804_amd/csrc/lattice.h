@@ -421,4 +421,45 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
   return x * q + (x < r ? x : r) + s;
 }
 
+
+// Strain rate S = (D + D^T)/2 of the step's velocity field at cell n, with
+// D_ab = d_a u_b by central differences; one-sided where one neighbour along
+// the axis is solid or outside a non-periodic axis, zero where both are
+// (hybrid collision, Sec. 2.2, Eq. (10)).  S[0..5] = xx, yy, zz, xy, xz, yz.
+// The velocity field of the hybrid is one vector per cell, (u_x, u_y, u_z,
+// rho) at a fluid cell and 0 elsewhere (rho > 0 marks the fluid cells): a
+// neighbour's velocity and whether it is fluid come in one vector load.
+template <typename R>
+struct alignas(4 * sizeof(R)) V4 {
+  R x, y, z, w;
+};
+
+template <typename R>
+__device__ __forceinline__ void fd_strain(const Nb &n, const KArgs &k, R S[6]) {
+  const V4<R> *v = static_cast<const V4<R> *>(k.vel);
+  const V4<R> c = v[n.cell];
+  R D[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const V4<R> zero = {R(0), R(0), R(0), R(0)};
+    const V4<R> P = ((n.out >> (2 * a + 1)) & 1u) ? zero : v[n.cell + n.d[a][1]];
+    const V4<R> M = ((n.out >> (2 * a)) & 1u) ? zero : v[n.cell + n.d[a][0]];
+    const bool fp = P.w > R(0), fm = M.w > R(0);
+    const R up[3] = {P.x, P.y, P.z}, um[3] = {M.x, M.y, M.z}, uc[3] = {c.x, c.y, c.z};
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (fp && fm) D[a][b] = R(0.5) * (up[b] - um[b]);
+      else if (fp) D[a][b] = up[b] - uc[b];
+      else if (fm) D[a][b] = uc[b] - um[b];
+      else D[a][b] = R(0);
+    }
+  }
+  S[0] = D[0][0];
+  S[1] = D[1][1];
+  S[2] = D[2][2];
+  S[3] = R(0.5) * (D[0][1] + D[1][0]);
+  S[4] = R(0.5) * (D[0][2] + D[2][0]);
+  S[5] = R(0.5) * (D[1][2] + D[2][1]);
+}
+
 }  // namespace lbmk

@@ -156,13 +156,3 @@ def test_hybrid_porous_cavity_fp64(gpu):
     for case in (hyb(I.porous_channel(shape=(40, 24, 12)), 0.4), hyb(I.cavity((140, 20, 18), q=19), 0.6)):
         _, _, rho, u, orho, ou = _run_both(gpu, case, 30, "f64")
         _check(f"hybrid {case.name} f64", moment_errors(rho, u, orho, ou), 1e-12)
-
-
-def test_hybrid_adjoint_refused(gpu):
-    case = hyb(I.porous_channel(shape=(16, 12, 8)), 0.5)
-    lat = gpu.Lattice(case, storage="f64")
-    lam, grad = lat.new_adjoint(), lat.new_gradient()
-    gpu.lbm_adjoint_seed(lat.ctx, case.extra["planes"], lam)
-    with pytest.raises(gpu.LbmError) as e:
-        gpu.lbm_adjoint_step(lat.ctx, lam, grad)
-    assert e.value.code == gpu.EINVAL and "finite-difference" in str(e.value)
