@@ -1181,14 +1181,16 @@ __global__ __launch_bounds__(256) void k_adjoint_ref(const uint8_t *__restrict__
   LinkMask sm = 0;
   if (ODD && (flags[r] & FL_NEAR)) sm = solid_mask<Q, SLIP>(n, flags);
   const size_t N = (size_t)k.N;
+  R cur[Q];  // all loads before any store (see k_adjoint_fd)
+#pragma unroll
+  for (int i = 0; i < Q; ++i) cur[i] = dev[read_slot<Q, ODD, SLIP>(n, sm, i, N)];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     double v = a;
     acc(v, Lat<Q>::c(i, 0), ax);
     acc(v, Lat<Q>::c(i, 1), ay);
     acc(v, Lat<Q>::c(i, 2), az);
-    R *p = dev + read_slot<Q, ODD, SLIP>(n, sm, i, N);
-    *p = (R)((double)*p + v);
+    dev[read_slot<Q, ODD, SLIP>(n, sm, i, N)] = (R)((double)cur[i] + v);
   }
 }
 
@@ -1264,14 +1266,18 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint_fd(const uint8_t *__restrict
   const R base = -(ub[0] * v.x + ub[1] * v.y + ub[2] * v.z) * ir;
   LinkMask sm = 0;
   if (SOLID && ODD && (fl & FL_NEAR)) sm = solid_mask<Q, SOLID == 2>(n, flags);
+  // all loads before any store: the slots are distinct, but the compiler
+  // cannot know it and would otherwise wait for each load in turn
+  R cur[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) cur[i] = dev[read_slot<Q, ODD, SOLID == 2>(n, sm, i, N)];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     R d = base;
     acc(d, Lat<Q>::c(i, 0), ub[0] * ir);
     acc(d, Lat<Q>::c(i, 1), ub[1] * ir);
     acc(d, Lat<Q>::c(i, 2), ub[2] * ir);
-    R *p = dev + read_slot<Q, ODD, SOLID == 2>(n, sm, i, N);
-    *p += d;
+    dev[read_slot<Q, ODD, SOLID == 2>(n, sm, i, N)] = cur[i] + d;
   }
 }
 
