@@ -577,6 +577,8 @@ def bench_adjoint(args, torch, lbm, case, storage, wname):
     """Forward step vs hand-written reverse step on the porosity workload,
     and one full checkpointed gradient."""
     r = adjoint_ratio(torch, lbm, case, storage, args.steps, args.warmup, spread=not args.no_spread)
+    if args.calibrate:
+        calibration_copy(torch)
     out = {
         "metric": "adjoint/forward step time ratio",
         "value": r["ratio"],
