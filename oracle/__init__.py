@@ -161,11 +161,13 @@ class Oracle:
                               1 if tangent else 0)
         if not self.h:
             raise OracleError(EINVAL, L.orc_create_error().decode())
+        # held here: at interpreter exit the module's globals may already be gone
+        self._free = L.orc_free
 
     def __del__(self):
         h = getattr(self, "h", None)
         if h:
-            lib().orc_free(h)
+            self._free(h)
             self.h = None
 
     def _check(self, rc):

@@ -10,7 +10,8 @@ which differentiate the same hybrid:
    (1e-12): a periodic porous box (central differences only), a porous
    channel with walls (one-sided differences at the walls, half-way
    bounce-back, D3Q19 and D3Q27), the same channel wall-modeled (full strain
-   in the wall cells) and an urban crop (buildings, fringe, lid);
+   in the wall cells), an urban crop (buildings, fringe, lid), the crop with
+   full-slip sides and top, and a box with full-slip y and z faces;
  - the checkpointed gradient (terminal and time-averaged objective, and the
    per-cell C_S gradient) against the oracle's tangent, FP64 (1e-10), and
    FP32 and FP16 storage against the FP64 gradient.
@@ -49,10 +50,17 @@ def _porous_channel(q=19, wall=False):
     return _hyb(c)
 
 
-def _urban_crop():
+def _urban_crop(slip=False):
     c = I.urban(nx=40, ny=24, nz=16, q=19, tau0=0.52, fringe_len=6, x_lo=6, x_hi=30, h_mean=6.0, h_max=10,
-                fp_lo=3, fp_hi=7)
+                fp_lo=3, fp_hi=7, slip_walls=slip)
     return _hyb(c, 0.5)
+
+
+def _slip_box():
+    # full-slip y and z faces: the strain is one-sided at them
+    case = I.Case(name="slipbox", q=27, shape=(37, 9, 7), periodic=(1, 0, 0), tau0=0.57, cs_smag=0.12,
+                  force=(2e-5, 0.0, 0.0), collision=1, slip=0b111100)
+    return _hyb(case, 0.4)
 
 
 def _transpose(gpu, case, parity, seed):
@@ -98,6 +106,8 @@ CASES = {
     "porous channel q27": lambda: _porous_channel(27),
     "wall-modeled channel": lambda: _porous_channel(19, wall=True),
     "urban crop": lambda: _urban_crop(),
+    "urban crop, full-slip sides and top": lambda: _urban_crop(slip=True),
+    "full-slip box": lambda: _slip_box(),
 }
 
 
