@@ -152,6 +152,22 @@ def test_hybrid_urban_crop(gpu, storage, tol, steps):
     _check(f"hybrid urban {storage}", moment_errors(rho, u, orho, ou), tol)
 
 
+@pytest.mark.parametrize("q", [19, 27])
+def test_hybrid_tgv_fp32_fp16(gpu, q):
+    """The hybrid in FP32 and FP16 deviation storage (the velocity field and
+    the strain in FP32), 100 steps.  FP32 within 1e-5 as everywhere; FP16
+    measured rho 1.0e-5 and u 2.8e-4 (q = 19), held to 5e-5 and 1.5e-3."""
+    case = hyb(I.taylor_green(32, u0=0.05, q=q, tau0=0.6, cs_smag=0.1), 0.3)
+    _, _, rho, u, orho, ou = _run_both(gpu, case, 100, "f32")
+    e_rho, e_u = rel_maxnorm(rho, orho), rel_maxnorm(u, ou)
+    announce(f"hybrid tgv q={q} f32: rho {e_rho:.3e} u {e_u:.3e}")
+    assert e_rho <= 1e-5 and e_u <= 1e-5
+    _, _, rho, u, _, _ = _run_both(gpu, case, 100, "f16")
+    e_rho, e_u = rel_maxnorm(rho, orho), rel_maxnorm(u, ou)
+    announce(f"hybrid tgv q={q} f16: rho {e_rho:.3e} u {e_u:.3e}")
+    assert e_rho <= 5e-5 and e_u <= 1.5e-3
+
+
 def test_hybrid_porous_cavity_fp64(gpu):
     for case in (hyb(I.porous_channel(shape=(40, 24, 12)), 0.4), hyb(I.cavity((140, 20, 18), q=19), 0.6)):
         _, _, rho, u, orho, ou = _run_both(gpu, case, 30, "f64")
