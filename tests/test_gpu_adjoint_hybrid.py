@@ -211,3 +211,16 @@ def test_hybrid_gradient_fp32_fp16(gpu):
     announce(f"hybrid gradient max-norm error: FP32 {e32:.3e}, FP16 {e16:.3e}")
     assert e32 <= 1e-5
     assert e16 <= 1e-3
+
+
+@pytest.mark.parametrize("storage,db", [("f64", 8), ("f32", 4), ("f16", 4)])
+def test_hybrid_adjoint_buffer_holds_strain_adjoints(gpu, storage, db):
+    """With the hybrid the adjoint buffer grows by six compute-type values per
+    cell (the strain adjoints, from a 256-byte boundary)."""
+    case = _porous_channel(19, wall=True)
+    plain = dataclasses.replace(case, fd_weight=0.0)
+    b_hyb = gpu.lbm_adjoint_bytes(gpu.Lattice(case, storage=storage).ctx)
+    b_plain = gpu.lbm_adjoint_bytes(gpu.Lattice(plain, storage=storage).ctx)
+    extra = 6 * case.ncells * db
+    assert extra <= b_hyb - b_plain <= extra + 255, (b_hyb, b_plain, extra)
+
