@@ -216,7 +216,9 @@ int lbm_objective(lbm_ctx *ctx, const int planes[2], double *J);
  *  lbm_adjoint_step: given lambda = dJ/df^{n+1} and the state f^n currently
  *    held by the context (step counter n), overwrites lambda with dJ/df^n
  *    and adds dJ/dphi contributions of step n to grad_phi [N] (double);
- *    decrements nothing (the caller restores f^{n-1} itself). Async.
+ *    decrements nothing (the caller restores f^{n-1} itself).  With the
+ *    hybrid collision it first rebuilds the workspace's velocity field from
+ *    f^n (the next forward step rebuilds it again).  Async.
  *  lbm_adjoint_to_natural / _from_natural: convert lambda between its
  *    in-memory form at the current parity and natural [q][N] order (FP64
  *    values; solid cells read as 0). */
