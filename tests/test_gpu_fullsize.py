@@ -61,7 +61,8 @@ def _check_samples(lat, case, cells, f_now, f_next, tol_rel, label):
                 z = flat // (case.shape[0] * case.shape[1])
                 wd = np.minimum(z + 0.5, nz - 0.5 - z).astype(np.float64)
         p = O.make_params(q, cshape, periodic=(0, 0, 0), tau0=case.tau0, cs_smag=case.cs_smag, force=case.force,
-                          wall_model=case.wall_model, kappa=case.kappa, E=case.E)
+                          wall_model=case.wall_model, kappa=case.kappa, E=case.E, collision=case.collision,
+                          fd_weight=case.fd_weight)
         orc = O.Oracle(p, mask=mask, wall_dist=wd)
         orc.set_populations(f0)
         orc.step(1)
@@ -99,6 +100,22 @@ def test_channel_fullsize_sampled(gpu, storage, tol):
     drift = abs(d1[0] - d0[0]) / d0[0]
     announce(f"channel {storage}: mass drift over 41 steps {drift:.3e}")
     assert drift <= (1e-6 if storage == "f32" else 1e-4)
+
+
+def test_channel_hybrid_fullsize_sampled(gpu):
+    """The same channel with RR3 and the hybrid at weight 0.3 (the benchmark's
+    hybrid configuration), FP32: a cell's next state also depends on its
+    neighbours' velocities, within the crop."""
+    case = I.channel(384, 192, 192, q=27)
+    case.collision = 1
+    case.fd_weight = 0.3
+    announce("channel full size, hybrid, f32")
+    lat = gpu.Lattice(case, storage="f32")
+    rng = np.random.default_rng(9)
+    nx, ny, nz = case.shape
+    cells = [int(rng.integers(nx)) + nx * (int(rng.integers(ny)) + ny * zz) for zz in (0, nz - 1, 1, nz - 2, 60, 130)
+             for _ in range(3)]
+    _run_sampled(lat, case, 40, cells, 2e-5, "channel hybrid f32")
 
 
 def test_urban_fullsize_sampled(gpu):
